@@ -1,0 +1,515 @@
+/*
+ * oracle.c -- plain, slow, high-precision CPU oracle for the real symmetric
+ * arrowhead eigenproblem and its two reductions (diagonal-plus-rank-one
+ * eigenproblem, SVD of a real upper-triangular arrowhead matrix).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library under
+ * paper_1302_7203_amd/ may include, link or call this file; only the tests,
+ * the smoke check and the benchmark's CPU-baseline leg use it.  It shares no
+ * code, header, table or helper with the GPU path.
+ *
+ * What it computes is the plain mathematical definition, not the paper's
+ * algorithm:
+ *
+ *   A = [D z; z^T alpha], D = diag(d_1..d_{n-1})            (Sec. 1, eq. (A),(z))
+ *   eigenvalues  = the n zeros of the Pick function
+ *       f(l) = alpha - l - sum_j zeta_j^2 / (d_j - l)          (Sec. 1, eq. (Pick))
+ *     one in each interval of the interlacing property         (Sec. 1, eq. (interlace))
+ *   eigenvector  = x / ||x||,  x = [ (D - l I)^{-1} z ; -1 ]     (Sec. 1, eq. (Aeigenvec))
+ *
+ *   DPR1 M = D + rho u u^T (rho > 0): eigenvalues are the n zeros of
+ *       phi(l) = 1 + rho sum_j u_j^2 / (d_j - l)               (Remark 1, secular equation)
+ *     one in each interval of eq. (lld) in Sec. 6.3; eigenvector q ~ (D - l I)^{-1} u.
+ *
+ *   SVD of B = [D z; 0 alpha]: sigma_k = sqrt(lambda_k(B^T B)), where
+ *     B^T B is the arrowhead with poles d_j^2, shaft d_j zeta_j and corner
+ *     alpha^2 + z^T z (Sec. 6.2); v_k its eigenvector, u_k = B v_k / sigma_k.
+ *
+ * Arithmetic: IEEE binary128 (__float128, unit roundoff 2^-113), the
+ * compiler's own type.  Each zero is located by bisection on the sign of the
+ * secular function, evaluated in the variable tau = l - d_p shifted to the
+ * nearer end-pole d_p of its interval (so that l - d_j = (d_j - d_p) - tau is
+ * formed from exact pole differences), together with a running error bound.
+ * A sign is used only when |value| exceeds that bound; otherwise bisection
+ * stops and the remaining width is reported in relerr[].  Bisection halves
+ * the set of binary128 numbers between the bracket ends (for brackets of one
+ * sign this is the midpoint of their bit patterns), so it needs at most ~130
+ * steps whatever the dynamic range.  A zero that lies much closer to 0 than
+ * to its pole is refined once more in the unshifted variable.  Results are
+ * rounded to FP64 once, at the end; lam/lam_lo etc. return the binary128
+ * value as an unevaluated hi+lo pair of doubles.
+ *
+ * No code here follows the printed listings of the paper.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <quadmath.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef __float128 R;
+
+enum { KIND_ARROW = 0, KIND_DPR1 = 1 };
+
+typedef struct {
+  int kind;
+  int64_t m;      /* number of poles */
+  const R *d;     /* poles, strictly decreasing */
+  const R *c;     /* weights > 0: zeta_j^2 (arrowhead) or rho*u_j^2 (DPR1) */
+  R alpha;        /* arrowhead corner; unused for DPR1 */
+} secular_t;
+
+typedef struct {
+  int64_t p;      /* index (sorted order) of the pole the zero is measured from */
+  R tau;          /* zero = d_p + tau */
+  R lam;          /* zero itself */
+  double relerr;  /* bound on the relative uncertainty of tau and of lam */
+} root_t;
+
+static const R U113 = 9.62964972193617926527988971292463659e-35Q; /* 2^-113 */
+
+/* g(l) is strictly decreasing on every interval between consecutive poles:
+ *   arrowhead: g = f (eq. Pick);   DPR1: g = -phi.
+ * Evaluated at l = d_p + tau with the pole differences formed first.
+ * *err receives a bound on |computed - exact|. */
+static R g_shifted(const secular_t *s, int64_t p, R tau, R *err) {
+  R sum = 0, mag = 0;
+  const R dp = s->d[p];
+  for (int64_t j = 0; j < s->m; ++j) {
+    R t = s->c[j] / ((s->d[j] - dp) - tau);
+    sum += t;
+    mag += fabsq(t);
+  }
+  R base, bmag;
+  if (s->kind == KIND_ARROW) {
+    R a = s->alpha - dp;
+    base = a - tau;
+    bmag = fabsq(a) + fabsq(tau);
+  } else {
+    base = -1;
+    bmag = 1;
+  }
+  *err = (R)(s->m + 16) * 2 * U113 * (bmag + mag);
+  return base - sum;
+}
+
+/* Same function evaluated directly at l (used only when l is far from every
+ * pole compared with |l|, i.e. for a zero close to the origin). */
+static R g_plain(const secular_t *s, R l, R *err) {
+  R sum = 0, mag = 0;
+  for (int64_t j = 0; j < s->m; ++j) {
+    R t = s->c[j] / (s->d[j] - l);
+    sum += t;
+    mag += fabsq(t);
+  }
+  R base, bmag;
+  if (s->kind == KIND_ARROW) {
+    base = s->alpha - l;
+    bmag = fabsq(s->alpha) + fabsq(l);
+  } else {
+    base = -1;
+    bmag = 1;
+  }
+  *err = (R)(s->m + 16) * 2 * U113 * (bmag + mag);
+  return base - sum;
+}
+
+/* |g'(l)| at l = d_p + tau, used only to turn an undecidable sign into an
+ * error estimate. */
+static R gprime_abs(const secular_t *s, int64_t p, R tau) {
+  R sum = (s->kind == KIND_ARROW) ? 1 : 0;
+  for (int64_t j = 0; j < s->m; ++j) {
+    R den = (s->d[j] - s->d[p]) - tau;
+    sum += s->c[j] / (den * den);
+  }
+  return sum;
+}
+
+/* Midpoint of two non-negative binary128 numbers in the ordering of their
+ * representations (monotone for non-negative values). */
+static R bits_mid(R lo, R hi) {
+  unsigned __int128 a, b, c;
+  memcpy(&a, &lo, sizeof a);
+  memcpy(&b, &hi, sizeof b);
+  c = a + (b - a) / 2;
+  R r;
+  memcpy(&r, &c, sizeof r);
+  return r;
+}
+
+/* Zero number k (0-based, descending order) of the secular function.
+ *   arrowhead: n = m + 1 zeros, l_0 in (d_0, upper], l_k in (d_k, d_{k-1}),
+ *              l_m in [lower, d_{m-1})           (eq. interlace)
+ *   DPR1:      n = m zeros, l_0 in (d_0, upper], l_k in (d_k, d_{k-1})  (eq. lld) */
+static void solve_root(const secular_t *s, int64_t k, R upper, R lower, root_t *out) {
+  const int64_t m = s->m;
+  int64_t p;
+  int sgn;
+  R h;
+  if (k == 0) {
+    p = 0; sgn = +1; h = (upper - s->d[0]) * (1 + 1e-20Q);
+  } else if (s->kind == KIND_ARROW && k == m) {
+    p = m - 1; sgn = -1; h = (s->d[m - 1] - lower) * (1 + 1e-20Q);
+  } else {
+    /* interior interval (d_k, d_{k-1}): the sign of g at its midpoint tells
+     * which end-pole is nearer to the zero (g decreasing). */
+    R gap = s->d[k - 1] - s->d[k];
+    R half = gap / 2, err;
+    R gm = g_shifted(s, k, half, &err);
+    R ext = gap * 1e-9Q;             /* reach a little past the midpoint */
+    if (gm < 0 && -gm > err) { p = k; sgn = +1; h = half + ext; }
+    else { p = k - 1; sgn = -1; h = (gap - half) + ext; }
+  }
+
+  /* Bisection on the magnitude t of tau = sgn*t, t in (lo, hi). */
+  R lo = 0, hi = h;
+  int undecided = 0;
+  for (int it = 0; it < 600; ++it) {
+    if (hi - lo <= hi * 1e-28Q) break;
+    R t = bits_mid(lo, hi);
+    if (!(t > lo && t < hi)) break;
+    R err, g = g_shifted(s, p, sgn * t, &err);
+    if (fabsq(g) <= err) { lo = hi = t; undecided = 1; break; }
+    int zero_above = g > 0;                 /* zero lies at larger l */
+    int farther = (sgn > 0) ? zero_above : !zero_above;
+    if (farther) lo = t; else hi = t;
+  }
+  R t = (lo == hi) ? hi : lo + (hi - lo) / 2;
+  R tau = sgn * t;
+  R rel = (t > 0) ? (hi - lo) / t : 1;
+  if (undecided) {
+    R err;
+    (void)g_shifted(s, p, tau, &err);
+    R gp = gprime_abs(s, p, tau);
+    rel = (gp > 0 && t > 0) ? err / gp / t : 1;
+  }
+  R lam = s->d[p] + tau;
+
+  /* A zero much closer to the origin than to its pole: refine it in the
+   * unshifted variable so that it is also accurate relative to itself. */
+  if (fabsq(lam) < fabsq(tau) * 1e-6Q) {
+    R a = s->d[p] + sgn * lo, b = s->d[p] + sgn * hi;
+    R llo = a < b ? a : b, lhi = a < b ? b : a;
+    /* widen by the rounding of d_p + tau */
+    R pad = fabsq(s->d[p]) * 4 * U113 + fabsq(tau) * 4 * U113;
+    llo -= pad; lhi += pad;
+    int und2 = 0;
+    R l = llo + (lhi - llo) / 2;
+    for (int it = 0; it < 800; ++it) {
+      l = llo + (lhi - llo) / 2;
+      R w = lhi - llo;
+      if (w <= fabsq(l) * 1e-28Q || !(l > llo && l < lhi)) break;
+      R err, g = g_plain(s, l, &err);
+      if (fabsq(g) <= err) { und2 = 1; break; }
+      if (g > 0) llo = l; else lhi = l;
+    }
+    l = und2 ? l : llo + (lhi - llo) / 2;
+    R rel2;
+    if (und2) {
+      R err;
+      (void)g_plain(s, l, &err);
+      R gp = gprime_abs(s, p, l - s->d[p]);
+      rel2 = (l != 0) ? err / gp / fabsq(l) : 1;
+    } else {
+      rel2 = (l != 0) ? (lhi - llo) / fabsq(l) : 1;
+    }
+    lam = l;
+    tau = l - s->d[p];
+    if (rel2 > rel) rel = rel2;
+  } else if (fabsq(lam) < fabsq(tau) && lam != 0) {
+    rel = rel * fabsq(tau) / fabsq(lam);   /* width seen relative to lam */
+  }
+  out->p = p;
+  out->tau = tau;
+  out->lam = lam;
+  out->relerr = (double)rel;
+}
+
+/* ---------------------------------------------------------------------- */
+
+static void split(R x, double *hi, double *lo) {
+  double h = (double)x;
+  if (hi) *hi = h;
+  if (lo) *lo = (double)(x - (R)h);
+}
+
+typedef struct { double key; int64_t idx; } keyed_t;
+
+static int cmp_desc(const void *a, const void *b) {
+  double x = ((const keyed_t *)a)->key, y = ((const keyed_t *)b)->key;
+  return (x > y) ? -1 : (x < y) ? 1 : 0;
+}
+
+/* order[i] = caller index of the i-th largest key; 1 if two keys are equal. */
+static int sort_desc(int64_t m, const double *key, int64_t *order) {
+  keyed_t *t = (keyed_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof *t);
+  if (!t) return -100;
+  for (int64_t i = 0; i < m; ++i) { t[i].key = key[i]; t[i].idx = i; }
+  qsort(t, (size_t)m, sizeof *t, cmp_desc);
+  int dup = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    order[i] = t[i].idx;
+    if (i > 0 && !(t[i - 1].key > t[i].key)) dup = 1;
+  }
+  free(t);
+  return dup;
+}
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+static int finite(double x) { return x == x && x - x == 0; }
+
+/*
+ * Arrowhead eigenpairs.  d, z: n-1 entries in any order; alpha: corner.
+ * ks[0..nk-1]: which eigenpairs (0 = largest); NULL means all (nk == n).
+ * Outputs (each may be NULL):
+ *   lam, lam_lo   eigenvalue as a hi+lo pair
+ *   tau, tau_lo   eigenvalue minus its reference pole, hi+lo
+ *   pole          caller index of that pole (-1 when n == 1)
+ *   V             n x nk, column-major, column i = eigenvector of ks[i],
+ *                 rows in caller order, last row = the corner coordinate,
+ *                 sign fixed by x_n = -1 (eq. Aeigenvec)
+ *   relerr        relative uncertainty of the located zero
+ * Returns 0, -1 bad argument, 1 reducible (zero z_j or repeated d_j).
+ */
+int oracle_arrow_eig(int64_t n, const double *d, const double *z, double alpha,
+                     int64_t nk, const int64_t *ks,
+                     double *lam, double *lam_lo, double *tau, double *tau_lo,
+                     int64_t *pole, double *V, double *relerr, int nthreads) {
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(alpha)) return -1;
+  const int64_t m = n - 1;
+  for (int64_t j = 0; j < m; ++j) {
+    if (!finite(d[j]) || !finite(z[j])) return -1;
+    if (z[j] == 0) return 1;
+  }
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) return -1;
+  }
+  if (n == 1) {
+    for (int64_t i = 0; i < nk; ++i) {
+      if (lam) lam[i] = alpha;
+      if (lam_lo) lam_lo[i] = 0;
+      if (tau) tau[i] = alpha;
+      if (tau_lo) tau_lo[i] = 0;
+      if (pole) pole[i] = -1;
+      if (V) V[i] = -1.0;
+      if (relerr) relerr[i] = 0;
+    }
+    return 0;
+  }
+  int64_t *order = (int64_t *)malloc((size_t)m * sizeof *order);
+  R *dq = (R *)malloc((size_t)m * sizeof *dq);
+  R *cq = (R *)malloc((size_t)m * sizeof *cq);
+  if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
+  int dup = sort_desc(m, d, order);
+  if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R zsum = 0, up = -1e4000Q, lowb = 1e4000Q;
+  for (int64_t j = 0; j < m; ++j) {
+    dq[j] = (R)d[order[j]];
+    R zz = (R)z[order[j]];
+    cq[j] = zz * zz;                          /* exact in binary128 */
+    zsum += fabsq(zz);
+    if (dq[j] + fabsq(zz) > up) up = dq[j] + fabsq(zz);
+    if (dq[j] - fabsq(zz) < lowb) lowb = dq[j] - fabsq(zz);
+  }
+  /* Gershgorin discs bound the spectrum. */
+  if ((R)alpha + zsum > up) up = (R)alpha + zsum;
+  if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
+  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha };
+
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    root_t r;
+    solve_root(&s, k, up, lowb, &r);
+    if (lam || lam_lo) split(r.lam, lam ? &lam[i] : NULL, lam_lo ? &lam_lo[i] : NULL);
+    if (tau || tau_lo) split(r.tau, tau ? &tau[i] : NULL, tau_lo ? &tau_lo[i] : NULL);
+    if (pole) pole[i] = order[r.p];
+    if (relerr) relerr[i] = r.relerr;
+    if (V) {
+      /* x_j = zeta_j / (d_j - l), x_n = -1, in caller order */
+      R nrm2 = 1;
+      R dp = dq[r.p];
+      for (int64_t j = 0; j < m; ++j) {
+        R x = (R)z[j] / (((R)d[j] - dp) - r.tau);
+        nrm2 += x * x;
+      }
+      R nrm = sqrtq(nrm2);
+      double *col = V + i * n;
+      for (int64_t j = 0; j < m; ++j) {
+        R x = (R)z[j] / (((R)d[j] - dp) - r.tau);
+        col[j] = (double)(x / nrm);
+      }
+      col[m] = (double)(-1 / nrm);
+    }
+  }
+  free(order); free(dq); free(cq);
+  return 0;
+}
+
+/*
+ * DPR1 eigenpairs of M = diag(d) + rho u u^T, rho > 0, d distinct (any order),
+ * u_j != 0.  Same conventions as above; Q is n x nk with q = x/||x||,
+ * x = (D - l I)^{-1} u (rows in caller order).
+ */
+int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
+                    int64_t nk, const int64_t *ks,
+                    double *lam, double *lam_lo, double *tau, double *tau_lo,
+                    int64_t *pole, double *Q, double *relerr, int nthreads) {
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(rho) || !(rho > 0)) return -1;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!finite(d[j]) || !finite(u[j])) return -1;
+    if (u[j] == 0) return 1;
+  }
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) return -1;
+  }
+  const int64_t m = n;
+  int64_t *order = (int64_t *)malloc((size_t)m * sizeof *order);
+  R *dq = (R *)malloc((size_t)m * sizeof *dq);
+  R *cq = (R *)malloc((size_t)m * sizeof *cq);
+  if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
+  int dup = sort_desc(m, d, order);
+  if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R csum = 0;
+  for (int64_t j = 0; j < m; ++j) {
+    dq[j] = (R)d[order[j]];
+    R uu = (R)u[order[j]];
+    cq[j] = (R)rho * (uu * uu);
+    csum += cq[j];
+  }
+  R up = dq[0] + csum;      /* l_1 <= d_1 + rho ||u||^2 */
+  secular_t s = { KIND_DPR1, m, dq, cq, 0 };
+
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    root_t r;
+    solve_root(&s, k, up, 0, &r);
+    if (lam || lam_lo) split(r.lam, lam ? &lam[i] : NULL, lam_lo ? &lam_lo[i] : NULL);
+    if (tau || tau_lo) split(r.tau, tau ? &tau[i] : NULL, tau_lo ? &tau_lo[i] : NULL);
+    if (pole) pole[i] = order[r.p];
+    if (relerr) relerr[i] = r.relerr;
+    if (Q) {
+      R nrm2 = 0, dp = dq[r.p];
+      for (int64_t j = 0; j < n; ++j) {
+        R x = (R)u[j] / (((R)d[j] - dp) - r.tau);
+        nrm2 += x * x;
+      }
+      R nrm = sqrtq(nrm2);
+      double *col = Q + i * n;
+      for (int64_t j = 0; j < n; ++j) {
+        R x = (R)u[j] / (((R)d[j] - dp) - r.tau);
+        col[j] = (double)(x / nrm);
+      }
+    }
+  }
+  free(order); free(dq); free(cq);
+  return 0;
+}
+
+/*
+ * SVD of the upper-triangular arrowhead B = [diag(d) z; 0 alpha] (order n):
+ * d: n-1 nonzero entries with distinct |d_j| (any order), z_j != 0.
+ * sigma (hi, lo): singular values, descending.  V: right singular vectors
+ * (eigenvectors of B^T B with the arrowhead sign convention x_n = -1).
+ * U: left singular vectors u = B v / sigma.  Both n x nk column-major.
+ */
+int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
+                     int64_t nk, const int64_t *ks,
+                     double *sigma, double *sigma_lo, double *U, double *V,
+                     double *relerr, int nthreads) {
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(alpha)) return -1;
+  const int64_t m = n - 1;
+  for (int64_t j = 0; j < m; ++j) {
+    if (!finite(d[j]) || !finite(z[j])) return -1;
+    if (z[j] == 0 || d[j] == 0) return 1;
+  }
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) return -1;
+  }
+  if (n == 1) {
+    for (int64_t i = 0; i < nk; ++i) {
+      double a = alpha < 0 ? -alpha : alpha;
+      if (sigma) sigma[i] = a;
+      if (sigma_lo) sigma_lo[i] = 0;
+      if (V) V[i] = -1.0;
+      if (U) U[i] = (alpha == 0) ? 0.0 : (alpha > 0 ? -1.0 : 1.0);
+      if (relerr) relerr[i] = 0;
+    }
+    return 0;
+  }
+  double *key = (double *)malloc((size_t)m * sizeof *key);
+  int64_t *order = (int64_t *)malloc((size_t)m * sizeof *order);
+  R *dq = (R *)malloc((size_t)m * sizeof *dq);
+  R *cq = (R *)malloc((size_t)m * sizeof *cq);
+  if (!key || !order || !dq || !cq) { free(key); free(order); free(dq); free(cq); return -100; }
+  for (int64_t j = 0; j < m; ++j) key[j] = d[j] < 0 ? -d[j] : d[j];
+  int dup = sort_desc(m, key, order);
+  if (dup) { free(key); free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  /* B^T B = [D^2, D z; z^T D, alpha^2 + z^T z] */
+  R corner = (R)alpha * (R)alpha, zsum = 0, up = -1e4000Q, lowb = 1e4000Q;
+  for (int64_t j = 0; j < m; ++j) corner += (R)z[j] * (R)z[j];
+  for (int64_t j = 0; j < m; ++j) {
+    R dj = (R)d[order[j]], zj = (R)z[order[j]];
+    dq[j] = dj * dj;
+    R sh = dj * zj;
+    cq[j] = sh * sh;
+    zsum += fabsq(sh);
+  }
+  for (int64_t j = 0; j < m; ++j) {
+    R r = sqrtq(cq[j]);
+    if (dq[j] + r > up) up = dq[j] + r;
+    if (dq[j] - r < lowb) lowb = dq[j] - r;
+  }
+  if (corner + zsum > up) up = corner + zsum;
+  if (corner - zsum < lowb) lowb = corner - zsum;
+  secular_t s = { KIND_ARROW, m, dq, cq, corner };
+
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    root_t r;
+    solve_root(&s, k, up, lowb, &r);
+    R lamq = r.lam < 0 ? 0 : r.lam;
+    R sg = sqrtq(lamq);
+    if (sigma || sigma_lo) split(sg, sigma ? &sigma[i] : NULL, sigma_lo ? &sigma_lo[i] : NULL);
+    if (relerr) relerr[i] = r.relerr;
+    if (U || V) {
+      R dp = dq[r.p], nrm2 = 1;
+      for (int64_t j = 0; j < m; ++j) {
+        R dj = (R)d[j];
+        R x = dj * (R)z[j] / ((dj * dj - dp) - r.tau);
+        nrm2 += x * x;
+      }
+      R nrm = sqrtq(nrm2);
+      double *vc = V ? V + i * n : NULL;
+      double *uc = U ? U + i * n : NULL;
+      for (int64_t j = 0; j < m; ++j) {
+        R dj = (R)d[j];
+        R v = dj * (R)z[j] / ((dj * dj - dp) - r.tau) / nrm;
+        if (vc) vc[j] = (double)v;
+        if (uc) uc[j] = (double)(sg * v / dj);        /* u_j = sigma v_j / d_j */
+      }
+      R vn = -1 / nrm;
+      if (vc) vc[m] = (double)vn;
+      if (uc) uc[m] = (double)((R)alpha * vn / sg);   /* u_n = alpha v_n / sigma */
+    }
+  }
+  free(key); free(order); free(dq); free(cq);
+  return 0;
+}
