@@ -1,0 +1,145 @@
+/*
+ * arrow.h -- C ABI of libarrow, an MI355X (gfx950) FP64 eigensolver for real
+ * symmetric arrowhead matrices and the two problems the method extends to.
+ *
+ * Method: Jakovcevic Stor, Slapnicar, Barlow, "Accurate eigenvalue
+ * decomposition of arrowhead matrices and applications".  Each eigenpair is
+ * computed independently by shifting to the nearest pole, inverting the
+ * shifted matrix, evaluating its one sensitive element b in double-double and
+ * bisecting for the extreme eigenvalue of the inverse (Algorithms 1-5).
+ *
+ * Conventions shared by every call:
+ *   - All array arguments are DEVICE pointers (HIP device memory of the
+ *     handle's device), owned by the caller.  The library never frees them.
+ *   - Calls are asynchronous on the handle's stream (arrow_set_stream; the
+ *     default is the null stream).  Outputs are valid once that stream has
+ *     completed the call.  One handle must not be used by two threads at once;
+ *     calls on one handle reuse its workspace and are ordered by its stream.
+ *   - Eigenvalues (singular values) are returned in descending order.
+ *   - Matrices are column-major with leading dimension ld >= n; column k is
+ *     the vector of the k-th largest eigenvalue; rows follow the caller's
+ *     original (unsorted) order of d.
+ *   - Return value: ARROW_OK (0), a negative value -i when argument i
+ *     (1-based, counting the handle as argument 1) is invalid, or a positive
+ *     ARROW_ERR_* for a host-side failure.  Conditions that depend on the
+ *     data (reducible input, remedies used) never fail the call; they are
+ *     reported per eigenvalue in info[] (ARROW_INFO_* bits) on the device.
+ */
+#ifndef ARROW_H
+#define ARROW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arrow_handle_s* arrow_handle_t;
+
+/* status codes */
+#define ARROW_OK 0
+#define ARROW_ERR_HIP 1      /* a HIP runtime call failed (launch, allocation) */
+#define ARROW_ERR_NOMEM 2    /* device workspace could not be allocated */
+#define ARROW_ERR_STATE 3    /* null or destroyed handle */
+
+/* info bits, one uint32 per eigenvalue */
+#define ARROW_INFO_DD_B 1u        /* b evaluated in double-double (Sec. 4, Theorem 6) */
+#define ARROW_INFO_REMEDY_A 2u    /* shifted to the other neighbouring pole (Remark 2(a)) */
+#define ARROW_INFO_REMEDY_B 4u    /* DPR1 inverse at a shift near lambda (Remark 2(b)) */
+#define ARROW_INFO_NEAR_ZERO 8u   /* eigenvalue closest to 0 taken from A^{-1} (Remark 1) */
+#define ARROW_INFO_REDUCIBLE 16u  /* some z_j = 0 or d_i = d_j (Sec. 1): not solved, outputs NaN */
+#define ARROW_INFO_NONFINITE 32u  /* non-finite input: not solved, outputs NaN */
+#define ARROW_INFO_KB_LARGE 64u   /* K_b (eq. K2) beyond what double-double resolves */
+#define ARROW_INFO_KNU_LARGE 128u /* reserved */
+#define ARROW_INFO_BAD_INPUT 256u /* arrow_svd: some d_j = 0: not solved, outputs NaN */
+#define ARROW_INFO_POLE_SHIFT 512u /* dpr1_eig: smallest eigenvalue measured from the pole d_n */
+
+/* options for arrow_set_option */
+#define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 10) */
+#define ARROW_OPT_TAU_ZERO 2   /* (|d_i|+|mu|)/|lambda| above which Remark 1 applies (default 10) */
+#define ARROW_OPT_FP64_B 3     /* 1: b in FP64 only (Algorithm 2), a negative control (default 0) */
+#define ARROW_OPT_REMEDIES 4   /* 0: no K_nu / near-zero remedies (default 1) */
+#define ARROW_OPT_LANES 5      /* lanes per eigenvalue: 0 = automatic, else 1,2,4,...,64 */
+#define ARROW_OPT_TIMING 6     /* 1: record HIP events around each stage of later calls */
+
+/* Create a handle on HIP device `device`.  *h receives the handle. */
+int arrow_create(arrow_handle_t* h, int device);
+
+/* Destroy a handle after synchronising its stream; frees its workspace. */
+int arrow_destroy(arrow_handle_t h);
+
+/* Set the HIP stream (a hipStream_t passed as void*) all later calls use. */
+int arrow_set_stream(arrow_handle_t h, void* hip_stream);
+
+/* Set one ARROW_OPT_* option.  Returns -2 for an unknown option, -3 for a bad value. */
+int arrow_set_option(arrow_handle_t h, int option, double value);
+
+/* Device workspace (bytes) one problem of order n needs; the handle grows
+ * its own workspace on demand (allocation synchronises its stream). */
+size_t arrow_workspace_size(int64_t n);
+
+/*
+ * Eigen-decomposition of the real symmetric arrowhead matrix
+ *     A = [ diag(d)  z ; z^T  alpha ]            (Sec. 1, eqs. (A), (z))
+ * of order n >= 1.  d, z: n-1 entries each, any order and signs (the
+ * symmetric permutation to decreasing d and the sign normalisation of Sec. 1
+ * are done inside; n == 1 allows null d, z).
+ *   lambda: n eigenvalues, descending.
+ *   V:      n x n eigenvectors (ldv >= n), or null for eigenvalues only.
+ *           v_k = x/||x||, x = [(D - lambda_k I)^{-1} z; -1] (eq. Aeigenvec),
+ *           so V[n-1, k] < 0.
+ *   shift, mu: optional (null allowed); lambda_k = shift_k + mu_k exactly in
+ *           real arithmetic, where shift_k is the pole the eigenvalue was
+ *           computed from (Remark 3); this pair carries ~32 digits.
+ *   info:   optional, n uint32 ARROW_INFO_* bits.
+ */
+int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+              double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info);
+
+/*
+ * Eigen-decomposition of the real symmetric DPR1 matrix M = diag(d) + rho u u^T
+ * (Sec. 6.3) of order n >= 1, rho > 0.  d, u: n entries, any order; d distinct,
+ * u_j != 0 (else info reports REDUCIBLE).
+ *   lambda: n eigenvalues, descending.
+ *   Q:      n x n eigenvectors (ldq >= n) or null; q_k = x/||x||,
+ *           x = (D - lambda_k I)^{-1} u.
+ *   info:   optional.
+ */
+int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, double rho,
+             double* lambda, double* Q, int64_t ldq, uint32_t* info);
+
+/*
+ * Singular value decomposition B = U Sigma V^T of the upper-triangular
+ * arrowhead B = [ diag(d)  z ; 0  alpha ] of order n >= 1 (Sec. 6.2).
+ * d: n-1 nonzero entries with distinct |d_j|; z: n-1 nonzero entries.
+ *   sigma: n singular values, descending.
+ *   U, V:  n x n (ldu, ldv >= n) or null.  v_k is the eigenvector of the
+ *          arrowhead B^T B with V[n-1, k] < 0; u_k = B v_k / sigma_k.
+ *   info:  optional.
+ */
+int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+              double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, uint32_t* info);
+
+/*
+ * Diagnostics of the most recent single-problem call on this handle.
+ *
+ * arrow_last_timing: ms[0..4] receive the elapsed times (milliseconds, from
+ *   HIP events on the handle's stream) of the stages sort, prologue, root
+ *   (shift, b, bisection), check (K_nu, remedies, norm) and vectors.  Needs
+ *   ARROW_OPT_TIMING set before that call; waits for it to finish.  Returns
+ *   ARROW_ERR_STATE when no timed call exists.
+ * arrow_last_counters: out[0..6] receive, summed over all eigenvalues, the
+ *   bisection steps, double-double O(n) passes and plain O(n) passes executed
+ *   by the root stage (out[0..2]) and by the check stage (out[3..5]), and the
+ *   matrix order n (out[6]; a pass visits the n-1 poles, n for DPR1 norms).
+ *   Synchronises the stream and copies 24 n bytes to the host.
+ */
+int arrow_last_timing(arrow_handle_t h, double* ms);
+int arrow_last_counters(arrow_handle_t h, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARROW_H */

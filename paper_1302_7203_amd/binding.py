@@ -1,0 +1,196 @@
+"""Thin ctypes binding of ``libarrow.so`` (C ABI in include/arrow.h).
+
+Only argument marshalling happens here: torch supplies device memory and the
+current HIP stream; every step of the solve runs in the library's kernels.
+There is no fallback: if the library is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libarrow.so")
+
+INFO_DD_B = 1
+INFO_REMEDY_A = 2
+INFO_REMEDY_B = 4
+INFO_NEAR_ZERO = 8
+INFO_REDUCIBLE = 16
+INFO_NONFINITE = 32
+INFO_KB_LARGE = 64
+INFO_BAD_INPUT = 256
+INFO_POLE_SHIFT = 512
+INFO_NOT_SOLVED = INFO_REDUCIBLE | INFO_NONFINITE | INFO_BAD_INPUT
+
+OPT_TAU_NU = 1
+OPT_TAU_ZERO = 2
+OPT_FP64_B = 3
+OPT_REMEDIES = 4
+OPT_LANES = 5
+OPT_TIMING = 6
+
+
+class ArrowError(RuntimeError):
+    pass
+
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise ArrowError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+                L = ctypes.CDLL(LIB_PATH)
+                P, I64, D, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+                L.arrow_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), I]
+                L.arrow_destroy.argtypes = [P]
+                L.arrow_set_stream.argtypes = [P, P]
+                L.arrow_set_option.argtypes = [P, I, D]
+                L.arrow_workspace_size.argtypes = [I64]
+                L.arrow_workspace_size.restype = ctypes.c_size_t
+                L.arrow_eig.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
+                L.dpr1_eig.argtypes = [P, I64, P, P, D, P, P, I64, P]
+                L.arrow_svd.argtypes = [P, I64, P, P, D, P, P, I64, P, I64, P]
+                L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+                L.arrow_last_counters.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+                for f in ("arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
+                          "arrow_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing", "arrow_last_counters"):
+                    getattr(L, f).restype = ctypes.c_int
+                _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ArrowError(f"{what} returned {rc}")
+
+
+def handle(device: int | torch.device | None = None) -> ctypes.c_void_p:
+    """The per-device default handle (created on first use)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _handles:
+        h = ctypes.c_void_p()
+        _check(lib().arrow_create(ctypes.byref(h), idx), "arrow_create")
+        _handles[idx] = h
+    return _handles[idx]
+
+
+def set_option(option: int, value: float, device=None):
+    _check(lib().arrow_set_option(handle(device), option, float(value)), "arrow_set_option")
+
+
+def last_timing(device=None) -> list[float]:
+    """Stage times (ms) of the last timed call: sort, prologue, root, check, vectors."""
+    ms = (ctypes.c_double * 5)()
+    _check(lib().arrow_last_timing(handle(device), ms), "arrow_last_timing")
+    return list(ms)
+
+
+def last_counters(device=None) -> dict:
+    """Pass counters of the last call (see arrow_last_counters)."""
+    out = (ctypes.c_int64 * 7)()
+    _check(lib().arrow_last_counters(handle(device), out), "arrow_last_counters")
+    keys = ("root_bisect", "root_dd", "root_plain", "check_bisect", "check_dd", "check_plain", "n")
+    return dict(zip(keys, list(out)))
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_vec(x, n, device, name):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.device.type != "cuda" or x.dtype != torch.float64 or x.dim() != 1 or x.numel() != n:
+        raise ValueError(f"{name} must be a 1-D float64 CUDA tensor of length {n}")
+    return x.contiguous()
+
+
+def _bind_stream(h, device):
+    s = torch.cuda.current_stream(device)
+    _check(lib().arrow_set_stream(h, ctypes.c_void_p(s.cuda_stream)), "arrow_set_stream")
+
+
+@dataclass
+class EigOut:
+    lam: torch.Tensor             # eigenvalues (singular values), descending
+    V: torch.Tensor | None        # n x n, column k = k-th vector (a transposed view of col-major storage)
+    U: torch.Tensor | None = None
+    shift: torch.Tensor | None = None
+    mu: torch.Tensor | None = None
+    info: torch.Tensor | None = None
+
+
+def _colmajor(n, device):
+    buf = torch.empty((n, n), dtype=torch.float64, device=device)   # buf[k, r] = V[r, k]
+    return buf
+
+
+def arrow_eig(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool = True,
+              pairs: bool = False) -> EigOut:
+    """Eigenpairs of A = [diag(d) z; z^T alpha]; d, z float64 CUDA tensors of length n-1."""
+    device = d.device
+    n = d.numel() + 1
+    d = _dev_vec(d, n - 1, device, "d")
+    z = _dev_vec(z, n - 1, device, "z")
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        lam = torch.empty(n, dtype=torch.float64, device=device)
+        buf = _colmajor(n, device) if vectors else None
+        shift = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
+        mu = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
+        info = torch.empty(n, dtype=torch.int32, device=device)
+        rc = lib().arrow_eig(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(lam), _ptr(buf), n,
+                             _ptr(shift), _ptr(mu), _ptr(info))
+    _check(rc, "arrow_eig")
+    return EigOut(lam, None if buf is None else buf.t(), None, shift, mu, info)
+
+
+def dpr1_eig(d: torch.Tensor, u: torch.Tensor, rho: float, *, vectors: bool = True) -> EigOut:
+    """Eigenpairs of diag(d) + rho u u^T (rho > 0); d, u float64 CUDA tensors of length n."""
+    device = d.device
+    n = d.numel()
+    d = _dev_vec(d, n, device, "d")
+    u = _dev_vec(u, n, device, "u")
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        lam = torch.empty(n, dtype=torch.float64, device=device)
+        buf = _colmajor(n, device) if vectors else None
+        info = torch.empty(n, dtype=torch.int32, device=device)
+        rc = lib().dpr1_eig(h, n, _ptr(d), _ptr(u), float(rho), _ptr(lam), _ptr(buf), n, _ptr(info))
+    _check(rc, "dpr1_eig")
+    return EigOut(lam, None if buf is None else buf.t(), None, None, None, info)
+
+
+def arrow_svd(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool = True) -> EigOut:
+    """SVD of B = [diag(d) z; 0 alpha]; returns sigma in ``lam``, U and V."""
+    device = d.device
+    n = d.numel() + 1
+    d = _dev_vec(d, n - 1, device, "d")
+    z = _dev_vec(z, n - 1, device, "z")
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        sig = torch.empty(n, dtype=torch.float64, device=device)
+        vb = _colmajor(n, device) if vectors else None
+        ub = _colmajor(n, device) if vectors else None
+        info = torch.empty(n, dtype=torch.int32, device=device)
+        rc = lib().arrow_svd(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(sig), _ptr(ub), n, _ptr(vb), n,
+                             _ptr(info))
+    _check(rc, "arrow_svd")
+    return EigOut(sig, None if vb is None else vb.t(), None if ub is None else ub.t(), None, None, info)

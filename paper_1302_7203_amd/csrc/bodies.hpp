@@ -1,0 +1,336 @@
+// Problem descriptor, workspace layout and the per-element / per-eigenvalue
+// bodies of the kernels in arrow.hip.  Each body is a __host__ __device__
+// function of (problem, index, lane) so that a kernel is a thin wrapper that
+// maps its grid onto these indices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "solver.hpp"
+
+namespace ahd {
+
+// One problem as the caller hands it over (all pointers are device memory).
+struct ProbDesc {
+  int32_t kind;        // KIND_ARROW / KIND_DPR1 / KIND_SVD
+  int32_t n;           // matrix order
+  const double* d;     // ARROW, SVD: n-1 poles; DPR1: n diagonal entries (any order)
+  const double* z;     // ARROW, SVD: n-1 shaft entries; DPR1: u (n)
+  double scalar;       // ARROW, SVD: alpha; DPR1: rho
+  double* lam;         // n: eigenvalues (SVD: singular values), descending
+  double* V;           // n x n column-major (ARROW: V, DPR1: Q, SVD: right vectors) or null
+  int64_t ldv;
+  double* U;           // SVD left vectors or null
+  int64_t ldu;
+  double* shift;       // n or null: lambda_k = shift_k + mu_k (Remark 3 pairs)
+  double* mu;          // n or null
+  uint32_t* info;      // n or null: INFO_* bits
+  double* ws;          // workspace of ws_doubles(n) doubles
+};
+
+__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 19; }
+
+// Workspace of one problem.
+struct Ws {
+  double* hdr;      // [0],[1] corner (dd); [2] 1 if some pole is exactly 0; [4] problem flags (uint32)
+  uint32_t* st;     // per-input status written by the sort
+  double* ds;       // sorted d
+  double* zs;       // z (u) in sorted order
+  double* ch;       // arrowhead shaft^2, hi part
+  double* cl;       // arrowhead shaft^2, lo part
+  double* dz;       // |arrowhead shaft|
+  double* pv1;      // first pass: shift pole value
+  double* mu1;      // first pass: mu
+  double* kb1;      // first pass: K_b
+  int32_t* ip1;     // first pass: shift pole index
+  uint32_t* fl1;    // first pass: info bits
+  double* pv;       // final shift pole value (0 for an absolute shift)
+  double* sf;       // final shift offset
+  double* mu;       // final mu
+  double* inrm;     // final 1 / ||x||
+  int32_t* cnt;     // per eigenvalue, 6 counters: (bisection steps, double-double passes, plain O(n)
+                    // passes) of k_root, then the same three of k_check
+};
+
+__host__ __device__ inline Ws ws_view(double* base, int64_t n) {
+  const size_t N = (size_t)n;
+  Ws w;
+  w.hdr = base;
+  w.st = (uint32_t*)(base + 16);
+  double* p = base + 16 + N;
+  w.ds = p; p += N;
+  w.zs = p; p += N;
+  w.ch = p; p += N;
+  w.cl = p; p += N;
+  w.dz = p; p += N;
+  w.pv1 = p; p += N;
+  w.mu1 = p; p += N;
+  w.kb1 = p; p += N;
+  w.ip1 = (int32_t*)p; p += N;
+  w.fl1 = (uint32_t*)p; p += N;
+  w.pv = p; p += N;
+  w.sf = p; p += N;
+  w.mu = p; p += N;
+  w.inrm = p; p += N;
+  w.cnt = (int32_t*)p; p += 3 * N;
+  return w;
+}
+
+__host__ __device__ inline uint32_t* prob_flags(const Ws& w) { return (uint32_t*)(w.hdr + 4); }
+
+__host__ __device__ inline int sorted_count(const ProbDesc& D) {
+  return D.kind == KIND_DPR1 ? D.n : D.n - 1;
+}
+
+__host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w) {
+  Prob P;
+  P.n = D.n;
+  P.m = D.n - 1;
+  P.nsorted = sorted_count(D);
+  P.ds = w.ds;
+  P.zs = w.zs;
+  P.ch = w.ch;
+  P.cl = w.cl;
+  P.dz = w.dz;
+  P.corner = {w.hdr[0], w.hdr[1]};
+  P.rho = D.scalar;
+  return P;
+}
+
+__host__ __device__ inline bool finite_d(double x) { return x - x == 0.0; }
+
+// ---------------------------------------------------------------------------
+// normalisation (symmetric permutation to decreasing poles, Sec. 1 eq. (order)):
+// the rank of input j among all keys; ties broken by input index.
+
+template <int KIND>
+__host__ __device__ inline double sort_key(double d) {
+  if constexpr (KIND == KIND_SVD) return fabs(d);
+  else return d;
+}
+
+// status of input j: reducibility (Sec. 1) and domain checks
+template <int KIND>
+__host__ __device__ inline uint32_t input_status(const ProbDesc& D, int j, bool dup) {
+  uint32_t st = 0;
+  const double dj = D.d[j], zj = D.z[j];
+  if (!finite_d(dj) || !finite_d(zj)) st |= INFO_NONFINITE;
+  if (zj == 0.0 || dup) st |= INFO_REDUCIBLE;
+  if (KIND == KIND_SVD && dj == 0.0) st |= INFO_BAD_INPUT;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// prologue: the reduced arrowhead's shaft weights, exactly in double-double.
+
+template <int KIND>
+__host__ __device__ inline void prologue_elem(const ProbDesc& D, const Ws& w, int j) {
+  dd c;
+  if constexpr (KIND == KIND_ARROW) {
+    c = two_prod(w.zs[j], w.zs[j]);                       // zeta_j^2
+  } else if constexpr (KIND == KIND_SVD) {
+    const dd p = two_prod(w.ds[j], w.zs[j]);              // d_j zeta_j (Sec. 6.2)
+    c = dd_mul(p, p);
+  } else {
+    const double dn = w.ds[D.n - 1];                      // Sec. 6.3: zeta_j^2 = rho u_j^2 (d_j - d_n)
+    const dd diff = two_sum(w.ds[j], -dn);
+    c = dd_mul_d(dd_mul(two_prod(w.zs[j], w.zs[j]), diff), D.scalar);
+  }
+  w.ch[j] = c.hi;
+  w.cl[j] = c.lo;
+  w.dz[j] = (KIND == KIND_ARROW) ? fabs(w.zs[j]) : sqrt(c.hi);
+}
+
+// contribution of sorted entry j to the corner
+template <int KIND>
+__host__ __device__ inline dd corner_term(const ProbDesc& D, const Ws& w, int j) {
+  if constexpr (KIND == KIND_ARROW) return dd_from(0.0);
+  else if constexpr (KIND == KIND_SVD) return two_prod(w.zs[j], w.zs[j]);           // z^T z
+  else return dd_mul_d(two_prod(w.zs[j], w.zs[j]), D.scalar);                          // rho u^T u
+}
+
+template <int KIND>
+__host__ __device__ inline dd corner_base(const ProbDesc& D, const Ws& w) {
+  if constexpr (KIND == KIND_ARROW) return dd_from(D.scalar);                          // alpha
+  else if constexpr (KIND == KIND_SVD) return two_prod(D.scalar, D.scalar);            // alpha^2
+  else return dd_from(w.ds[D.n - 1]);                                                  // d_n
+}
+
+// ---------------------------------------------------------------------------
+// first pass for eigenvalue k: shift, b, bisection (Algorithm 5 without the
+// final K_nu test).
+
+template <int KIND, int G>
+__host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln) {
+  const Ws w = ws_view(D.ws, D.n);
+  const Prob P = make_prob(D, w);
+  const uint32_t pf = *prob_flags(w);
+  if (pf & INFO_NOT_SOLVED) {
+    if (ln == 0) {
+      w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0;
+      w.pv1[k] = NAN; w.mu1[k] = NAN; w.kb1[k] = NAN; w.ip1[k] = -1; w.fl1[k] = pf;
+    }
+    return;
+  }
+  if (P.m == 0) {  // n == 1: lambda = corner, x = [-1]
+    if (ln == 0) {
+      w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0;
+      w.pv1[k] = 0.0; w.mu1[k] = dd_to_d(P.corner); w.kb1[k] = 0.0; w.ip1[k] = -1; w.fl1[k] = 0;
+    }
+    return;
+  }
+  int i, side;
+  select_shift<KIND, G>(P, k, ln, i, side);
+  const BPass bp = b_pass<KIND, G>(P, i, side, ln, opt.fp64_b);
+  int iters = 0;
+  const double nu = bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
+  if (ln == 0) {
+    w.cnt[6 * k + 0] = iters;
+    w.cnt[6 * k + 1] = opt.fp64_b ? 0 : 1;
+    w.cnt[6 * k + 2] = ((k > 0 && k < P.m) ? 1 : 0) + (opt.fp64_b ? 1 : 0);
+    w.pv1[k] = P.ds[i];
+    w.mu1[k] = 1.0 / nu;
+    w.kb1[k] = bp.Kb;
+    w.ip1[k] = i;
+    uint32_t fl = opt.fp64_b ? 0u : INFO_DD_B;
+    // Theorem 6 needs K_b <= O(1/eps); flag when the double-double b cannot hold it
+    if (bp.Kb * (double)(D.n + 4) * 4.930380657631324e-32 > 1e-3) fl |= INFO_KB_LARGE;
+    w.fl1[k] = fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K_nu test and remedies (Algorithm 5, last part; Remarks 1 and 2), then the
+// eigenvector norm.  Writes the final shift pair and the caller's outputs.
+
+template <int KIND, int G>
+__host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln) {
+  const Ws w = ws_view(D.ws, D.n);
+  const Prob P = make_prob(D, w);
+  const uint32_t pf = *prob_flags(w);
+  if (pf & INFO_NOT_SOLVED) {
+    if (ln == 0) {
+      w.pv[k] = NAN; w.sf[k] = NAN; w.mu[k] = NAN; w.inrm[k] = NAN;
+      D.lam[k] = NAN;
+      if (D.shift) D.shift[k] = NAN;
+      if (D.mu) D.mu[k] = NAN;
+      if (D.info) D.info[k] = pf;
+    }
+    return;
+  }
+  double pv = w.pv1[k], s = 0.0, mu = w.mu1[k];
+  uint32_t fl = w.fl1[k];
+  const int m = P.m;
+  int c_it = 0, c_dd = 0, c_plain = 1;   // the norm pass
+  if (m > 0 && opt.remedies) {
+    const int i = w.ip1[k];
+    const int side = (k == i) ? +1 : -1;
+    const double di = P.ds[i];
+    const double lam1 = dd_to_d(dd_add_d(pval_dd<KIND>(di), mu));
+    // Theorem 2 (C1) and its exceptions (a)-(c): lambda near zero
+    const double quot = (fabs(pval<KIND>(di)) + fabs(mu)) / fabs(lam1);
+    // K_nu (eq. K0): ||A_i^{-1}||_2 = 1 / distance from d_i to the nearer of
+    // the two eigenvalues adjacent to d_i
+    const int o = (side > 0) ? k + 1 : k - 1;
+    const double dist_o = fabs(pdiff<KIND>(w.pv1[o], di) + w.mu1[o]);
+    const double knu = fabs(mu) / fmin(fabs(mu), dist_o);
+    const bool zero_pole = w.hdr[2] != 0.0;
+    if (quot > opt.tau_zero && !zero_pole) {
+      // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
+      int z0 = 0, it = 0;
+      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it);
+      pv = 0.0; s = 0.0; mu = z0 ? 0.0 : m2;
+      fl |= INFO_NEAR_ZERO;
+      c_it += it; c_dd += 1;
+    } else if (knu > opt.tau_nu) {
+      bool done = false;
+      const int i2 = (side > 0) ? i - 1 : i + 1;
+      if (i2 >= 0 && i2 < m) {
+        // Remark 2(a): the other neighbouring pole, if K_nu is small there
+        const double d2 = P.ds[i2];
+        const double mu2 = fabs(pdiff<KIND>(di, d2) + mu);
+        const int o2 = (side > 0) ? k - 1 : k + 1;
+        const double dist2 = fabs(pdiff<KIND>(w.pv1[o2], d2) + w.mu1[o2]);
+        const double knu2 = mu2 / fmin(mu2, dist2);
+        if (knu2 <= opt.tau_nu) {
+          const BPass bp = b_pass<KIND, G>(P, i2, -side, ln, opt.fp64_b);
+          int it = 0;
+          const double nu = bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
+          pv = d2; s = 0.0; mu = 1.0 / nu;
+          fl |= INFO_REMEDY_A;
+          done = true;
+          c_it += it; c_dd += opt.fp64_b ? 0 : 1; c_plain += opt.fp64_b ? 1 : 0;
+        }
+      }
+      if (!done) {
+        // Remark 2(b): invert A - sigma I with sigma between d_i and lambda,
+        // 2^-10 |mu| away from lambda
+        s = mu - mu * (1.0 / 1024.0);
+        int z0 = 0, it = 0;
+        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it);
+        pv = di; mu = z0 ? 0.0 : m2;
+        fl |= INFO_REMEDY_B;
+        c_it += it; c_dd += 1;
+      }
+    }
+  }
+  if constexpr (KIND == KIND_DPR1) {
+    // the smallest eigenvalue, when nearer to d_n than to d_{n-1}
+    if (m > 0 && k == m) {
+      const double dn = P.ds[P.nsorted - 1];
+      const double gap = P.ds[P.nsorted - 2] - dn;
+      const double tau = (pv - dn) + s + mu;
+      if (tau < 0.5 * gap) {
+        int it = 0;
+        const double t2 = dpr1_from_last_pole<G>(P, gap, ln, &it);
+        pv = dn; s = 0.0; mu = t2;
+        fl |= INFO_POLE_SHIFT;
+        c_it += it;
+      }
+    }
+  }
+  const double inrm = inv_norm<KIND, G>(P, pv, s, mu, ln);
+  if (ln == 0) {
+    w.cnt[6 * k + 3] = c_it;
+    w.cnt[6 * k + 4] = c_dd;
+    w.cnt[6 * k + 5] = c_plain;
+    w.pv[k] = pv;
+    w.sf[k] = s;
+    w.mu[k] = mu;
+    w.inrm[k] = inrm;
+    const dd sh = dd_add_d(pval_dd<KIND>(pv), s);
+    const double lam = dd_to_d(dd_add_d(sh, mu));
+    if constexpr (KIND == KIND_SVD) D.lam[k] = sqrt(fmax(lam, 0.0));
+    else D.lam[k] = lam;
+    if (D.shift) D.shift[k] = dd_to_d(sh);
+    if (D.mu) D.mu[k] = mu;
+    if (D.info) D.info[k] = fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// eigenvector entry (row r, caller order) of column k; eq. (eigenvecAi) with
+// the shift pair, normalised.  SVD also returns u_r (Sec. 6.2).
+
+template <int KIND>
+__host__ __device__ inline double vec_elem(const ProbDesc& D, double pv, double s, double mu, double inrm,
+                                           int r) {
+  const int n = D.n;
+  if constexpr (KIND == KIND_DPR1) {
+    return D.z[r] * inrm / (((D.d[r] - pv) - s) - mu);
+  } else {
+    if (r == n - 1) return -inrm;
+    const double num = (KIND == KIND_SVD) ? D.d[r] * D.z[r] : D.z[r];
+    return num * inrm / ((pdiff<KIND>(D.d[r], pv) - s) - mu);
+  }
+}
+
+// SVD left vector entry from the right vector entry v_r: u_j = sigma v_j / d_j,
+// u_n = alpha v_n / sigma
+__host__ __device__ inline double svd_left(const ProbDesc& D, double sigma, double v, int r) {
+  return (r == D.n - 1) ? D.scalar * v / sigma : sigma * v / D.d[r];
+}
+
+}  // namespace ahd

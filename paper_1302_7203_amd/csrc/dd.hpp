@@ -1,0 +1,86 @@
+// Double-double arithmetic on FP64, written from the published error-free
+// transformations: TwoSum (Knuth, TAOCP vol. 2, 4.2.2), FastTwoSum (Dekker
+// 1971), TwoProd through one fused multiply-add, and the usual double-double
+// add/mul/div built from them.  A value is the unevaluated sum hi + lo with
+// |lo| <= ulp(hi)/2; the unit roundoff of the format is about 2^-104, which
+// realises the "double of the working precision" of Sec. 4 (Theorem 6).
+//
+// Everything here must be compiled without floating-point contraction
+// (-ffp-contract=off): the transformations rely on each + and - being
+// rounded separately.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ahd {
+
+struct dd {
+  double hi, lo;
+};
+
+__host__ __device__ inline dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+// requires |a| >= |b| (or a == 0)
+__host__ __device__ inline dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  double e = b - (s - a);
+  return {s, e};
+}
+
+__host__ __device__ inline dd two_prod(double a, double b) {
+  double p = a * b;
+  double e = fma(a, b, -p);
+  return {p, e};
+}
+
+__host__ __device__ inline dd dd_from(double a) { return {a, 0.0}; }
+__host__ __device__ inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+
+__host__ __device__ inline dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  dd t = two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+__host__ __device__ inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+
+__host__ __device__ inline dd dd_add_d(dd a, double b) {
+  dd s = two_sum(a.hi, b);
+  s.lo += a.lo;
+  return fast_two_sum(s.hi, s.lo);
+}
+
+__host__ __device__ inline dd dd_mul(dd a, dd b) {
+  dd p = two_prod(a.hi, b.hi);
+  p.lo = fma(a.hi, b.lo, fma(a.lo, b.hi, p.lo));
+  return fast_two_sum(p.hi, p.lo);
+}
+
+__host__ __device__ inline dd dd_mul_d(dd a, double b) {
+  dd p = two_prod(a.hi, b);
+  p.lo = fma(a.lo, b, p.lo);
+  return fast_two_sum(p.hi, p.lo);
+}
+
+// three quotient digits, then renormalise
+__host__ __device__ inline dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd r = dd_sub(a, dd_mul_d(b, q1));
+  double q2 = r.hi / b.hi;
+  r = dd_sub(r, dd_mul_d(b, q2));
+  double q3 = r.hi / b.hi;
+  dd q = fast_two_sum(q1, q2);
+  return dd_add_d(q, q3);
+}
+
+__host__ __device__ inline double dd_to_d(dd a) { return a.hi + a.lo; }
+
+}  // namespace ahd

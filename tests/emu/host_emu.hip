@@ -1,0 +1,93 @@
+// Host-only driver of the library's kernel bodies (test infrastructure).
+//
+// It runs the same __host__ __device__ per-eigenvalue bodies that the GPU
+// kernels wrap, with one lane per eigenvalue (G = 1) and plain loops in place
+// of the grid, so that the method itself can be checked against the oracle on
+// a machine without a GPU.  The GPU path never uses this file.
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <vector>
+
+#include "../../paper_1302_7203_amd/csrc/bodies.hpp"
+
+using namespace ahd;
+
+template <int KIND>
+static void run(ProbDesc D, const Options& opt, double* U) {
+  const int ms = sorted_count(D);
+  Ws w = ws_view(D.ws, D.n);
+  for (int j = 0; j < ms; ++j) {
+    const double kj = sort_key<KIND>(D.d[j]);
+    int rank = 0;
+    bool dup = false;
+    for (int l = 0; l < ms; ++l) {
+      const double kl = sort_key<KIND>(D.d[l]);
+      rank += (kl > kj) || (kl == kj && l < j);
+      dup |= (kl == kj) && (l != j);
+    }
+    w.ds[rank] = D.d[j];
+    w.zs[rank] = D.z[j];
+    w.st[j] = input_status<KIND>(D, j, dup);
+  }
+  uint32_t st = 0;
+  int zp = 0;
+  dd acc = {0.0, 0.0};
+  for (int j = 0; j < ms; ++j) {
+    st |= w.st[j];
+    acc = dd_add(acc, corner_term<KIND>(D, w, j));
+  }
+  for (int j = 0; j < D.n - 1; ++j) {
+    prologue_elem<KIND>(D, w, j);
+    zp |= w.ds[j] == 0.0;
+  }
+  const dd c = dd_add(corner_base<KIND>(D, w), acc);
+  w.hdr[0] = c.hi;
+  w.hdr[1] = c.lo;
+  w.hdr[2] = zp ? 1.0 : 0.0;
+  *prob_flags(w) = st;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int k = 0; k < D.n; ++k) root_body<KIND, 1>(D, opt, k, 0);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int k = 0; k < D.n; ++k) check_body<KIND, 1>(D, opt, k, 0);
+  if (D.V) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < D.n; ++k) {
+      for (int r = 0; r < D.n; ++r) {
+        const double v = vec_elem<KIND>(D, w.pv[k], w.sf[k], w.mu[k], w.inrm[k], r);
+        D.V[(size_t)k * D.ldv + r] = v;
+        if (KIND == KIND_SVD && U) U[(size_t)k * D.ldv + r] = svd_left(D, D.lam[k], v, r);
+      }
+    }
+  }
+}
+
+extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, double scalar, double* lam,
+                         double* V, double* U, double* shift, double* mu, uint32_t* info, double tau_nu,
+                         double tau_zero, int fp64_b, int remedies, double* kb) {
+  std::vector<double> ws(ws_doubles(n), 0.0);
+  ProbDesc D{};
+  D.kind = kind;
+  D.n = (int32_t)n;
+  D.d = d;
+  D.z = z;
+  D.scalar = scalar;
+  D.lam = lam;
+  D.V = V;
+  D.ldv = n;
+  D.U = U;
+  D.ldu = n;
+  D.shift = shift;
+  D.mu = mu;
+  D.info = info;
+  D.ws = ws.data();
+  Options opt{tau_nu, tau_zero, fp64_b, remedies};
+  if (kind == KIND_ARROW) run<KIND_ARROW>(D, opt, U);
+  else if (kind == KIND_DPR1) run<KIND_DPR1>(D, opt, U);
+  else run<KIND_SVD>(D, opt, U);
+  if (kb) {
+    const Ws w = ws_view(D.ws, D.n);
+    for (int k = 0; k < D.n; ++k) kb[k] = w.kb1[k];
+  }
+  return 0;
+}

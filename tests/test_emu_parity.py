@@ -1,0 +1,106 @@
+"""The library's kernel bodies, driven on the host with one lane per eigenvalue,
+against the oracle (no GPU).  This checks the method as implemented; the GPU
+tests check the same bodies under the real grid."""
+import numpy as np
+import pytest
+
+import oracle
+from emu import emu
+from paper_1302_7203_amd import workloads as W
+from parity import TOL, assert_close, relerr
+
+EPS = 2.0 ** -52
+
+
+def _examples():
+    return {
+        "ex1": (np.array([2e-3, 1e-7, 0.0, -1e-7, -2e-3]), np.array([1e7, 1e7, 1.0, 1e7, 1e7]), 1e20),
+        "ex2": (np.array([1 + 4 * EPS, 1 + 3 * EPS, 1 + 2 * EPS, 1 + EPS]), np.array([1.0, 2, 3, 4]), 0.0),
+        "ex3": (np.array([1e10, 4, 3, 2, 1.0]), np.array([1e10, 1, 1, 1, 1.0]), 1e10),
+    }
+
+
+@pytest.mark.parametrize("name", ["ex1", "ex2", "ex3"])
+def test_examples(name, oracle_lib):
+    d, z, a = _examples()[name]
+    r = emu.solve(0, d, z, a)
+    ref = oracle.arrow_eig(d, z, a)
+    assert_close(r["lam"], ref.lam, f"{name} lambda")
+    assert_close(r["V"], ref.vec, f"{name} V")
+
+
+def test_example3_negative_control_and_kb(oracle_lib):
+    """With b in FP64 only (Algorithm 2) the example's eigenvalues lose the digits the
+    paper's Algorithm 1 column loses; with double-double b they are exact (Sec. 5, Ex. 3)."""
+    d, z, a = _examples()["ex3"]
+    ref = oracle.arrow_eig(d, z, a)
+    good = emu.solve(0, d, z, a)
+    bad = emu.solve(0, d, z, a, fp64_b=1, remedies=0)
+    e_good = relerr(good["lam"], ref.lam)
+    e_bad = relerr(bad["lam"], ref.lam)
+    assert e_good.max() < 1e-15
+    # printed Algorithm 1 errors: ~8e-12 (lambda_2) ... 2e-8 (lambda_5), 3.4e-7 (lambda_6)
+    assert e_bad[1] > 1e-12 and e_bad[4] > 1e-9 and e_bad[5] > 1e-8
+    printed_basic = [4.150396802313551, 3.161498641452035, 2.188045596352105, 1.216093560005649,
+                     -7.160348702977373e-1]
+    for k in range(1, 6):
+        e_printed = abs(printed_basic[k - 1] - ref.lam[k]) / abs(ref.lam[k])
+        assert 0.01 * e_printed < e_bad[k] < 100 * e_printed, (k, e_bad[k], e_printed)
+    # K_b table of the example (lambda_2..lambda_6); the printed K_nu ~ 1 values carry noise
+    kb_printed = [3.243243243540540e9, 3.636363636818182e9, 4.444444445000000e9, 5.217390439488477e9,
+                  5.217390439488477e9]
+    for k in range(1, 6):
+        assert abs(good["kb"][k] - kb_printed[k - 1]) <= 1e-6 * kb_printed[k - 1], (k, good["kb"][k])
+
+
+def test_uniform_512(oracle_lib):
+    pr = W.single_uniform_512()
+    r = emu.solve(0, pr.d, pr.z, pr.scalar)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "V")
+    assert np.all(np.diff(r["lam"]) < 0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 130])
+def test_small_and_ragged(n, oracle_lib):
+    pr = W.uniform_arrow(n, np.random.default_rng(n))
+    sh = W.shuffled(pr, 5)
+    r = emu.solve(0, sh.d, sh.z, sh.scalar)
+    ref = oracle.arrow_eig(sh.d, sh.z, sh.scalar)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "V")
+
+
+def test_graded_with_clusters(oracle_lib):
+    pr = W.graded_arrow(400, np.random.default_rng(17), clusters=10, cluster_size=8)
+    r = emu.solve(0, pr.d, pr.z, pr.scalar)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "V")
+
+
+@pytest.mark.parametrize("n", [1, 2, 60, 300])
+def test_dpr1(n, oracle_lib):
+    pr = W.dpr1(n, np.random.default_rng(40 + n))
+    r = emu.solve(1, pr.d, pr.z, pr.scalar)
+    ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "Q")
+
+
+@pytest.mark.parametrize("n", [2, 60, 300])
+def test_svd(n, oracle_lib):
+    pr = W.svd_arrow(n, np.random.default_rng(50 + n))
+    r = emu.solve(2, pr.d, pr.z, pr.scalar)
+    ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+    assert_close(r["lam"], ref.sigma, "sigma")
+    assert_close(r["V"], ref.V, "V")
+    assert_close(r["U"], ref.U, "U")
+
+
+def test_reducible_reported(oracle_lib):
+    r = emu.solve(0, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+    assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))
+    r = emu.solve(0, np.array([1.0, 0.7, 0.5]), np.array([1.0, 0.0, 3.0]), 0.0)
+    assert np.all(r["info"] & 16)

@@ -1,0 +1,207 @@
+"""GPU path (through the C ABI) against the oracle, element by element, at the
+1e-13 relative bar for every eigenvalue and every vector entry."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_7203_amd import workloads as W
+from parity import assert_close, relerr
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    from paper_1302_7203_amd import binding
+    assert torch.cuda.is_available()
+    binding.lib()
+    return torch, binding, torch.device("cuda", 0)
+
+
+def _arrow(gpu, d, z, a, vectors=True, pairs=False):
+    torch, binding, dev = gpu
+    out = binding.arrow_eig(torch.from_numpy(np.ascontiguousarray(d)).to(dev),
+                            torch.from_numpy(np.ascontiguousarray(z)).to(dev), a, vectors=vectors, pairs=pairs)
+    torch.cuda.synchronize(dev)
+    return out
+
+
+def _np(t):
+    return None if t is None else t.cpu().numpy()
+
+
+EXAMPLES = {
+    "ex1": (np.array([2e-3, 1e-7, 0.0, -1e-7, -2e-3]), np.array([1e7, 1e7, 1.0, 1e7, 1e7]), 1e20),
+    "ex2": (np.array([1 + 4 * EPS, 1 + 3 * EPS, 1 + 2 * EPS, 1 + EPS]), np.array([1.0, 2, 3, 4]), 0.0),
+    "ex3": (np.array([1e10, 4, 3, 2, 1.0]), np.array([1e10, 1, 1, 1, 1.0]), 1e10),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EXAMPLES))
+def test_examples(gpu, name, oracle_lib):
+    d, z, a = EXAMPLES[name]
+    out = _arrow(gpu, d, z, a, pairs=True)
+    ref = oracle.arrow_eig(d, z, a)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
+    # Remark 3 pairs: shift + mu represents lambda
+    lam2 = _np(out.shift) + _np(out.mu)
+    assert_close(lam2, ref.lam, "shift+mu")
+
+
+def test_example2_pairs_carry_32_digits(gpu, oracle_lib):
+    d, z, a = EXAMPLES["ex2"]
+    out = _arrow(gpu, d, z, a, pairs=True)
+    ref = oracle.arrow_eig(d, z, a)
+    sh, mu = _np(out.shift), _np(out.mu)
+    # lambda_2..lambda_4: the pair (d_i, mu) equals the oracle's (pole, tau) to ~1e-13 in mu
+    for k in (1, 2, 3):
+        assert sh[k] == d[ref.pole[k]]
+        assert abs(mu[k] - ref.tau[k]) <= 1e-13 * abs(ref.tau[k])
+
+
+def test_uniform_512_full(gpu, oracle_lib):
+    pr = W.single_uniform_512()
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
+
+
+def _sample_ks(n, info, step, extra=16):
+    ks = set(range(0, n, step)) | {0, 1, n - 2, n - 1}
+    flagged = np.flatnonzero(info & (2 | 4 | 8))
+    ks |= set(int(k) for k in flagged[:: max(1, flagged.size // 64)]) if flagged.size else set()
+    rng = np.random.default_rng(n)
+    ks |= set(int(k) for k in rng.integers(0, n, extra))
+    return np.array(sorted(ks), dtype=np.int64)
+
+
+def test_graded_4096_sampled(gpu, oracle_lib):
+    torch, _, _ = gpu
+    pr = W.single_graded_4096()
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    lam, info = _np(out.lam), _np(out.info).astype(np.uint32)
+    assert np.all(info & 1)                       # b in double-double everywhere
+    assert np.all(np.diff(lam) < 0)
+    ks = _sample_ks(pr.n, info, 8)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+    assert_close(lam[ks], ref.lam, "lambda")
+    V = out.V[:, torch.from_numpy(ks).to(out.V.device)].cpu().numpy()
+    assert_close(V, ref.vec, "V columns")
+
+
+def test_uniform_16384_sampled(gpu, oracle_lib):
+    torch, _, _ = gpu
+    pr = W.single_uniform_16384()
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    lam, info = _np(out.lam), _np(out.info).astype(np.uint32)
+    # interlacing with the (sorted) poles for every eigenvalue
+    assert np.all(lam[:-1] > pr.d) and np.all(pr.d > lam[1:])
+    ks = _sample_ks(pr.n, info, 512)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+    assert_close(lam[ks], ref.lam, "lambda")
+    V = out.V[:, torch.from_numpy(ks).to(out.V.device)].cpu().numpy()
+    assert_close(V, ref.vec, "V columns")
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_every_lane_count(gpu, lanes, oracle_lib):
+    _, binding, _ = gpu
+    pr = W.uniform_arrow(301, np.random.default_rng(3))
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    binding.set_option(binding.OPT_LANES, lanes)
+    try:
+        out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    finally:
+        binding.set_option(binding.OPT_LANES, 0)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 255, 1025])
+def test_small_ragged_shuffled(gpu, n, oracle_lib):
+    pr = W.shuffled(W.uniform_arrow(n, np.random.default_rng(n)), 9)
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
+
+
+def test_order_and_sign_invariance_bitwise(gpu):
+    pr = W.uniform_arrow(200, np.random.default_rng(8))
+    base = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    sh = W.shuffled(pr, 2)
+    perm = sh.meta["perm"]
+    out = _arrow(gpu, sh.d, sh.z, sh.scalar)
+    assert np.array_equal(_np(out.lam), _np(base.lam))
+    assert np.array_equal(_np(out.V)[:-1], _np(base.V)[perm])
+    z2 = pr.z.copy()
+    z2[7] = -z2[7]
+    fl = _arrow(gpu, pr.d, z2, pr.scalar)
+    assert np.array_equal(_np(fl.V)[7], -_np(base.V)[7])
+
+
+def test_repeat_is_bitwise_deterministic(gpu):
+    pr = W.single_graded_4096()
+    a = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    b = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    assert np.array_equal(_np(a.lam), _np(b.lam))
+    assert bool((a.V == b.V).all())
+
+
+def test_reducible_and_nonfinite_reported(gpu):
+    out = _arrow(gpu, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+    assert np.all(_np(out.info) & 16) and np.all(np.isnan(_np(out.lam)))
+    out = _arrow(gpu, np.array([1.0, np.inf, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+    assert np.all(_np(out.info) & 32)
+    # a good call after a bad one is unaffected
+    pr = W.uniform_arrow(50, np.random.default_rng(1))
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+
+
+def test_fp64_b_negative_control(gpu, oracle_lib):
+    _, binding, _ = gpu
+    d, z, a = EXAMPLES["ex3"]
+    ref = oracle.arrow_eig(d, z, a)
+    binding.set_option(binding.OPT_FP64_B, 1)
+    binding.set_option(binding.OPT_REMEDIES, 0)
+    try:
+        out = _arrow(gpu, d, z, a)
+    finally:
+        binding.set_option(binding.OPT_FP64_B, 0)
+        binding.set_option(binding.OPT_REMEDIES, 1)
+    e = relerr(_np(out.lam), ref.lam)
+    assert e[4] > 1e-9 and e[5] > 1e-8      # the digits Algorithm 1 loses (Sec. 5, Ex. 3)
+    good = _arrow(gpu, d, z, a)
+    assert relerr(_np(good.lam), ref.lam).max() < 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 1000])
+def test_dpr1(gpu, n, oracle_lib):
+    torch, binding, dev = gpu
+    pr = W.dpr1(n, np.random.default_rng(60 + n))
+    out = binding.dpr1_eig(torch.from_numpy(pr.d).to(dev), torch.from_numpy(pr.z).to(dev), pr.scalar)
+    torch.cuda.synchronize(dev)
+    ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "Q")
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 1000])
+def test_svd(gpu, n, oracle_lib):
+    torch, binding, dev = gpu
+    pr = W.svd_arrow(n, np.random.default_rng(70 + n))
+    out = binding.arrow_svd(torch.from_numpy(pr.d).to(dev), torch.from_numpy(pr.z).to(dev), pr.scalar)
+    torch.cuda.synchronize(dev)
+    ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+    assert_close(_np(out.lam), ref.sigma, "sigma")
+    assert_close(_np(out.V), ref.V, "V")
+    assert_close(_np(out.U), ref.U, "U")
