@@ -36,8 +36,9 @@ PEAK_HBM = 8.0e12               # bytes/s
 # Algorithmic FP64 operations per pole term of each O(n) pass (an FMA counts
 # 2, a divide or square root 1), read off the kernel bodies:
 F_BISECT = 6      # bisection step: e = d_j - d_i, fma(-nu, e, 1), e*(.), c_j/(.), sum
+F_RATIONAL = 11   # rational step: e, fma(nu, e, -1), e*(.), 1/(.), c_j*q, sum, t*e, e*q, *, sum
 F_SELECT = 4      # shift selection: (d_j - d_k) - mid, c_j/(.), sum
-F_DD = 108        # b in double-double: TwoSum, dd divide, dd accumulate + FP64 bounds
+F_DD = 44         # b in double-double: TwoSum (6), two-digit dd quotient (17), TwoSum accumulate (9), FP64 part (12)
 F_NORM = 6        # eigenvector norm: ((e_j - s) - mu)^2, c_j/(.), sum
 
 WORKLOADS = {
@@ -51,6 +52,58 @@ WORKLOADS = {
 }
 
 
+def batched_leg(args, binding, workloads, dev):
+    """10,000 independent problems (n log-uniform in [16, 1024]; half arrowhead, half DPR1) in one
+    hipGraph-captured plan, against the same problems solved one launch sequence each."""
+    import numpy as np
+    import torch
+
+    from paper_1302_7203_amd import batch
+
+    probs = workloads.batch_mixed()
+    pairs = sum(p.n for p in probs)
+    b = batch.Batch(probs, device=dev, graph=True)
+    b.run()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        b.run()
+    torch.cuda.synchronize(dev)
+    t_b = (time.perf_counter() - t0) / args.batch_steps
+    out_batched = b.out_pool.clone()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    b.run_sequential()
+    torch.cuda.synchronize(dev)
+    t_s = time.perf_counter() - t0
+    same = bool(torch.equal(b.out_pool, out_batched))
+    res = {"workload": "10,000 problems, n = round(exp U(ln16, ln1024)); even: arrowhead (d~U(-1,1), "
+                       "z~U(0.1,1)), odd: DPR1 (u = g/|g|, rho~U(0.1,10)); all eigenvalues + vectors",
+           "eigenpairs": pairs, "ms_batched": t_b * 1e3, "ms_sequential": t_s * 1e3,
+           "eigenpairs_per_s_batched": pairs / t_b, "eigenpairs_per_s_sequential": pairs / t_s,
+           "speedup": t_s / t_b, "graph": True, "sequential_bitwise_equal": same}
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(3)
+        worst_l = worst_v = 0.0
+        idx = rng.choice(len(probs), 24, replace=False)
+        for p in idx:
+            pr = probs[int(p)]
+            lam, V, _, _ = b.result(int(p))
+            ref = (oracle.arrow_eig if pr.kind == 0 else oracle.dpr1_eig)(pr.d, pr.z, pr.scalar)
+            lam_b = out_batched[b.packed.descs[int(p)].lam_off:b.packed.descs[int(p)].lam_off + pr.n]
+            worst_l = max(worst_l, float(np.max(np.abs(lam_b.cpu().numpy() - ref.lam) / np.abs(ref.lam))))
+            off = b.packed.descs[int(p)].vec_off
+            Vb = out_batched[off:off + pr.n * pr.n].view(pr.n, pr.n).t().cpu().numpy()
+            worst_v = max(worst_v, float(np.max(np.abs(Vb - ref.vec) / np.abs(ref.vec))))
+        res["parity"] = {"sample_problems": int(idx.size), "max_rel_err_lambda": worst_l, "max_rel_err_V": worst_v,
+                         "pass": bool(worst_l <= 1e-13 and worst_v <= 1e-13)}
+    b.close()
+    del b, out_batched
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +112,10 @@ def main():
     ap.add_argument("--workload", default="graded_4096", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=512, help="eigenpairs the oracle solves for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--root", default="rational", choices=["rational", "bisect"],
+                    help="root finder for the extreme eigenvalue of the shifted inverse")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched vs one-launch-per-solve leg")
+    ap.add_argument("--batch-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -79,6 +136,7 @@ def main():
     z = torch.from_numpy(pr.z).to(dev)
     torch.cuda.synchronize(dev)
 
+    binding.set_option(binding.OPT_ROOT, binding.ROOT_RATIONAL if args.root == "rational" else binding.ROOT_BISECT)
     binding.set_option(binding.OPT_TIMING, 0)
     for _ in range(args.warmup):
         out = binding.arrow_eig(d, z, pr.scalar)
@@ -100,7 +158,8 @@ def main():
     cnt = binding.last_counters()
     m = n - 1
 
-    root_flops = m * (F_BISECT * cnt["root_bisect"] + F_DD * cnt["root_dd"] + F_SELECT * cnt["root_plain"])
+    f_iter = F_RATIONAL if args.root == "rational" else F_BISECT
+    root_flops = m * (f_iter * cnt["root_bisect"] + F_DD * cnt["root_dd"] + F_SELECT * cnt["root_plain"])
     root_s = stages_ms[2] * 1e-3
     roof = {"kernel": "k_root", "bound": "alu", "achieved": root_flops / root_s / 1e12,
             "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": None}
@@ -124,7 +183,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "problems_per_step": 1, "parallelism": "single GPU"},
+        "config": {"workload": desc, "n": n, "problems_per_step": 1, "parallelism": "single GPU",
+                   "root_finder": args.root},
         "stages_ms": {k: float(v) for k, v in zip(("sort", "prologue", "root", "check", "vectors"), stages_ms)},
         "counters": cnt,
         "roofline": roof,
@@ -135,6 +195,9 @@ def main():
     info = out.info.cpu().numpy().astype(np.uint32)
     result["info_counts"] = {name: int(np.sum((info & bit) != 0)) for name, bit in
                              (("dd_b", 1), ("remedy_a", 2), ("remedy_b", 4), ("near_zero", 8), ("not_solved", 304))}
+
+    if not args.no_batch:
+        result["batched"] = batched_leg(args, binding, workloads, dev)
 
     if not args.no_cpu_baseline:
         import oracle

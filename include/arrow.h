@@ -62,6 +62,9 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_OPT_REMEDIES 4   /* 0: no K_nu / near-zero remedies (default 1) */
 #define ARROW_OPT_LANES 5      /* lanes per eigenvalue: 0 = automatic, else 1,2,4,...,64 */
 #define ARROW_OPT_TIMING 6     /* 1: record HIP events around each stage of later calls */
+#define ARROW_OPT_ROOT 7       /* root finder for the extreme eigenvalue of the inverse:
+                                  0 = bisection (Algorithm 3), 1 = safeguarded rational
+                                  (secular) iteration on the same function (default) */
 
 /* Create a handle on HIP device `device`.  *h receives the handle. */
 int arrow_create(arrow_handle_t* h, int device);
@@ -120,6 +123,74 @@ int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, doub
  */
 int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
               double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, uint32_t* info);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent problems of uneven order in one plan.
+ *
+ * Each problem is described by offsets (counted in elements) into three
+ * caller-owned device pools.  Vector outputs of a problem are column-major
+ * with leading dimension n.  Problems are independent: each one's results are
+ * the same whether it is solved alone or inside any batch (same order n gives
+ * the same schedule).
+ */
+#define ARROW_KIND_ARROW 0   /* arrowhead: d, z (n-1 each), scalar = alpha */
+#define ARROW_KIND_DPR1 1    /* diag(d) + rho u u^T: d, u (n each), scalar = rho > 0 */
+#define ARROW_KIND_SVD 2     /* triangular arrowhead SVD: d, z (n-1 each), scalar = alpha */
+
+typedef struct {
+  int32_t kind;       /* ARROW_KIND_* */
+  int32_t n;          /* matrix order, 1 <= n <= 46340 */
+  int64_t d_off;      /* in_pool offset of d */
+  int64_t z_off;      /* in_pool offset of z (DPR1: u) */
+  double scalar;      /* alpha, or rho for DPR1 */
+  int64_t lam_off;    /* out_pool offset of the n eigenvalues (SVD: singular values) */
+  int64_t vec_off;    /* out_pool offset of the n x n vectors (V, Q, or SVD right vectors), -1: none */
+  int64_t left_off;   /* SVD: out_pool offset of the n x n left vectors U, -1: none */
+  int64_t info_off;   /* info_pool offset of n uint32 ARROW_INFO_* words, -1: none */
+} arrow_desc_t;
+
+typedef struct arrow_batch_s* arrow_batch_t;
+
+#define ARROW_BATCH_GRAPH 1   /* capture the plan's launches in a HIP graph on its first run */
+
+/* Device bytes a plan for these problems needs (descriptor tables + per-problem workspace). */
+size_t arrow_batch_workspace_size(int64_t count, const arrow_desc_t* descs);
+
+/*
+ * Build a plan for `count` problems described by the HOST array `descs`.
+ * in_pool, out_pool, info_pool: device pools the offsets refer to (info_pool
+ * may be null when no problem asks for info).  workspace: device memory of at
+ * least arrow_batch_workspace_size bytes owned by the caller, or null to let
+ * the plan allocate (and free) its own.  The plan records the handle's options
+ * and stream; the descriptor tables are copied to the device on that stream.
+ * Invalid descriptors fail with -3.
+ */
+int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                       double* out_pool, uint32_t* info_pool, void* workspace, size_t workspace_bytes, int flags,
+                       arrow_batch_t* plan);
+
+/* Launch the plan on the handle's stream (asynchronous).  Can be run again. */
+int arrow_batch_run(arrow_batch_t plan);
+
+/* Synchronise the handle's stream and free the plan (and its own workspace). */
+int arrow_batch_destroy(arrow_batch_t plan);
+
+/* The same problems solved one after another with the single-problem entry
+ * points (one launch sequence per problem, on the handle's stream, sharing the
+ * handle's workspace): the reference the batched plan is measured against. */
+int arrow_solve_sequential(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                           double* out_pool, uint32_t* info_pool);
+
+/* create + run + destroy; returns after the solve has finished. */
+int arrow_solve_batched(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                        double* out_pool, uint32_t* info_pool);
+
+/*
+ * Batched schedule: lanes of a wavefront per eigenvalue (4, 8, 16, 32 or 64)
+ * for problems of order n <= n_max[e] (first matching entry, n_max strictly
+ * increasing, at most 16 entries; larger n use 64).  Filled by the autotuner.
+ */
+int arrow_set_lanes_table(arrow_handle_t h, int32_t entries, const int32_t* n_max, const int32_t* lanes);
 
 /*
  * Diagnostics of the most recent single-problem call on this handle.

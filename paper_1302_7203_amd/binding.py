@@ -33,6 +33,9 @@ OPT_FP64_B = 3
 OPT_REMEDIES = 4
 OPT_LANES = 5
 OPT_TIMING = 6
+OPT_ROOT = 7
+ROOT_BISECT = 0
+ROOT_RATIONAL = 1
 
 
 class ArrowError(RuntimeError):

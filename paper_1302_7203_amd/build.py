@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libarrow.so")
-SOURCES = [os.path.join(CSRC, "arrow.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("dd.hpp", "solver.hpp", "bodies.hpp")] + [
+SOURCES = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+HEADERS = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")) + [
     os.path.join(os.path.dirname(HERE), "include", "arrow.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -16,7 +16,8 @@
 #include <string.h>
 
 #include "../../include/arrow.h"
-#include "bodies.hpp"
+#include "blocks.hpp"
+#include "host.hpp"
 
 using namespace ahd;
 
@@ -27,114 +28,161 @@ static_assert(ARROW_INFO_DD_B == INFO_DD_B && ARROW_INFO_REMEDY_A == INFO_REMEDY
                   ARROW_INFO_POLE_SHIFT == INFO_POLE_SHIFT,
               "info bits");
 
-constexpr int BLOCK = 256;
-constexpr int VEC_ROWS = 1024;  // rows of one column written by one k_vec block
 
 // ---------------------------------------------------------------------------
 // kernels
 
+// Sorting (symmetric permutation to decreasing poles, Sec. 1): a one-block
+// check whether the input already is in that order (the usual case), then,
+// only if not, a rank count over a 2-D grid of (pole tile, comparison chunk)
+// blocks, then the scatter.  rank[] holds the count in its low 30 bits and a
+// duplicate marker in bit 30.
+constexpr int SORT_CHUNK = 2048;
+
+__host__ __device__ inline uint32_t* rank_array(const Ws& w, int64_t n) { return w.st + n; }
+
 template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
+__global__ __launch_bounds__(1024) void k_sortcheck(ProbDesc D) {
+  const Ws w = ws_view(D.ws, D.n);
+  const int ms = sorted_count(D);
+  uint32_t* rank = rank_array(w, D.n);
+  int bad = 0;
+  for (int j = threadIdx.x; j < ms; j += blockDim.x) {
+    rank[j] = 0;
+    if (j + 1 < ms && !(sort_key<KIND>(D.d[j]) > sort_key<KIND>(D.d[j + 1]))) bad = 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) w.hdr[5] = bad ? 1.0 : 0.0;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(BLOCK) void k_rank(ProbDesc D) {
   __shared__ double tile[BLOCK];
+  const Ws w = ws_view(D.ws, D.n);
+  if (w.hdr[5] == 0.0) return;  // already sorted
   const int ms = sorted_count(D);
   const int j = blockIdx.x * BLOCK + threadIdx.x;
   const double kj = (j < ms) ? sort_key<KIND>(D.d[j]) : NAN;
-  int rank = 0;
+  const int l0 = blockIdx.y * SORT_CHUNK;
+  const int l1 = min(ms, l0 + SORT_CHUNK);
+  uint32_t cnt = 0;
   bool dup = false;
-  for (int base = 0; base < ms; base += BLOCK) {
+  for (int base = l0; base < l1; base += BLOCK) {
     const int l = base + threadIdx.x;
-    tile[threadIdx.x] = (l < ms) ? sort_key<KIND>(D.d[l]) : NAN;
+    tile[threadIdx.x] = (l < l1) ? sort_key<KIND>(D.d[l]) : NAN;
     __syncthreads();
-    const int lim = min(BLOCK, ms - base);
+    const int lim = min(BLOCK, l1 - base);
     for (int t = 0; t < lim; ++t) {
       const double kl = tile[t];
       const int idx = base + t;
-      rank += (kl > kj) || (kl == kj && idx < j);
+      cnt += (kl > kj) || (kl == kj && idx < j);
       dup |= (kl == kj) && (idx != j);
     }
     __syncthreads();
   }
   if (j < ms) {
-    const Ws w = ws_view(D.ws, D.n);
-    w.ds[rank] = D.d[j];
-    w.zs[rank] = D.z[j];
-    w.st[j] = input_status<KIND>(D, j, dup);
+    uint32_t* rank = rank_array(w, D.n);
+    if (cnt) atomicAdd(&rank[j], cnt);
+    if (dup) atomicOr(&rank[j], 1u << 30);
   }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(BLOCK) void k_scatter(ProbDesc D) {
+  const Ws w = ws_view(D.ws, D.n);
+  const int ms = sorted_count(D);
+  const int j = blockIdx.x * BLOCK + threadIdx.x;
+  if (j >= ms) return;
+  int r = j;
+  bool dup = false;
+  if (w.hdr[5] != 0.0) {
+    const uint32_t raw = rank_array(w, D.n)[j];
+    r = (int)(raw & 0x3fffffffu);
+    dup = (raw >> 30) & 1u;
+  }
+  w.ds[r] = D.d[j];
+  w.zs[r] = D.z[j];
+  w.st[j] = input_status<KIND>(D, j, dup);
 }
 
 template <int KIND>
 __global__ __launch_bounds__(BLOCK) void k_prologue(ProbDesc D) {
-  __shared__ double shi[BLOCK], slo[BLOCK];
-  __shared__ uint32_t sst[BLOCK];
+  prologue_block<KIND>(D);
+}
+
+// Root and check stages: ROOT_BLOCK threads per block, G lanes per
+// eigenvalue.  When the sorted poles and shaft weights fit, the block first
+// copies them to LDS and every O(n) pass reads them from there.
+constexpr int ROOT_BLOCK = 512;
+
+__device__ inline void stage_hot(const ProbDesc& D, double* lds) {
   const Ws w = ws_view(D.ws, D.n);
-  const int ms = sorted_count(D);
-  const int m = D.n - 1;
-  const int t = threadIdx.x;
-  uint32_t st = 0;
-  uint32_t zp = 0;
-  dd acc = {0.0, 0.0};
-  for (int j = t; j < ms; j += BLOCK) {
-    st |= w.st[j];
-    acc = dd_add(acc, corner_term<KIND>(D, w, j));
-  }
-  for (int j = t; j < m; j += BLOCK) {
-    prologue_elem<KIND>(D, w, j);
-    zp |= (w.ds[j] == 0.0) ? 1u : 0u;
-  }
-  shi[t] = acc.hi;
-  slo[t] = acc.lo;
-  sst[t] = st | (zp << 31);
+  const int ns = sorted_count(D), m = D.n - 1;
+  for (int j = threadIdx.x; j < ns; j += blockDim.x) lds[j] = w.ds[j];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) lds[ns + j] = w.ch[j];
   __syncthreads();
-  for (int o = BLOCK / 2; o > 0; o >>= 1) {
-    if (t < o) {
-      const dd a = dd_add(dd{shi[t], slo[t]}, dd{shi[t + o], slo[t + o]});
-      shi[t] = a.hi;
-      slo[t] = a.lo;
-      sst[t] |= sst[t + o];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    const dd c = dd_add(corner_base<KIND>(D, w), dd{shi[0], slo[0]});
-    w.hdr[0] = c.hi;
-    w.hdr[1] = c.lo;
-    w.hdr[2] = (sst[0] >> 31) ? 1.0 : 0.0;
-    *prob_flags(w) = sst[0] & 0x7fffffffu;
-  }
 }
 
-template <int KIND, int G>
-__global__ __launch_bounds__(BLOCK) void k_root(ProbDesc D, Options opt) {
-  const int gid = blockIdx.x * BLOCK + threadIdx.x;
+// STAGE is a template argument so that, once the bodies are inlined, the
+// compiler sees the hot arrays as LDS and reads them with ds_read.
+template <int KIND, int G, bool STAGE>
+__global__ __launch_bounds__(ROOT_BLOCK) void k_root(ProbDesc D, Options opt) {
+  extern __shared__ double lds[];
+  if constexpr (STAGE) stage_hot(D, lds);
+  const int gid = blockIdx.x * ROOT_BLOCK + threadIdx.x;
   const int k = gid / G;
   if (k >= D.n) return;
-  root_body<KIND, G>(D, opt, k, gid % G);
+  if constexpr (STAGE) root_body<KIND, G, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
+  else root_body<KIND, G>(D, opt, k, gid % G);
 }
 
-template <int KIND, int G>
-__global__ __launch_bounds__(BLOCK) void k_check(ProbDesc D, Options opt) {
-  const int gid = blockIdx.x * BLOCK + threadIdx.x;
+template <int KIND, int G, bool STAGE>
+__global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
+  extern __shared__ double lds[];
+  if constexpr (STAGE) stage_hot(D, lds);
+  const int gid = blockIdx.x * ROOT_BLOCK + threadIdx.x;
   const int k = gid / G;
   if (k >= D.n) return;
-  check_body<KIND, G>(D, opt, k, gid % G);
+  if constexpr (STAGE) check_body<KIND, G, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
+  else check_body<KIND, G>(D, opt, k, gid % G);
 }
+
+// Eigenvector stage: a block owns VEC_TILE rows (kept in registers) of
+// VEC_COLS consecutive columns and streams those columns to HBM.
+constexpr int VEC_RPT = 4;                     // rows per thread
+constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
+constexpr int VEC_COLS = 16;                   // columns per block
 
 template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int tiles) {
-  const int col = blockIdx.x / tiles;
-  const int tile = blockIdx.x - col * tiles;
-  const Ws w = ws_view(D.ws, D.n);
-  const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
-  double* vc = D.V + (size_t)col * (size_t)D.ldv;
-  double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
-  const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
+__global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles) {
+  const int ct = blockIdx.x / row_tiles;
+  const int rt = blockIdx.x - ct * row_tiles;
+  const int n = D.n;
+  const Ws w = ws_view(D.ws, n);
+  double dr[VEC_RPT], num[VEC_RPT];
 #pragma unroll
-  for (int q = 0; q < VEC_ROWS / BLOCK; ++q) {
-    const int r = tile * VEC_ROWS + q * BLOCK + threadIdx.x;
-    if (r < D.n) {
-      const double v = vec_elem<KIND>(D, pv, s, mu, inrm, r);
-      __builtin_nontemporal_store(v, vc + r);
-      if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
+  for (int q = 0; q < VEC_RPT; ++q) {
+    const int r = rt * VEC_TILE + q * BLOCK + threadIdx.x;
+    const bool in = r < n;
+    const bool body = (KIND == KIND_DPR1) ? in : (r < n - 1);
+    dr[q] = body ? D.d[r] : 0.0;
+    num[q] = body ? ((KIND == KIND_SVD) ? dr[q] * D.z[r] : D.z[r]) : 0.0;
+  }
+  const int c0 = ct * VEC_COLS;
+  const int c1 = min(n, c0 + VEC_COLS);
+  for (int col = c0; col < c1; ++col) {
+    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
+    double* vc = D.V + (size_t)col * (size_t)D.ldv;
+    double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
+    const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
+#pragma unroll
+    for (int q = 0; q < VEC_RPT; ++q) {
+      const int r = rt * VEC_TILE + q * BLOCK + threadIdx.x;
+      if (r < n) {
+        const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);
+        __builtin_nontemporal_store(v, vc + r);
+        if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
+      }
     }
   }
 }
@@ -142,77 +190,42 @@ __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int tiles) {
 // ---------------------------------------------------------------------------
 // host side
 
-struct arrow_handle_s {
-  int device;
-  hipStream_t stream;
-  double* ws;
-  size_t ws_cap;  // doubles
-  Options opt;
-  int lanes;      // 0: automatic
-  int timing;     // record stage events
-  hipEvent_t ev[6];
-  int ev_made;
-  int have_last;  // a timed call has been launched
-  int64_t last_n;
-  uint32_t magic;
-};
-
-static constexpr uint32_t HANDLE_MAGIC = 0xA770E16u;
-
-static bool valid(arrow_handle_t h) { return h && h->magic == HANDLE_MAGIC; }
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-static int ensure_ws(arrow_handle_t h, size_t doubles) {
-  if (doubles <= h->ws_cap) return ARROW_OK;
-  if (h->ws) {
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->ws);
-    h->ws = nullptr;
-    h->ws_cap = 0;
-  }
-  if (hipMalloc((void**)&h->ws, doubles * sizeof(double)) != hipSuccess) {
-    h->ws = nullptr;
-    return ARROW_ERR_NOMEM;
-  }
-  h->ws_cap = doubles;
-  return ARROW_OK;
-}
-
-static int auto_lanes(int64_t n) {
-  int64_t want = n / 8;
-  int g = 1;
-  while (g < 64 && g < want) g <<= 1;
-  return g;
-}
-
 template <int KIND, int G>
-static void launch_rc(const ProbDesc& D, const Options& opt, hipStream_t st, bool check) {
+static void launch_rc(const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds) {
   const int64_t threads = (int64_t)D.n * G;
-  const dim3 grid((unsigned)((threads + BLOCK - 1) / BLOCK));
-  if (!check) hipLaunchKernelGGL((k_root<KIND, G>), grid, dim3(BLOCK), 0, st, D, opt);
-  else hipLaunchKernelGGL((k_check<KIND, G>), grid, dim3(BLOCK), 0, st, D, opt);
+  const dim3 grid((unsigned)((threads + ROOT_BLOCK - 1) / ROOT_BLOCK));
+  if (lds > 0) {
+    if (!check) hipLaunchKernelGGL((k_root<KIND, G, true>), grid, dim3(ROOT_BLOCK), lds, st, D, opt);
+    else hipLaunchKernelGGL((k_check<KIND, G, true>), grid, dim3(ROOT_BLOCK), lds, st, D, opt);
+  } else {
+    if (!check) hipLaunchKernelGGL((k_root<KIND, G, false>), grid, dim3(ROOT_BLOCK), 0, st, D, opt);
+    else hipLaunchKernelGGL((k_check<KIND, G, false>), grid, dim3(ROOT_BLOCK), 0, st, D, opt);
+  }
 }
 
 template <int KIND>
-static void launch_rc_any(int G, const ProbDesc& D, const Options& opt, hipStream_t st, bool check) {
+static void launch_rc_any(int G, const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds) {
   switch (G) {
-    case 1: launch_rc<KIND, 1>(D, opt, st, check); break;
-    case 2: launch_rc<KIND, 2>(D, opt, st, check); break;
-    case 4: launch_rc<KIND, 4>(D, opt, st, check); break;
-    case 8: launch_rc<KIND, 8>(D, opt, st, check); break;
-    case 16: launch_rc<KIND, 16>(D, opt, st, check); break;
-    case 32: launch_rc<KIND, 32>(D, opt, st, check); break;
-    default: launch_rc<KIND, 64>(D, opt, st, check); break;
+    case 1: launch_rc<KIND, 1>(D, opt, st, check, lds); break;
+    case 2: launch_rc<KIND, 2>(D, opt, st, check, lds); break;
+    case 4: launch_rc<KIND, 4>(D, opt, st, check, lds); break;
+    case 8: launch_rc<KIND, 8>(D, opt, st, check, lds); break;
+    case 16: launch_rc<KIND, 16>(D, opt, st, check, lds); break;
+    case 32: launch_rc<KIND, 32>(D, opt, st, check, lds); break;
+    default: launch_rc<KIND, 64>(D, opt, st, check, lds); break;
+  }
+}
+
+template <int KIND>
+static int launch_problem(arrow_handle_t h, const ProbDesc& D);
+
+// one single-problem solve (all launches) on the handle's stream; used by the
+// sequential reference path of the batched API
+int launch_single(arrow_handle_t h, const ProbDesc& D) {
+  switch (D.kind) {
+    case KIND_ARROW: return launch_problem<KIND_ARROW>(h, D);
+    case KIND_DPR1: return launch_problem<KIND_DPR1>(h, D);
+    default: return launch_problem<KIND_SVD>(h, D);
   }
 }
 
@@ -226,18 +239,28 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   };
   const int ms = sorted_count(D);
   mark(0);
-  if (ms > 0) hipLaunchKernelGGL(k_sort<KIND>, dim3((ms + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, st, D);
+  if (ms > 0) {
+    const unsigned jt = (unsigned)((ms + BLOCK - 1) / BLOCK);
+    const unsigned lc = (unsigned)((ms + SORT_CHUNK - 1) / SORT_CHUNK);
+    hipLaunchKernelGGL(k_sortcheck<KIND>, dim3(1), dim3(1024), 0, st, D);
+    hipLaunchKernelGGL(k_rank<KIND>, dim3(jt, lc), dim3(BLOCK), 0, st, D);
+    hipLaunchKernelGGL(k_scatter<KIND>, dim3(jt), dim3(BLOCK), 0, st, D);
+  }
   mark(1);
   hipLaunchKernelGGL(k_prologue<KIND>, dim3(1), dim3(BLOCK), 0, st, D);
   mark(2);
   const int G = h->lanes ? h->lanes : auto_lanes(D.n);
-  launch_rc_any<KIND>(G, D, h->opt, st, false);
+  const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
+  const size_t lds = (hot <= h->lds_max) ? hot : 0;
+  launch_rc_any<KIND>(G, D, h->opt, st, false, lds);
   mark(3);
-  launch_rc_any<KIND>(G, D, h->opt, st, true);
+  launch_rc_any<KIND>(G, D, h->opt, st, true, lds);
   mark(4);
   if (D.V) {
-    const int tiles = (D.n + VEC_ROWS - 1) / VEC_ROWS;
-    hipLaunchKernelGGL(k_vec<KIND>, dim3((unsigned)((int64_t)tiles * D.n)), dim3(BLOCK), 0, st, D, tiles);
+    const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
+    const int col_chunks = (D.n + VEC_COLS - 1) / VEC_COLS;
+    hipLaunchKernelGGL(k_vec<KIND>, dim3((unsigned)((int64_t)row_tiles * col_chunks)), dim3(BLOCK), 0, st, D,
+                       row_tiles);
   }
   mark(5);
   h->have_last = tm ? 1 : 0;
@@ -262,7 +285,23 @@ int arrow_create(arrow_handle_t* h, int device) {
   p->opt.tau_zero = 10.0;
   p->opt.fp64_b = 0;
   p->opt.remedies = 1;
+  p->opt.root = ROOT_RATIONAL;
   p->lanes = 0;
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) v = 0;
+    p->lds_max = v > 0 ? (size_t)v : 0;
+    v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) v = 0;
+    p->cus = v > 0 ? v : 1;
+  }
+  // default batched schedule: lanes per eigenvalue by order n
+  {
+    const int32_t tn[] = {24, 48, 96, 192, 2147483647};
+    const int32_t tg[] = {4, 8, 16, 32, 64};
+    p->ntab = 5;
+    for (int e = 0; e < 5; ++e) { p->tab_n[e] = tn[e]; p->tab_g[e] = tg[e]; }
+  }
   p->magic = HANDLE_MAGIC;
   *h = p;
   return ARROW_OK;
@@ -302,6 +341,10 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
       return ARROW_OK;
     case ARROW_OPT_REMEDIES:
       h->opt.remedies = value != 0.0;
+      return ARROW_OK;
+    case ARROW_OPT_ROOT:
+      if (value != 0.0 && value != 1.0) return -3;
+      h->opt.root = (int)value;
       return ARROW_OK;
     case ARROW_OPT_TIMING:
       if (value != 0.0 && !h->ev_made) {

@@ -1,0 +1,426 @@
+// Batched solves: many independent ARROW / DPR1 / SVD problems of uneven
+// order in one plan of four launches.
+//
+//   k_b_prep    one block per problem: sort (Sec. 1 ordering) and prologue
+//   k_b_stage   persistent: every wavefront takes (problem, eigenvalue-group)
+//               items from an atomic queue and runs the first pass (shift,
+//               b, root of the inverse) on them; problems are queued by
+//               decreasing order n so the long items start first
+//   k_b_stage   the same queue again for the K_nu test, remedies and norms
+//   k_b_vec     flat map of every problem's n*n vector entries onto blocks
+//
+// A wavefront gives G lanes to each eigenvalue, so one item covers 64/G
+// consecutive eigenvalues of one problem; G comes from the handle's table of
+// lanes by order n (filled by the autotuner).
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "blocks.hpp"
+#include "host.hpp"
+
+using namespace ahd;
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int STAGE_BLOCK = 256;
+constexpr int VEC_CHUNK = 1024;   // vector entries per k_b_vec block
+
+struct BatchArgs {
+  const ProbDesc* descs;     // problems in queue order
+  const int32_t* item_start; // count + 1 prefix sums of items
+  const int32_t* lanes;      // G per problem
+  const int32_t* vec_start;  // count + 1 prefix sums of vector chunks
+  uint32_t* counters;        // [0] first-pass queue, [1] check queue
+  int32_t count;
+  int32_t total_items;
+};
+
+__device__ inline int find_problem(const int32_t* start, int count, int x) {
+  int lo = 0, hi = count;   // start[lo] <= x < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) B.counters[threadIdx.x] = 0;
+  const ProbDesc D = B.descs[blockIdx.x];
+  if (sorted_count(D) > 0) {
+    switch (D.kind) {
+      case KIND_ARROW: sort_block<KIND_ARROW>(D); break;
+      case KIND_DPR1: sort_block<KIND_DPR1>(D); break;
+      default: sort_block<KIND_SVD>(D); break;
+    }
+  }
+  switch (D.kind) {
+    case KIND_ARROW: prologue_block<KIND_ARROW>(D); break;
+    case KIND_DPR1: prologue_block<KIND_DPR1>(D); break;
+    default: prologue_block<KIND_SVD>(D); break;
+  }
+}
+
+template <bool CHECK, int KIND, int G>
+__device__ inline void run_item(const ProbDesc& D, const Options& opt, int k, int ln) {
+  if (CHECK) check_body<KIND, G>(D, opt, k, ln);
+  else root_body<KIND, G>(D, opt, k, ln);
+}
+
+template <bool CHECK, int KIND>
+__device__ inline void run_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln) {
+  switch (G) {
+    case 4: run_item<CHECK, KIND, 4>(D, opt, k, ln); break;
+    case 8: run_item<CHECK, KIND, 8>(D, opt, k, ln); break;
+    case 16: run_item<CHECK, KIND, 16>(D, opt, k, ln); break;
+    case 32: run_item<CHECK, KIND, 32>(D, opt, k, ln); break;
+    default: run_item<CHECK, KIND, 64>(D, opt, k, ln); break;
+  }
+}
+
+template <bool CHECK>
+__global__ __launch_bounds__(STAGE_BLOCK) void k_b_stage(BatchArgs B, Options opt) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = (int)atomicAdd(&B.counters[CHECK ? 1 : 0], 1u);
+    item = __shfl(item, 0);
+    if (item >= B.total_items) break;
+    const int p = find_problem(B.item_start, B.count, item);
+    const ProbDesc D = B.descs[p];
+    const int G = B.lanes[p];
+    const int k = (item - B.item_start[p]) * (WAVE / G) + lane / G;
+    const int ln = lane & (G - 1);
+    if (k < D.n) {
+      switch (D.kind) {
+        case KIND_ARROW: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;
+        case KIND_DPR1: run_kind<CHECK, KIND_DPR1>(D, opt, G, k, ln); break;
+        default: run_kind<CHECK, KIND_SVD>(D, opt, G, k, ln); break;
+      }
+    }
+  }
+}
+
+template <int KIND>
+__device__ inline void vec_chunk(const ProbDesc& D, int64_t base) {
+  const int n = D.n;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  const Ws w = ws_view(D.ws, n);
+#pragma unroll
+  for (int q = 0; q < VEC_CHUNK / BLOCK; ++q) {
+    const int64_t e64 = base + q * BLOCK + threadIdx.x;
+    if (e64 >= nn) break;
+    const uint32_t e = (uint32_t)e64;
+    const uint32_t col = e / (uint32_t)n;
+    const int r = (int)(e - col * (uint32_t)n);
+    const bool body = (KIND == KIND_DPR1) ? true : (r < n - 1);
+    const double dr = body ? D.d[r] : 0.0;
+    const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[r] : D.z[r]) : 0.0;
+    const double v = vec_entry<KIND>(dr, num, r == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
+    __builtin_nontemporal_store(v, D.V + e);
+    if (KIND == KIND_SVD && D.U) __builtin_nontemporal_store(svd_left(D, D.lam[col], v, r), D.U + e);
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_b_vec(BatchArgs B) {
+  const int p = find_problem(B.vec_start, B.count, (int)blockIdx.x);
+  const ProbDesc D = B.descs[p];
+  if (!D.V) return;
+  const int64_t base = (int64_t)((int)blockIdx.x - B.vec_start[p]) * VEC_CHUNK;
+  switch (D.kind) {
+    case KIND_ARROW: vec_chunk<KIND_ARROW>(D, base); break;
+    case KIND_DPR1: vec_chunk<KIND_DPR1>(D, base); break;
+    default: vec_chunk<KIND_SVD>(D, base); break;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+struct arrow_batch_s {
+  arrow_handle_t h;
+  int64_t count;
+  int flags;
+  int32_t total_items, total_vec;
+  void* dev;            // device block: counters, descriptors, tables, workspaces
+  int own_dev;          // dev allocated by the plan
+  size_t dev_bytes;
+  std::vector<ProbDesc> descs;
+  std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1)
+  BatchArgs args;
+  int persistent_blocks;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int captured;
+  uint32_t magic;
+};
+
+static constexpr uint32_t BATCH_MAGIC = 0xBA7C4EDu;
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t off_desc, off_tab, off_ws, total;
+};
+
+static Layout plan_layout(int64_t count, const arrow_desc_t* descs) {
+  Layout L;
+  size_t off = 256;                                   // counters
+  L.off_desc = off;
+  off = align_up(off + (size_t)count * sizeof(ProbDesc), 256);
+  L.off_tab = off;
+  off = align_up(off + (size_t)(3 * count + 2) * sizeof(int32_t), 256);
+  L.off_ws = off;
+  for (int64_t p = 0; p < count; ++p) off += align_up(ws_doubles(descs[p].n) * sizeof(double), 256);
+  L.total = off;
+  return L;
+}
+
+static int check_desc(const arrow_desc_t& a) {
+  if (a.kind < ARROW_KIND_ARROW || a.kind > ARROW_KIND_SVD) return 1;
+  if (a.n < 1 || a.n > 46340) return 1;
+  if (!(a.scalar - a.scalar == 0.0)) return 1;
+  if (a.kind == ARROW_KIND_DPR1 && !(a.scalar > 0.0)) return 1;
+  const int64_t ms = a.kind == ARROW_KIND_DPR1 ? a.n : a.n - 1;
+  if (ms > 0 && (a.d_off < 0 || a.z_off < 0)) return 1;
+  if (a.lam_off < 0) return 1;
+  if (a.kind == ARROW_KIND_SVD && a.left_off >= 0 && a.vec_off < 0) return 1;
+  return 0;
+}
+
+extern "C" {
+
+size_t arrow_batch_workspace_size(int64_t count, const arrow_desc_t* descs) {
+  if (count < 1 || !descs) return 0;
+  return plan_layout(count, descs).total;
+}
+
+int arrow_set_lanes_table(arrow_handle_t h, int32_t entries, const int32_t* n_max, const int32_t* lanes) {
+  if (!valid(h)) return -1;
+  if (entries < 1 || entries > LANE_TABLE_MAX) return -2;
+  if (!n_max) return -3;
+  if (!lanes) return -4;
+  for (int e = 0; e < entries; ++e) {
+    const int g = lanes[e];
+    if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64) return -4;
+    if (e > 0 && n_max[e] <= n_max[e - 1]) return -3;
+  }
+  h->ntab = entries;
+  for (int e = 0; e < entries; ++e) {
+    h->tab_n[e] = n_max[e];
+    h->tab_g[e] = lanes[e];
+  }
+  return ARROW_OK;
+}
+
+int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                       double* out_pool, uint32_t* info_pool, void* workspace, size_t workspace_bytes, int flags,
+                       arrow_batch_t* plan) {
+  if (!valid(h)) return -1;
+  if (count < 1 || count > (int64_t)1 << 24) return -2;
+  if (!descs) return -3;
+  if (!in_pool) return -4;
+  if (!out_pool) return -5;
+  if (!plan) return -10;
+  for (int64_t p = 0; p < count; ++p) {
+    if (check_desc(descs[p])) return -3;
+    if (descs[p].info_off >= 0 && !info_pool) return -6;
+  }
+  DeviceGuard g(h->device);
+  const Layout L = plan_layout(count, descs);
+  if (workspace && workspace_bytes < L.total) return -8;
+  arrow_batch_s* b = new (std::nothrow) arrow_batch_s();
+  if (!b) return ARROW_ERR_NOMEM;
+  b->h = h;
+  b->count = count;
+  b->flags = flags;
+  b->dev_bytes = L.total;
+  if (workspace) {
+    b->dev = workspace;
+    b->own_dev = 0;
+  } else {
+    if (hipMalloc(&b->dev, L.total) != hipSuccess) {
+      delete b;
+      return ARROW_ERR_NOMEM;
+    }
+    b->own_dev = 1;
+  }
+  // queue order: decreasing n (stable), so the longest items are taken first
+  std::vector<int64_t> order((size_t)count);
+  for (int64_t p = 0; p < count; ++p) order[(size_t)p] = p;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t c) { return descs[a].n > descs[c].n; });
+  b->descs.resize((size_t)count);
+  b->tabs.assign((size_t)(3 * count + 2), 0);
+  int32_t* item_start = b->tabs.data();
+  int32_t* lanes = item_start + count + 1;
+  int32_t* vec_start = lanes + count;
+  char* base = (char*)b->dev;
+  size_t wsoff = L.off_ws;
+  int64_t items = 0, vchunks = 0;
+  for (int64_t q = 0; q < count; ++q) {
+    const arrow_desc_t& a = descs[order[(size_t)q]];
+    ProbDesc D{};
+    D.kind = a.kind;
+    D.n = a.n;
+    D.d = in_pool + a.d_off;
+    D.z = in_pool + a.z_off;
+    D.scalar = a.scalar;
+    D.lam = out_pool + a.lam_off;
+    D.V = a.vec_off >= 0 ? out_pool + a.vec_off : nullptr;
+    D.ldv = a.n;
+    D.U = (a.kind == ARROW_KIND_SVD && a.left_off >= 0) ? out_pool + a.left_off : nullptr;
+    D.ldu = a.n;
+    D.info = a.info_off >= 0 ? info_pool + a.info_off : nullptr;
+    D.ws = (double*)(base + wsoff);
+    wsoff += align_up(ws_doubles(a.n) * sizeof(double), 256);
+    b->descs[(size_t)q] = D;
+    const int G = table_lanes(h, a.n);
+    lanes[q] = G;
+    item_start[q] = (int32_t)items;
+    items += (a.n + (WAVE / G) - 1) / (WAVE / G);
+    vec_start[q] = (int32_t)vchunks;
+    if (D.V) vchunks += ((int64_t)a.n * a.n + VEC_CHUNK - 1) / VEC_CHUNK;
+  }
+  item_start[count] = (int32_t)items;
+  vec_start[count] = (int32_t)vchunks;
+  if (items > INT32_MAX / 2 || vchunks > INT32_MAX / 2) {
+    if (b->own_dev) (void)hipFree(b->dev);
+    delete b;
+    return -2;
+  }
+  b->total_items = (int32_t)items;
+  b->total_vec = (int32_t)vchunks;
+  hipStream_t st = h->stream;
+  if (hipMemcpyAsync(base + L.off_desc, b->descs.data(), (size_t)count * sizeof(ProbDesc), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(base + L.off_tab, b->tabs.data(), b->tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                     st) != hipSuccess) {
+    if (b->own_dev) (void)hipFree(b->dev);
+    delete b;
+    return ARROW_ERR_HIP;
+  }
+  BatchArgs& A = b->args;
+  A.descs = (const ProbDesc*)(base + L.off_desc);
+  A.item_start = (const int32_t*)(base + L.off_tab);
+  A.lanes = A.item_start + count + 1;
+  A.vec_start = A.lanes + count;
+  A.counters = (uint32_t*)base;
+  A.count = (int32_t)count;
+  A.total_items = b->total_items;
+  // persistent grid: enough resident wavefronts to fill every SIMD several times
+  const int64_t want = (int64_t)h->cus * 16 * WAVE / STAGE_BLOCK;
+  const int64_t need = ((int64_t)items * WAVE + STAGE_BLOCK - 1) / STAGE_BLOCK;
+  b->persistent_blocks = (int)std::max<int64_t>(1, std::min(want, need));
+  b->magic = BATCH_MAGIC;
+  *plan = b;
+  return ARROW_OK;
+}
+
+static int batch_launch(arrow_batch_s* b, hipStream_t st) {
+  const BatchArgs A = b->args;
+  const Options opt = b->h->opt;
+  hipLaunchKernelGGL(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), 0, st, A);
+  hipLaunchKernelGGL((k_b_stage<false>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
+  hipLaunchKernelGGL((k_b_stage<true>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
+  if (b->total_vec > 0) hipLaunchKernelGGL(k_b_vec, dim3((unsigned)b->total_vec), dim3(BLOCK), 0, st, A);
+  return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
+}
+
+int arrow_batch_run(arrow_batch_t b) {
+  if (!b || b->magic != BATCH_MAGIC || !valid(b->h)) return -1;
+  DeviceGuard g(b->h->device);
+  hipStream_t st = b->h->stream;
+  (void)hipGetLastError();
+  if (!(b->flags & ARROW_BATCH_GRAPH)) return batch_launch(b, st);
+  if (!b->captured) {
+    // capture on a private stream: the legacy null stream cannot be captured
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return ARROW_ERR_HIP;
+    int rc = ARROW_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = ARROW_ERR_HIP;
+    if (rc == ARROW_OK) {
+      rc = batch_launch(b, cap);
+      if (hipStreamEndCapture(cap, &b->graph) != hipSuccess) rc = ARROW_ERR_HIP;
+    }
+    if (rc == ARROW_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+      rc = ARROW_ERR_HIP;
+    (void)hipStreamDestroy(cap);
+    if (rc != ARROW_OK) return rc;
+    b->captured = 1;
+  }
+  return hipGraphLaunch(b->exec, st) == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
+}
+
+int arrow_batch_destroy(arrow_batch_t b) {
+  if (!b || b->magic != BATCH_MAGIC) return -1;
+  DeviceGuard g(b->h->device);
+  (void)hipStreamSynchronize(b->h->stream);
+  if (b->captured) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+  }
+  if (b->own_dev) (void)hipFree(b->dev);
+  b->magic = 0;
+  delete b;
+  return ARROW_OK;
+}
+
+int arrow_solve_sequential(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                           double* out_pool, uint32_t* info_pool) {
+  if (!valid(h)) return -1;
+  if (count < 1) return -2;
+  if (!descs) return -3;
+  if (!in_pool) return -4;
+  if (!out_pool) return -5;
+  int64_t nmax = 1;
+  for (int64_t p = 0; p < count; ++p) {
+    if (check_desc(descs[p])) return -3;
+    if (descs[p].info_off >= 0 && !info_pool) return -6;
+    nmax = std::max<int64_t>(nmax, descs[p].n);
+  }
+  DeviceGuard g(h->device);
+  const int rc = ensure_ws(h, ws_doubles(nmax));
+  if (rc) return rc;
+  for (int64_t p = 0; p < count; ++p) {
+    const arrow_desc_t& a = descs[p];
+    ProbDesc D{};
+    D.kind = a.kind;
+    D.n = a.n;
+    D.d = in_pool + a.d_off;
+    D.z = in_pool + a.z_off;
+    D.scalar = a.scalar;
+    D.lam = out_pool + a.lam_off;
+    D.V = a.vec_off >= 0 ? out_pool + a.vec_off : nullptr;
+    D.ldv = a.n;
+    D.U = (a.kind == ARROW_KIND_SVD && a.left_off >= 0) ? out_pool + a.left_off : nullptr;
+    D.ldu = a.n;
+    D.info = a.info_off >= 0 ? info_pool + a.info_off : nullptr;
+    D.ws = h->ws;
+    const int r = launch_single(h, D);
+    if (r) return r;
+  }
+  return ARROW_OK;
+}
+
+int arrow_solve_batched(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,
+                        double* out_pool, uint32_t* info_pool) {
+  arrow_batch_t b = nullptr;
+  int rc = arrow_batch_create(h, count, descs, in_pool, out_pool, info_pool, nullptr, 0, 0, &b);
+  if (rc != ARROW_OK) return rc;
+  rc = arrow_batch_run(b);
+  const int rc2 = arrow_batch_destroy(b);
+  return rc != ARROW_OK ? rc : rc2;
+}
+
+}  // extern "C"

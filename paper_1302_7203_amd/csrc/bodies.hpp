@@ -84,7 +84,12 @@ __host__ __device__ inline int sorted_count(const ProbDesc& D) {
   return D.kind == KIND_DPR1 ? D.n : D.n - 1;
 }
 
-__host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w) {
+// HOT: hot_d / hot_c are copies of the sorted poles and shaft weights (in LDS)
+// used by the O(n) passes in place of the workspace arrays.  A compile-time
+// choice, so that the compiler knows which memory the passes read.
+template <bool HOT = false>
+__host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const double* hot_d = nullptr,
+                                          const double* hot_c = nullptr) {
   Prob P;
   P.n = D.n;
   P.m = D.n - 1;
@@ -96,6 +101,10 @@ __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w) {
   P.dz = w.dz;
   P.corner = {w.hdr[0], w.hdr[1]};
   P.rho = D.scalar;
+  if constexpr (HOT) {
+    P.ds = hot_d;
+    P.ch = hot_c;
+  }
   return P;
 }
 
@@ -162,10 +171,11 @@ __host__ __device__ inline dd corner_base(const ProbDesc& D, const Ws& w) {
 // first pass for eigenvalue k: shift, b, bisection (Algorithm 5 without the
 // final K_nu test).
 
-template <int KIND, int G>
-__host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln) {
+template <int KIND, int G, bool HOT = false>
+__host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln,
+                                          const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);
-  const Prob P = make_prob(D, w);
+  const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
@@ -185,7 +195,9 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   select_shift<KIND, G>(P, k, ln, i, side);
   const BPass bp = b_pass<KIND, G>(P, i, side, ln, opt.fp64_b);
   int iters = 0;
-  const double nu = bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
+  const double nu = (opt.root == ROOT_RATIONAL)
+      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters)
+      : bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
   if (ln == 0) {
     w.cnt[6 * k + 0] = iters;
     w.cnt[6 * k + 1] = opt.fp64_b ? 0 : 1;
@@ -205,10 +217,11 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
 // K_nu test and remedies (Algorithm 5, last part; Remarks 1 and 2), then the
 // eigenvector norm.  Writes the final shift pair and the caller's outputs.
 
-template <int KIND, int G>
-__host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln) {
+template <int KIND, int G, bool HOT = false>
+__host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln,
+                                           const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);
-  const Prob P = make_prob(D, w);
+  const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
@@ -240,7 +253,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     if (quot > opt.tau_zero && !zero_pole) {
       // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
       int z0 = 0, it = 0;
-      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it);
+      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root);
       pv = 0.0; s = 0.0; mu = z0 ? 0.0 : m2;
       fl |= INFO_NEAR_ZERO;
       c_it += it; c_dd += 1;
@@ -248,16 +261,23 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       bool done = false;
       const int i2 = (side > 0) ? i - 1 : i + 1;
       if (i2 >= 0 && i2 < m) {
-        // Remark 2(a): the other neighbouring pole, if K_nu is small there
+        // Remark 2(a): the other neighbouring pole, if K_nu is small there and
+        // lambda is not so close to d_i that its vector entries would suffer
         const double d2 = P.ds[i2];
         const double mu2 = fabs(pdiff<KIND>(di, d2) + mu);
         const int o2 = (side > 0) ? k - 1 : k + 1;
         const double dist2 = fabs(pdiff<KIND>(w.pv1[o2], d2) + w.mu1[o2]);
         const double knu2 = mu2 / fmin(mu2, dist2);
-        if (knu2 <= opt.tau_nu) {
+        // the eigenvector entry of the nearer pole d_i is then formed as
+        // (d_i - d_{i2}) - mu2, which cancels by |d_i - d_{i2}| / |lambda - d_i|
+        const double cancel = fabs(pdiff<KIND>(di, d2)) / fabs(mu);
+        if (knu2 <= opt.tau_nu && cancel <= 8.0) {
           const BPass bp = b_pass<KIND, G>(P, i2, -side, ln, opt.fp64_b);
           int it = 0;
-          const double nu = bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
+          const int side2 = -side;
+          const double nu = (opt.root == ROOT_RATIONAL)
+              ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it)
+              : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
           pv = d2; s = 0.0; mu = 1.0 / nu;
           fl |= INFO_REMEDY_A;
           done = true;
@@ -269,7 +289,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
         // 2^-10 |mu| away from lambda
         s = mu - mu * (1.0 / 1024.0);
         int z0 = 0, it = 0;
-        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it);
+        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root);
         pv = di; mu = z0 ? 0.0 : m2;
         fl |= INFO_REMEDY_B;
         c_it += it; c_dd += 1;
@@ -319,11 +339,24 @@ __host__ __device__ inline double vec_elem(const ProbDesc& D, double pv, double 
                                            int r) {
   const int n = D.n;
   if constexpr (KIND == KIND_DPR1) {
-    return D.z[r] * inrm / (((D.d[r] - pv) - s) - mu);
+    return (D.z[r] * inrm) * recip(((D.d[r] - pv) - s) - mu);
   } else {
     if (r == n - 1) return -inrm;
     const double num = (KIND == KIND_SVD) ? D.d[r] * D.z[r] : D.z[r];
-    return num * inrm / ((pdiff<KIND>(D.d[r], pv) - s) - mu);
+    return (num * inrm) * recip((pdiff<KIND>(D.d[r], pv) - s) - mu);
+  }
+}
+
+// the same entry from values preloaded per row: dr = d_r, num = z_r (u_r for
+// DPR1, d_r z_r for SVD); last marks the corner row of ARROW / SVD
+template <int KIND>
+__host__ __device__ inline double vec_entry(double dr, double num, bool last, double pv, double s, double mu,
+                                            double inrm) {
+  if constexpr (KIND == KIND_DPR1) {
+    return (num * inrm) * recip(((dr - pv) - s) - mu);
+  } else {
+    if (last) return -inrm;
+    return (num * inrm) * recip((pdiff<KIND>(dr, pv) - s) - mu);
   }
 }
 

@@ -42,12 +42,17 @@ constexpr uint32_t INFO_NOT_SOLVED = INFO_REDUCIBLE | INFO_NONFINITE | INFO_BAD_
 
 constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 3
 constexpr int MAX_BISECT = 4000;
+constexpr int MAX_RATIONAL = 60;     // rational steps before falling back to bisection steps
+constexpr int RATIONAL_TO_BISECT = 14;
+
+enum RootMethod { ROOT_BISECT = 0, ROOT_RATIONAL = 1 };
 
 struct Options {
   double tau_nu;     // K_nu threshold for the Remark 2 remedies
   double tau_zero;   // threshold on (|d_i| + |mu|) / |lambda| for Remark 1
   int fp64_b;        // 1: b by Algorithm 2 in FP64 only (negative control)
   int remedies;      // 0: skip the K_nu and near-zero remedies
+  int root;          // RootMethod for the extreme eigenvalue of the inverse
 };
 
 // Read-only view of one problem after normalisation (sorted order).
@@ -88,45 +93,83 @@ __host__ __device__ inline dd pval_dd(double d) {
   else return dd_from(d);
 }
 
+// 1/x to about one ulp: on the device the hardware reciprocal estimate
+// refined by two Newton steps (x finite, nonzero and in the normal range, as
+// every denominator here is); on the host an ordinary division.
+__host__ __device__ inline double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 // ---------------------------------------------------------------------------
-// group reductions (XOR butterfly: every lane of the group gets the same bits)
+// group reductions.  Every step adds a value and its partner's, so every lane
+// of the group ends with the same bits.  Partners within 16 lanes come from
+// DPP lane permutes (quad xor 1, quad xor 2, half-row mirror, row mirror);
+// the 16- and 32-lane steps use the LDS crossbar (ds_bpermute).
 
-template <int G>
-__host__ __device__ inline double gsum(double v) {
-  if constexpr (G > 1) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-  }
+#if defined(__HIP_DEVICE_COMPILE__)
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+#endif
+
+constexpr int DPP_QUAD_XOR1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;   // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;        // lane i <-> 15 - i within 16
+
+template <int G, class Op>
+__host__ __device__ inline double greduce(double v, Op op) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (G >= 2) v = op(v, dpp<DPP_QUAD_XOR1>(v));
+  if constexpr (G >= 4) v = op(v, dpp<DPP_QUAD_XOR2>(v));
+  if constexpr (G >= 8) v = op(v, dpp<DPP_HALF_MIRROR>(v));
+  if constexpr (G >= 16) v = op(v, dpp<DPP_MIRROR>(v));
+  if constexpr (G >= 32) v = op(v, __shfl_xor(v, 16, G));
+  if constexpr (G >= 64) v = op(v, __shfl_xor(v, 32, G));
+#endif
   return v;
 }
 
-template <int G>
-__host__ __device__ inline double gmax(double v) {
-  if constexpr (G > 1) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
-  }
-  return v;
-}
+struct OpAdd {
+  __host__ __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMax {
+  __host__ __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+struct OpMin {
+  __host__ __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
 
 template <int G>
-__host__ __device__ inline double gmin(double v) {
-  if constexpr (G > 1) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, G));
-  }
-  return v;
-}
+__host__ __device__ inline double gsum(double v) { return greduce<G>(v, OpAdd()); }
+
+template <int G>
+__host__ __device__ inline double gmax(double v) { return greduce<G>(v, OpMax()); }
+
+template <int G>
+__host__ __device__ inline double gmin(double v) { return greduce<G>(v, OpMin()); }
 
 template <int G>
 __host__ __device__ inline dd gsum_dd(dd v) {
-  if constexpr (G > 1) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      dd w = {__shfl_xor(v.hi, o, G), __shfl_xor(v.lo, o, G)};
-      v = dd_add(v, w);
-    }
-  }
+#if defined(__HIP_DEVICE_COMPILE__)
+  if constexpr (G >= 2) v = dd_add(v, dd{dpp<DPP_QUAD_XOR1>(v.hi), dpp<DPP_QUAD_XOR1>(v.lo)});
+  if constexpr (G >= 4) v = dd_add(v, dd{dpp<DPP_QUAD_XOR2>(v.hi), dpp<DPP_QUAD_XOR2>(v.lo)});
+  if constexpr (G >= 8) v = dd_add(v, dd{dpp<DPP_HALF_MIRROR>(v.hi), dpp<DPP_HALF_MIRROR>(v.lo)});
+  if constexpr (G >= 16) v = dd_add(v, dd{dpp<DPP_MIRROR>(v.hi), dpp<DPP_MIRROR>(v.lo)});
+  if constexpr (G >= 32) v = dd_add(v, dd{__shfl_xor(v.hi, 16, G), __shfl_xor(v.lo, 16, G)});
+  if constexpr (G >= 64) v = dd_add(v, dd{__shfl_xor(v.hi, 32, G), __shfl_xor(v.lo, 32, G)});
+#endif
   return v;
 }
 
@@ -145,7 +188,8 @@ __host__ __device__ inline void select_shift(const Prob& P, int k, int ln, int& 
   const double dk = P.ds[k];
   const double mid = 0.5 * pdiff<KIND>(P.ds[k - 1], dk);
   double s = 0.0;
-  for (int j = ln; j < m; j += G) s += P.ch[j] / (pdiff<KIND>(P.ds[j], dk) - mid);
+#pragma unroll 4
+  for (int j = ln; j < m; j += G) s += P.ch[j] * recip(pdiff<KIND>(P.ds[j], dk) - mid);
   s = gsum<G>(s);
   const double a = dd_to_d(dd_sub(P.corner, pval_dd<KIND>(dk)));
   const double fmid = (a - mid) - s;
@@ -172,22 +216,23 @@ __host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, 
   double wsum = 0.0;                    // sum_{j != i} |shaft_j| / |e_j|
   double dmx = -INFINITY, dmn = INFINITY, gmx = -INFINITY, gmn = INFINITY;
   const double rzi = 1.0 / P.dz[i];
+#pragma unroll 2
   for (int j = ln; j < m; j += G) {
     if (j == i) continue;
     const double ej = pdiff<KIND>(P.ds[j], di);
-    const double t = P.ch[j] / ej;
+    const double rj = recip(ej);                    // delta_j, the diagonal of A_i^{-1}
+    const double t = P.ch[j] * rj;
     if (j < i) f1 += t; else f2 += t;
     if (!fp64_b) {
-      const dd q = dd_div(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di));
-      if (j < i) p1 = dd_add(p1, q); else p2 = dd_add(p2, q);
+      const dd q = dd_div2(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di));
+      if (j < i) dd_acc(p1, q); else dd_acc(p2, q);
     }
-    const double delta = 1.0 / ej;                  // diagonal of A_i^{-1}
-    const double wj = P.dz[j] / fabs(ej);           // |w_j| |zeta_i|
+    const double wj = P.dz[j] * fabs(rj);           // |w_j| |zeta_i|
     wsum += wj;
-    dmx = fmax(dmx, delta);
-    dmn = fmin(dmn, delta);
-    gmx = fmax(gmx, delta + wj * rzi);
-    gmn = fmin(gmn, delta - wj * rzi);
+    dmx = fmax(dmx, rj);
+    dmn = fmin(dmn, rj);
+    gmx = fmax(gmx, rj + wj * rzi);
+    gmn = fmin(gmn, rj - wj * rzi);
   }
   f1 = gsum<G>(f1);
   f2 = gsum<G>(f2);
@@ -205,8 +250,8 @@ __host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, 
     r.b = ((-a.hi + f1) + f2) / ci;
     num_abs = fabs(r.b) * ci;
   } else {
-    p1 = gsum_dd<G>(p1);
-    p2 = gsum_dd<G>(p2);
+    p1 = gsum_dd<G>(dd_norm(p1));
+    p2 = gsum_dd<G>(dd_norm(p2));
     dd pp, qq;
     if (-a.hi > 0) { pp = dd_add(dd_neg(a), p1); qq = dd_neg(p2); }
     else { pp = p1; qq = dd_sub(a, p2); }
@@ -249,9 +294,10 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
   int it = 0;
   while ((hi - lo) / fabs(mid) > 2.0 * EPS && it < MAX_BISECT) {
     double S = 0.0;
+#pragma unroll 4
     for (int j = ln; j < m; j += G) {
       const double e = pdiff<KIND>(P.ds[j], di);
-      const double t = P.ch[j] / (e * fma(-mid, e, 1.0));
+      const double t = P.ch[j] * recip(e * fma(-mid, e, 1.0));
       S += (j == i) ? 0.0 : t;
     }
     S = gsum<G>(S);
@@ -262,6 +308,152 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
   }
   if (iters) *iters = it;
   return hi;
+}
+
+// ---------------------------------------------------------------------------
+// Secular (rational) iteration for the same exterior eigenvalue.  With the
+// poles of the inverse, delta_j = 1/e_j, and weights W_j = w_j^2 the Pick
+// function reads g(nu) = b - nu + psi(nu), psi(nu) = sum_k W_k / (nu - delta_k),
+// and on the exterior side all terms of psi share one sign.  In the variable
+// x = side * nu the problem takes the one form
+//     h(x) = c0 - kappa x + psi_x(x) = 0,  x > y = max_k side*delta_k,
+// with psi_x positive, decreasing and convex.  Each step fits psi_x by
+// A/(x - y) + B through its value and slope at the current point (the
+// nearest pole carries the singularity) and solves the fitted equation in
+// closed form; a step that leaves the bracket kept from the signs of h is
+// replaced by the bracket midpoint, and after RATIONAL_TO_BISECT steps only
+// midpoints are taken.  One O(n) pass per step gives psi and psi'.
+
+// sums over j != excl of  c_j / (e_j (nu e_j - 1)),  c_j / (nu e_j - 1)^2  and
+// c_j e_j / (nu e_j - 1)^3, with e_j = pdiff(d_j, pv) - s (the pole terms of
+// psi and of its first two derivatives, up to constant factors)
+template <int KIND, int G>
+__host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
+                                         double& sum, double& dsum, double& d2sum) {
+  double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll 4
+  for (int j = ln; j < P.m; j += G) {
+    const double e = pdiff<KIND>(P.ds[j], pv) - s;
+    const double q = recip(e * fma(nu, e, -1.0));
+    const double t = P.ch[j] * q;
+    const double eq = e * q;               // 1 / (nu e - 1)
+    const double d1 = (t * e) * eq;
+    const double d2 = d1 * (e * eq);
+    a += (j == excl) ? 0.0 : t;
+    b += (j == excl) ? 0.0 : d1;
+    c += (j == excl) ? 0.0 : d2;
+  }
+  sum = gsum<G>(a);
+  dsum = gsum<G>(b);
+  d2sum = gsum<G>(c);
+}
+
+// The rational step in x-space: the zero of c0 - kappa x + A/(x - p) + B with
+// A, B fitted to psi_x and its slope at x and the pole p either the nearest
+// pole y of psi_x or p = x + 2 psi'/psi'' (the pole that also matches psi'';
+// it never lies right of y since every pole is left of x).  NaN when the
+// fitted equation has no zero right of p.
+__host__ __device__ inline double rational_candidate(double x, double psi_x, double dpsi_x, double pole, double c0,
+                                                     int kappa) {
+  const double u = x - pole;
+  const double A = -dpsi_x * u * u;
+  const double B = psi_x - A / u;
+  double un = NAN;
+  if (kappa) {
+    const double beta = c0 + B - pole;
+    const double disc = sqrt(beta * beta + 4.0 * A);
+    un = (beta >= 0) ? 0.5 * (beta + disc) : 2.0 * A / (disc - beta);
+  } else {
+    const double beta = c0 + B;
+    if (beta < 0) un = -A / beta;
+  }
+  return (un > 0) ? pole + un : NAN;
+}
+
+// Midpoint of a bracket 0 <= lo < hi in the ordering of the FP64 bit patterns
+// (monotone for non-negative numbers): the arithmetic midpoint when lo and hi
+// are within a binade or two, the geometric one when they are decades apart.
+__host__ __device__ inline double bits_mid(double lo, double hi) {
+  uint64_t a, b;
+  lo += 0.0;   // -0 -> +0
+  hi += 0.0;
+  __builtin_memcpy(&a, &lo, sizeof a);
+  __builtin_memcpy(&b, &hi, sizeof b);
+  const uint64_t c = a + (b - a) / 2;
+  double r;
+  __builtin_memcpy(&r, &c, sizeof r);
+  return r;
+}
+
+// Next point of the safeguarded iteration and whether to stop.  During the
+// rational phase the second-order candidate is taken when it lies inside the
+// bracket, else the nearest-pole candidate, else the midpoint.  A candidate
+// step that is still large and no less than 0.3 times the previous step shows
+// linear (slow) progress: the midpoint is taken instead.  Stop when a
+// candidate no longer moves x, when |h| is down to its rounding level hnoise,
+// or when the bracket is within 4 ulps.
+__host__ __device__ inline double rational_next(double x, double h, double hnoise, double psi_x, double dpsi_x,
+                                                double d2psi_x, double y, double c0, int kappa, double lo, double hi,
+                                                int it, double prev_step, int* done) {
+  *done = 0;
+  if ((hi - lo) <= 4.0 * EPS * fabs(x)) { *done = 1; return x; }
+  if (it < RATIONAL_TO_BISECT) {
+    double cand = NAN;
+    if (d2psi_x > 0) {
+      const double pe = x + 2.0 * dpsi_x / d2psi_x;
+      if (pe <= y && pe < x) cand = rational_candidate(x, psi_x, dpsi_x, pe, c0, kappa);
+    }
+    if (!(cand > lo && cand < hi)) cand = rational_candidate(x, psi_x, dpsi_x, y, c0, kappa);
+    if (cand == cand && (fabs(cand - x) <= 2.0 * EPS * fabs(cand) || fabs(h) <= hnoise)) {
+      *done = 1;
+      return (cand > lo && cand < hi) ? cand : x;
+    }
+    // a bracket spanning decades above a positive end: slow linear steps are
+    // replaced by its (near-geometric) bit-pattern midpoint
+    const bool decades = lo > 0.0 && hi > 16.0 * lo;
+    const double step = fabs(cand - x);
+    const bool slow = decades && it >= 2 && step > 0.3 * prev_step && step > 1e-3 * fabs(x);
+    if (cand > lo && cand < hi && !slow) return cand;
+  }
+  return (lo > 0.0 && hi > 16.0 * lo) ? bits_mid(lo, hi) : 0.5 * (lo + hi);
+}
+
+// extreme eigenvalue of A_i^{-1} on the given side, by the rational iteration
+template <int KIND, int G>
+__host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
+                                                   double hi, double ymax_nu, int ln, int* iters) {
+  const double sg = (double)side;
+  const double di = P.ds[i];
+  const double rci = 1.0 / P.ch[i];
+  // x-space bracket
+  double xlo = (side > 0) ? lo : -hi;
+  double xhi = (side > 0) ? hi : -lo;
+  const double y = sg * ymax_nu;
+  const double c0 = sg * b;
+  double x = xhi;
+  int it = 0;
+  double prev_step = INFINITY;
+  for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
+    const double nu = sg * x;
+    double s1, s2, s3;
+    psi_pass<KIND, G>(P, di, 0.0, i, nu, ln, s1, s2, s3);
+    const double rnu = 1.0 / nu;
+    const double psi = (s1 + rnu) * rci;                       // psi(nu)
+    const double dpsi = -(s2 + rnu * rnu) * rci;               // psi'(nu)
+    const double d2psi = 2.0 * (s3 + rnu * rnu * rnu) * rci;   // psi''(nu)
+    const double psi_x = sg * psi, dpsi_x = dpsi, d2psi_x = sg * d2psi;
+    const double h = c0 - x + psi_x;
+    if (h > 0) xlo = x; else xhi = x;
+    if (h == 0) break;
+    const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi_x));
+    int done = 0;
+    const double xn = rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 1, xlo, xhi, it, prev_step, &done);
+    prev_step = fabs(xn - x);
+    x = xn;
+    if (done) { ++it; break; }
+  }
+  if (iters) *iters = it;
+  return sg * x;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,7 +468,7 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
 
 template <int KIND, int G>
 __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double s, int ln, int* zero,
-                                               int* iters) {
+                                               int* iters, int method) {
   const int m = P.m;
   dd fs = {0.0, 0.0};
   double usum = 0.0, dmx = -INFINITY, dmn = INFINITY;
@@ -284,8 +476,8 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
     const dd e = dd_add_d(pdiff_dd<KIND>(P.ds[j], pv), -s);
     fs = dd_add(fs, dd_div(dd{P.ch[j], P.cl[j]}, e));
     const double eh = e.hi;
-    const double Dj = 1.0 / eh;
-    usum += P.ch[j] / (eh * eh);
+    const double Dj = recip(eh);
+    usum += P.ch[j] * Dj * Dj;
     dmx = fmax(dmx, Dj);
     dmn = fmin(dmn, Dj);
   }
@@ -303,13 +495,46 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
   double lo, hi;
   if (rho > 0) { lo = fmax(dmx, 0.0); hi = lo + rho * u2; }
   else { hi = fmin(dmn, 0.0); lo = hi + rho * u2; }
-  double mid = 0.5 * (lo + hi);
   int it = 0;
+  if (method == ROOT_RATIONAL) {
+    // phi(nu) = 1 - rho psi(nu), psi(nu) = sum_j c_j/(e_j (nu e_j - 1)) + 1/nu;
+    // in x = sign(rho) nu:  h(x) = psi_x(x) - 1/|rho|, psi_x = sign(rho) psi
+    const double sg = rho > 0 ? 1.0 : -1.0;
+    double xlo = (rho > 0) ? lo : -hi;
+    double xhi = (rho > 0) ? hi : -lo;
+    const double y = (rho > 0) ? lo : -hi;
+    const double c0 = -1.0 / fabs(rho);
+    double x = xhi;
+    double prev_step = INFINITY;
+    for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
+      const double nu = sg * x;
+      double s1, s2, s3;
+      psi_pass<KIND, G>(P, pv, s, -1, nu, ln, s1, s2, s3);
+      const double rnu = 1.0 / nu;
+      const double psi_x = sg * (s1 + rnu);
+      const double dpsi_x = -(s2 + rnu * rnu);
+      const double d2psi_x = sg * 2.0 * (s3 + rnu * rnu * rnu);
+      const double h = c0 + psi_x;
+      if (h > 0) xlo = x; else xhi = x;
+      if (h == 0) break;
+      const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(psi_x));
+      int done = 0;
+      const double xn =
+          rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 0, xlo, xhi, it, prev_step, &done);
+      prev_step = fabs(xn - x);
+      x = xn;
+      if (done) { ++it; break; }
+    }
+    *iters = it;
+    return 1.0 / (sg * x);
+  }
+  double mid = 0.5 * (lo + hi);
   while ((hi - lo) / fabs(mid) > 2.0 * EPS && it < MAX_BISECT) {
     double S = 0.0;
+#pragma unroll 4
     for (int j = ln; j < m; j += G) {
       const double e = pdiff<KIND>(P.ds[j], pv) - s;
-      S += P.ch[j] / (e * fma(-mid, e, 1.0));
+      S += P.ch[j] * recip(e * fma(-mid, e, 1.0));
     }
     S = gsum<G>(S);
     const double phi = 1.0 + rho * (S - 1.0 / mid);
@@ -364,15 +589,17 @@ template <int KIND, int G>
 __host__ __device__ inline double inv_norm(const Prob& P, double pv, double s, double mu, int ln) {
   double acc = 0.0;
   if constexpr (KIND == KIND_DPR1) {
+#pragma unroll 4
     for (int j = ln; j < P.nsorted; j += G) {
-      const double x = P.zs[j] / (((P.ds[j] - pv) - s) - mu);
+      const double x = P.zs[j] * recip(((P.ds[j] - pv) - s) - mu);
       acc = fma(x, x, acc);
     }
     acc = gsum<G>(acc);
   } else {
+#pragma unroll 4
     for (int j = ln; j < P.m; j += G) {
-      const double den = (pdiff<KIND>(P.ds[j], pv) - s) - mu;
-      acc += P.ch[j] / (den * den);
+      const double r = recip((pdiff<KIND>(P.ds[j], pv) - s) - mu);
+      acc = fma(P.ch[j] * r, r, acc);
     }
     acc = gsum<G>(acc) + 1.0;
   }

@@ -32,7 +32,7 @@ def _load():
         L = ctypes.CDLL(build())
         P = ctypes.c_void_p
         L.emu_solve.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_double, P, P, P, P, P, P,
-                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P]
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
         L.emu_solve.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -42,7 +42,7 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1):
+def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1):
     """kind 0 arrowhead, 1 DPR1, 2 SVD.  Returns dict of numpy arrays (V[:, k] = k-th vector)."""
     d = np.ascontiguousarray(d, dtype=np.float64)
     z = np.ascontiguousarray(z, dtype=np.float64)
@@ -52,7 +52,8 @@ def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0
     Ub = np.empty((n, n)) if (vectors and kind == 2) else None
     sh, mu, kb = np.empty(n), np.empty(n), np.empty(n)
     info = np.empty(n, dtype=np.uint32)
+    cnt = np.empty((n, 6), dtype=np.int32)
     _load().emu_solve(kind, n, _p(d), _p(z), float(scalar), _p(lam), _p(Vb), _p(Ub), _p(sh), _p(mu), _p(info),
-                      tau_nu, tau_zero, fp64_b, remedies, _p(kb))
+                      tau_nu, tau_zero, fp64_b, remedies, _p(kb), root, _p(cnt))
     return {"lam": lam, "V": None if Vb is None else Vb.T, "U": None if Ub is None else Ub.T,
-            "shift": sh, "mu": mu, "info": info, "kb": kb}
+            "shift": sh, "mu": mu, "info": info, "kb": kb, "cnt": cnt}

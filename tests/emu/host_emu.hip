@@ -64,7 +64,7 @@ static void run(ProbDesc D, const Options& opt, double* U) {
 
 extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, double scalar, double* lam,
                          double* V, double* U, double* shift, double* mu, uint32_t* info, double tau_nu,
-                         double tau_zero, int fp64_b, int remedies, double* kb) {
+                         double tau_zero, int fp64_b, int remedies, double* kb, int root, int32_t* cnt) {
   std::vector<double> ws(ws_doubles(n), 0.0);
   ProbDesc D{};
   D.kind = kind;
@@ -81,13 +81,17 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   D.mu = mu;
   D.info = info;
   D.ws = ws.data();
-  Options opt{tau_nu, tau_zero, fp64_b, remedies};
+  Options opt{tau_nu, tau_zero, fp64_b, remedies, root};
   if (kind == KIND_ARROW) run<KIND_ARROW>(D, opt, U);
   else if (kind == KIND_DPR1) run<KIND_DPR1>(D, opt, U);
   else run<KIND_SVD>(D, opt, U);
   if (kb) {
     const Ws w = ws_view(D.ws, D.n);
     for (int k = 0; k < D.n; ++k) kb[k] = w.kb1[k];
+  }
+  if (cnt) {
+    const Ws w = ws_view(D.ws, D.n);
+    for (int64_t k = 0; k < 6 * (int64_t)D.n; ++k) cnt[k] = w.cnt[k];
   }
   return 0;
 }

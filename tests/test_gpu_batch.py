@@ -1,0 +1,146 @@
+"""Batched plans (arrow_batch_*) and the sequential reference path against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1302_7203_amd import workloads as W
+from parity import assert_close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1302_7203_amd import batch, binding
+    assert torch.cuda.is_available()
+    binding.lib()
+    return torch, batch, torch.device("cuda", 0)
+
+
+def _mixed(count, seed, nmin=16, nmax=300):
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        k = p % 3
+        out.append(W.uniform_arrow(n, rng) if k == 0 else W.dpr1(n, rng) if k == 1 else W.svd_arrow(n, rng))
+    # a graded problem and the edge orders
+    out.append(W.graded_arrow(200, rng, clusters=4, cluster_size=8))
+    out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
+    return out
+
+
+def _oracle(pr):
+    if pr.kind == W.KIND_ARROW:
+        r = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+        return r.lam, r.vec, None
+    if pr.kind == W.KIND_DPR1:
+        r = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+        return r.lam, r.vec, None
+    r = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+    return r.sigma, r.V, r.U
+
+
+def _check(b, problems, torch, idx=None):
+    torch.cuda.synchronize()
+    for p in (range(len(problems)) if idx is None else idx):
+        lam, V, U, info = b.result(p)
+        rl, rV, rU = _oracle(problems[p])
+        assert_close(lam.cpu().numpy(), rl, f"problem {p} values")
+        assert_close(V.cpu().numpy(), rV, f"problem {p} vectors")
+        if rU is not None:
+            assert_close(U.cpu().numpy(), rU, f"problem {p} left vectors")
+
+
+def test_batched_plan_matches_oracle(env, oracle_lib):
+    torch, batch, dev = env
+    probs = _mixed(45, 1)
+    b = batch.Batch(probs, device=dev)
+    b.run()
+    _check(b, probs, torch)
+    b.close()
+
+
+def test_sequential_path_matches_oracle(env, oracle_lib):
+    torch, batch, dev = env
+    probs = _mixed(20, 2)
+    b = batch.Batch(probs, device=dev)
+    b.run_sequential()
+    _check(b, probs, torch)
+    b.close()
+
+
+def test_alone_equals_in_the_mix_bitwise(env):
+    torch, batch, dev = env
+    probs = _mixed(30, 3)
+    mix = batch.Batch(probs, device=dev)
+    mix.run()
+    for p in (0, 7, 13, len(probs) - 5):
+        one = batch.Batch([probs[p]], device=dev)
+        one.run()
+        torch.cuda.synchronize()
+        a, b_ = mix.result(p), one.result(0)
+        assert torch.equal(a[0], b_[0]) and torch.equal(a[1], b_[1])
+        if a[2] is not None:
+            assert torch.equal(a[2], b_[2])
+        one.close()
+    mix.close()
+
+
+def test_graph_replays_equal_eager(env):
+    torch, batch, dev = env
+    probs = _mixed(25, 4)
+    eager = batch.Batch(probs, device=dev)
+    eager.run()
+    torch.cuda.synchronize()
+    ref = eager.out_pool.clone()
+    g = batch.Batch(probs, device=dev, graph=True)
+    for rep in range(3):
+        g.out_pool.fill_(float("nan"))          # eager work between replays
+        torch.cuda.synchronize()
+        g.run()
+        torch.cuda.synchronize()
+        assert torch.equal(g.out_pool, ref), f"replay {rep}"
+    g.close()
+    eager.close()
+
+
+def test_bad_problem_is_isolated(env, oracle_lib):
+    torch, batch, dev = env
+    probs = _mixed(6, 5)
+    bad = W.Problem(W.KIND_ARROW, 4, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+    probs.insert(3, bad)
+    b = batch.Batch(probs, device=dev)
+    b.run()
+    torch.cuda.synchronize()
+    lam, V, U, info = b.result(3)
+    assert bool((info.cpu() & 16).all()) and bool(torch.isnan(lam).all())
+    _check(b, probs, torch, idx=[p for p in range(len(probs)) if p != 3])
+    b.close()
+
+
+def test_invalid_descriptor_rejected(env):
+    torch, batch, dev = env
+    pr = W.uniform_arrow(5, np.random.default_rng(1))
+    pk = batch.pack([pr])
+    pk.descs[0].n = 0
+    with pytest.raises(Exception):
+        batch.Batch([pr], device=dev, packed=pk)
+
+
+def test_full_size_batch_sampled(env, oracle_lib):
+    """The 10,000-problem mixed batch (n log-uniform in [16, 1024]) in the plan the benchmark times."""
+    torch, batch, dev = env
+    probs = W.batch_mixed()
+    b = batch.Batch(probs, device=dev, graph=True)
+    b.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = sorted(set(int(i) for i in rng.integers(0, len(probs), 40)) | {0, 1, len(probs) - 1})
+    _check(b, probs, torch, idx=idx)
+    info = b.info_pool.cpu().numpy().astype(np.uint32)
+    assert not np.any(info & (16 | 32 | 256))
+    b.close()
+    del b
+    torch.cuda.empty_cache()

@@ -205,3 +205,36 @@ def test_svd(gpu, n, oracle_lib):
     assert_close(_np(out.lam), ref.sigma, "sigma")
     assert_close(_np(out.V), ref.V, "V")
     assert_close(_np(out.U), ref.U, "U")
+
+
+def test_bisection_method_matches_oracle(gpu, oracle_lib):
+    """Algorithm 3 (bisection) instead of the default rational iteration."""
+    torch, binding, _ = gpu
+    binding.set_option(binding.OPT_ROOT, binding.ROOT_BISECT)
+    try:
+        pr = W.single_uniform_512()
+        out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+        assert_close(_np(out.lam), ref.lam, "lambda (bisection)")
+        assert_close(_np(out.V), ref.vec, "V (bisection)")
+        pr = W.single_graded_4096()
+        out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+        ks = _sample_ks(pr.n, _np(out.info).astype(np.uint32), 32)
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+        assert_close(_np(out.lam)[ks], ref.lam, "lambda (bisection, graded)")
+        V = out.V[:, torch.from_numpy(ks).to(out.V.device)].cpu().numpy()
+        assert_close(V, ref.vec, "V (bisection, graded)")
+    finally:
+        binding.set_option(binding.OPT_ROOT, binding.ROOT_RATIONAL)
+
+
+def test_unsorted_large_input_matches_sorted(gpu):
+    """The rank sort over several comparison chunks gives the same bits as sorted input."""
+    pr = W.single_graded_4096()
+    base = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    sh = W.shuffled(pr, 11)
+    out = _arrow(gpu, sh.d, sh.z, sh.scalar)
+    assert np.array_equal(_np(out.lam), _np(base.lam))
+    perm = sh.meta["perm"]
+    Vb, Vo = _np(base.V), _np(out.V)
+    assert np.array_equal(Vo[:-1], Vb[perm]) and np.array_equal(Vo[-1], Vb[-1])
