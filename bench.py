@@ -104,6 +104,87 @@ def batched_leg(args, binding, workloads, dev):
     return res
 
 
+SERVE_DESC = ("Poisson stream, n = round(exp U(ln32, ln8192)); 60% arrowhead eigen (d~U(-1,1) min gap 1e-6, "
+              "z~U(0.1,1)), 25% DPR1 eigen (rho~U(0.1,10), u = g/|g|), 15% SVD of an upper-triangular arrowhead "
+              "(d~U(0,1), z~U(0.1,1)); all values + vectors; admission by an HBM budget")
+
+
+def serving_leg(args, dev):
+    """The serving loop: saturated capacity (batched, and one launch per request), then a
+    Poisson stream offered at a fixed fraction of that capacity, with p50/p99 latency.
+    Sampled requests of the offered-load run are checked against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_1302_7203_amd import serve, workloads
+
+    arr = workloads.serving_requests(count=args.serve_requests, nmin=32, nmax=8192, rate=1.0)
+    probs = [p for _, p in arr]
+    budget = int(args.serve_budget_gib * (1 << 30))
+    pairs = sum(p.n for p in probs)
+
+    rng = np.random.default_rng(5)
+    check_rids = set(int(i) for i in rng.choice(len(probs), 8, replace=False)) if not args.no_cpu_baseline else set()
+    got = {}
+
+    def grab(srv, r):
+        if r.rid in check_rids and r.arrival > 0.0:
+            lam, V, U, info = srv.result(r)
+            n = r.problem.n
+            ks = np.unique(np.linspace(0, n - 1, min(n, 16)).astype(np.int64))
+            kt = torch.from_numpy(ks).to(dev)
+            got[r.rid] = (ks, lam[kt].cpu().numpy(), V[:, kt].cpu().numpy(),
+                          None if U is None else U[:, kt].cpu().numpy())
+
+    srv = serve.Server(hbm_budget=budget, device=dev, streams=3, on_done=grab)
+    srv.run([(0.0, p) for p in probs[:200]])                     # warm-up
+    torch.cuda.synchronize(dev)
+    sat = serve.latency_stats(srv.run([(0.0, p) for p in probs]))
+    l0 = srv.launches
+    rate = args.serve_load * sat["solves_per_s"]
+    offered = srv.run([(t / rate, p) for t, p in arr])
+    st = serve.latency_stats(offered)
+    launches = srv.launches - l0
+    peak = srv.peak_used
+    srv.close()
+    del srv
+    torch.cuda.empty_cache()
+
+    one = serve.Server(hbm_budget=budget, device=dev, streams=1, max_batch=1)
+    one.run([(0.0, p) for p in probs[:16]])
+    per_solve = serve.latency_stats(one.run([(0.0, p) for p in probs]))
+    one.close()
+    del one
+    torch.cuda.empty_cache()
+
+    res = {"workload": SERVE_DESC, "requests": len(probs), "eigenpairs": pairs, "hbm_budget_gib": args.serve_budget_gib,
+           "saturated_batched": {k: sat[k] for k in ("solves_per_s", "eigenpairs_per_s", "wall_s")},
+           "saturated_per_solve_launch": {k: per_solve[k] for k in ("solves_per_s", "eigenpairs_per_s", "wall_s")},
+           "speedup_vs_per_solve": sat["eigenpairs_per_s"] / per_solve["eigenpairs_per_s"],
+           "offered_load": args.serve_load, "offered_solves_per_s": rate,
+           "achieved_solves_per_s": st["solves_per_s"], "achieved_eigenpairs_per_s": st["eigenpairs_per_s"],
+           "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+           "launches": launches, "mean_batch": len(probs) / max(1, launches), "peak_arena_gib": peak / (1 << 30)}
+    if got:
+        import oracle
+        worst_l = worst_v = 0.0
+        for rid, (ks, lam, V, U) in got.items():
+            pr = probs[rid]
+            if pr.kind == 2:
+                ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar, ks=ks)
+                rl, rV = ref.sigma, ref.V
+                worst_v = max(worst_v, float(np.max(np.abs(U - ref.U) / np.abs(ref.U))))
+            else:
+                ref = (oracle.arrow_eig if pr.kind == 0 else oracle.dpr1_eig)(pr.d, pr.z, pr.scalar, ks=ks)
+                rl, rV = ref.lam, ref.vec
+            worst_l = max(worst_l, float(np.max(np.abs(lam - rl) / np.abs(rl))))
+            worst_v = max(worst_v, float(np.max(np.abs(V - rV) / np.abs(rV))))
+        res["parity"] = {"sample_requests": len(got), "eigenpairs_each": "16 evenly spaced (all if n<16)",
+                         "max_rel_err_values": worst_l, "max_rel_err_vectors": worst_v,
+                         "pass": bool(worst_l <= 1e-13 and worst_v <= 1e-13)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +197,10 @@ def main():
                     help="root finder for the extreme eigenvalue of the shifted inverse")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs one-launch-per-solve leg")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -198,6 +283,8 @@ def main():
 
     if not args.no_batch:
         result["batched"] = batched_leg(args, binding, workloads, dev)
+    if not args.no_serve:
+        result["serving"] = serving_leg(args, dev)
 
     if not args.no_cpu_baseline:
         import oracle

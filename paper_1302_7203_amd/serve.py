@@ -1,0 +1,375 @@
+"""Serving loop: continuous batching of eigen/SVD solve requests on one GPU.
+
+Requests (arrowhead eigen, DPR1 eigen, triangular-arrowhead SVD) arrive over
+time.  The loop
+
+* admits them first-come first-served whenever their device bytes (inputs,
+  outputs, info words and solver workspace) fit in a fixed HBM budget -- one
+  arena allocated once, so the loop itself never allocates device memory;
+* packs everything admitted since the last launch into one batch plan
+  (arrow_batch_create with workspace carved from the arena) and launches it
+  on one of a few streams, so batches that arrive while others run overlap
+  with them on the device;
+* polls completion events, records each request's latency (arrival to results
+  resident on the device) and returns the arena space of finished requests.
+
+Each request's results are the same as if it were solved alone: a problem's
+kernels depend only on its own data and its order n (which fixes its lanes).
+"""
+from __future__ import annotations
+
+import bisect
+import ctypes
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import batch, binding
+from .workloads import KIND_DPR1, KIND_SVD, Problem
+
+ALIGN = 256
+
+
+class Arena:
+    """First-fit allocator over [0, capacity) with coalescing free list (byte offsets)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.free_list = [(0, self.capacity)]     # sorted (offset, size)
+        self.used = 0
+
+    def alloc(self, nbytes: int):
+        size = (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+        for idx, (off, sz) in enumerate(self.free_list):
+            if sz >= size:
+                if sz == size:
+                    del self.free_list[idx]
+                else:
+                    self.free_list[idx] = (off + size, sz - size)
+                self.used += size
+                return off, size
+        return None
+
+    def free(self, off: int, size: int):
+        self.used -= size
+        i = bisect.bisect_left(self.free_list, (off, 0))
+        self.free_list.insert(i, (off, size))
+        # coalesce with neighbours
+        if i + 1 < len(self.free_list) and self.free_list[i][0] + self.free_list[i][1] == self.free_list[i + 1][0]:
+            self.free_list[i] = (off, size + self.free_list[i + 1][1])
+            del self.free_list[i + 1]
+        if i > 0 and self.free_list[i - 1][0] + self.free_list[i - 1][1] == self.free_list[i][0]:
+            self.free_list[i - 1] = (self.free_list[i - 1][0], self.free_list[i - 1][1] + self.free_list[i][1])
+            del self.free_list[i]
+
+    def largest_free(self):
+        return max((sz for _, sz in self.free_list), default=0)
+
+
+def _ms(pr: Problem):
+    return pr.n if pr.kind == KIND_DPR1 else pr.n - 1
+
+
+def out_doubles(pr: Problem, vectors=True):
+    k = (2 if pr.kind == KIND_SVD else 1) if vectors else 0
+    return pr.n + k * pr.n * pr.n
+
+
+def _up(nbytes: int) -> int:
+    return (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+
+
+# Arena bytes a batch needs once, whatever its size: the plan's counter block and the
+# rounding of its descriptor, table, input and workspace chunks to ALIGN.
+BATCH_OVERHEAD = 6 * ALIGN
+
+
+def request_parts(pr: Problem, vectors=True):
+    """(outputs, info, rest): arena bytes of a request's results, of its info words, and of
+    its share of the batch's input chunk and plan workspace (inputs, solver workspace,
+    104-byte descriptor and three table words)."""
+    out = _up(8 * out_doubles(pr, vectors))
+    info = _up(4 * pr.n)
+    rest = 16 * _ms(pr) + _up(8 * (16 + 19 * pr.n)) + 128
+    return out, info, rest
+
+
+def request_bytes(pr: Problem, vectors=True):
+    """Device bytes one request holds while in flight."""
+    return sum(request_parts(pr, vectors))
+
+
+@dataclass
+class Request:
+    rid: int
+    problem: Problem
+    arrival: float                 # seconds on the loop's clock
+    admitted: float = -1.0
+    done: float = -1.0
+    out: tuple | None = None       # (offset, size) in the arena: values, vectors, left vectors
+    info: tuple | None = None
+    desc_fields: dict = field(default_factory=dict)
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class Scheduler:
+    """Admission policy (no device work): FIFO admission by byte budget, batches capped in size."""
+
+    def __init__(self, arena: Arena, max_batch=4096, vectors=True):
+        self.arena = arena
+        self.max_batch = max_batch
+        self.vectors = vectors
+        self.pending: deque[Request] = deque()
+
+    def submit(self, req: Request):
+        if request_bytes(req.problem, self.vectors) + BATCH_OVERHEAD > self.arena.capacity:
+            raise ValueError(f"request {req.rid} needs more than the whole HBM budget")
+        self.pending.append(req)
+
+    def admit(self, now: float) -> list[Request]:
+        """Requests admitted now, in arrival order, as one batch: stops at the first one
+        that does not fit.  Their results and info words are allocated here; room for the
+        batch's inputs and plan workspace is kept free for the launch that follows at once."""
+        out = []
+        reserve = BATCH_OVERHEAD
+        while self.pending and len(out) < self.max_batch:
+            req = self.pending[0]
+            out_b, info_b, rest = request_parts(req.problem, self.vectors)
+            if self.arena.capacity - self.arena.used - reserve < out_b + info_b + rest:
+                break
+            got = self.arena.alloc(out_b)
+            if got is None:
+                break
+            inf = self.arena.alloc(info_b)
+            if inf is None:
+                self.arena.free(*got)
+                break
+            req.out, req.info, req.admitted = got, inf, now
+            reserve += rest
+            out.append(self.pending.popleft())
+        return out
+
+    def release(self, req: Request):
+        self.arena.free(*req.out)
+        self.arena.free(*req.info)
+
+
+@dataclass
+class InFlight:
+    reqs: list
+    plan: "batch.Batch | None"
+    ws: tuple
+    event: object
+    stream: object
+    staging_slot: int
+
+
+class Server:
+    """Continuous batching of requests on one device within an HBM budget."""
+
+    def __init__(self, hbm_budget: int, device=None, streams=3, max_batch=4096, vectors=True,
+                 staging_bytes=64 << 20, on_done=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.arena = Arena(hbm_budget)
+        self.sched = Scheduler(self.arena, max_batch=max_batch, vectors=vectors)
+        self.vectors = vectors
+        self.buf = torch.empty(hbm_budget // 8, dtype=torch.float64, device=self.device)   # the arena
+        self.base = self.buf.data_ptr()
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.handles = []
+        L = batch.lib()
+        for s in self.streams:
+            h = ctypes.c_void_p()
+            binding._check(L.arrow_create(ctypes.byref(h), self.device.index or 0), "arrow_create")
+            binding._check(L.arrow_set_stream(h, ctypes.c_void_p(s.cuda_stream)), "arrow_set_stream")
+            self.handles.append(h)
+        self.staging = torch.empty(staging_bytes // 8 * streams, dtype=torch.float64).pin_memory()
+        self.slot_doubles = staging_bytes // 8
+        self.slot_busy = [None] * streams          # event of the last copy out of each staging slot
+        self.inflight: list[InFlight] = []
+        self.finished: list[Request] = []
+        self.next_stream = 0
+        self.peak_used = 0
+        self.launches = 0
+        # on_done(server, req) runs when req's results are complete on the device and
+        # before its arena space is returned; it may read server.result(req) synchronously.
+        self.on_done = on_done
+
+    # -- device bookkeeping -------------------------------------------------
+    def _free_stream(self):
+        busy = {f.staging_slot for f in self.inflight}
+        for k in range(len(self.streams)):
+            s = (self.next_stream + k) % len(self.streams)
+            if s not in busy:
+                self.next_stream = (s + 1) % len(self.streams)
+                return s
+        return None
+
+    def _launch(self, reqs: list[Request], now: float) -> bool:
+        s = self._free_stream()
+        if s is None:
+            return False
+        # inputs of the batch: one contiguous arena chunk, one H2D copy
+        ins = []
+        for r in reqs:
+            ins += [np.asarray(r.problem.d, dtype=np.float64), np.asarray(r.problem.z, dtype=np.float64)]
+        in_host = np.concatenate(ins) if ins else np.zeros(1)
+        if in_host.size > self.slot_doubles:
+            raise ValueError("batch inputs exceed the staging slot")
+        descs = (batch.ArrowDesc * len(reqs))()
+        ioff = 0
+        for q, r in enumerate(reqs):
+            pr, D = r.problem, descs[q]
+            ms = _ms(pr)
+            D.kind, D.n, D.scalar = pr.kind, pr.n, float(pr.scalar)
+            D.d_off, D.z_off = ioff, ioff + ms     # relative; shifted below
+            ioff += 2 * ms
+            o = r.out[0] // 8
+            D.lam_off = o
+            D.vec_off = o + pr.n if self.vectors else -1
+            D.left_off = o + pr.n + pr.n * pr.n if (self.vectors and pr.kind == KIND_SVD) else -1
+            D.info_off = r.info[0] // 4
+        in_chunk = self.arena.alloc(8 * max(1, in_host.size))
+        if in_chunk is None:
+            return False
+        for q in range(len(reqs)):
+            descs[q].d_off += in_chunk[0] // 8
+            descs[q].z_off += in_chunk[0] // 8
+        L = batch.lib()
+        ws_bytes = int(L.arrow_batch_workspace_size(len(reqs), ctypes.cast(descs, ctypes.c_void_p)))
+        ws = self.arena.alloc(ws_bytes)
+        if ws is None:
+            self.arena.free(*in_chunk)
+            return False
+        self.peak_used = max(self.peak_used, self.arena.used)
+        stream = self.streams[s]
+        if self.slot_busy[s] is not None:
+            self.slot_busy[s].synchronize()
+        slot = self.staging[s * self.slot_doubles: s * self.slot_doubles + in_host.size]
+        slot.numpy()[:] = in_host
+        with torch.cuda.stream(stream):
+            self.buf[in_chunk[0] // 8: in_chunk[0] // 8 + in_host.size].copy_(slot, non_blocking=True)
+            copied = torch.cuda.Event()
+            copied.record(stream)
+            self.slot_busy[s] = copied
+            plan = ctypes.c_void_p()
+            rc = L.arrow_batch_create(self.handles[s], len(reqs), ctypes.cast(descs, ctypes.c_void_p),
+                                      ctypes.c_void_p(self.base), ctypes.c_void_p(self.base),
+                                      ctypes.c_void_p(self.base), ctypes.c_void_p(self.base + ws[0]), ws[1], 0,
+                                      ctypes.byref(plan))
+            binding._check(rc, "arrow_batch_create")
+            binding._check(L.arrow_batch_run(plan), "arrow_batch_run")
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        self.inflight.append(InFlight(reqs, plan, (in_chunk, ws), ev, stream, s))
+        self.launches += 1
+        return True
+
+    def _poll(self, now_fn, keep_results):
+        still = []
+        for f in self.inflight:
+            if f.event.query():
+                t = now_fn()
+                binding._check(batch.lib().arrow_batch_destroy(f.plan), "arrow_batch_destroy")
+                self.arena.free(*f.ws[0])
+                self.arena.free(*f.ws[1])
+                for r in f.reqs:
+                    r.done = t
+                    self.finished.append(r)
+                    if self.on_done is not None:
+                        self.on_done(self, r)
+                    if not keep_results:
+                        self.sched.release(r)
+            else:
+                still.append(f)
+        self.inflight = still
+
+    def release(self, req: Request):
+        """The client is done with req's results: return its arena space."""
+        self.sched.release(req)
+
+    def result(self, req: Request):
+        pr, n = req.problem, req.problem.n
+        o = req.out[0] // 8
+        lam = self.buf[o:o + n]
+        V = self.buf[o + n:o + n + n * n].view(n, n).t() if self.vectors else None
+        U = (self.buf[o + n + n * n:o + n + 2 * n * n].view(n, n).t()
+             if (self.vectors and pr.kind == KIND_SVD) else None)
+        info = self.buf.view(torch.int32)[req.info[0] // 4: req.info[0] // 4 + n]
+        return lam, V, U, info
+
+    # -- the loop -------------------------------------------------------------
+    def _try_launch(self, adm: list[Request], now: float) -> list[Request]:
+        """Launch adm (splitting it when the arena is too fragmented); returns what could not go."""
+        if self._launch(adm, now):
+            return []
+        if len(adm) > 1 and not self.inflight:
+            half = len(adm) // 2
+            rest = self._try_launch(adm[:half], now)
+            return rest + adm[half:]
+        if not self.inflight:
+            raise RuntimeError("a single request does not fit the HBM budget next to its workspace")
+        return adm
+
+    def run(self, arrivals: list[tuple[float, Problem]], keep_results=False, progress=None):
+        """Serve requests arriving at the given times (seconds from start); returns them, finished."""
+        reqs = [Request(i, pr, t) for i, (t, pr) in enumerate(arrivals)]
+        for r in reqs:
+            if request_bytes(r.problem, self.vectors) + BATCH_OVERHEAD > self.arena.capacity:
+                raise ValueError(f"request {r.rid} exceeds the HBM budget")
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0   # noqa: E731
+        nxt = 0
+        reported = 0
+        while nxt < len(reqs) or self.sched.pending or self.inflight:
+            t = now()
+            while nxt < len(reqs) and reqs[nxt].arrival <= t:
+                self.sched.submit(reqs[nxt])
+                nxt += 1
+            if self.sched.pending and self._free_stream() is not None:
+                adm = self.sched.admit(t)
+                if adm:
+                    back = self._try_launch(adm, t)
+                    for r in reversed(back):
+                        self.sched.release(r)
+                        r.admitted = -1.0
+                        self.sched.pending.appendleft(r)
+                elif not self.inflight:
+                    # nothing runs that could free space: only kept results hold the arena
+                    raise RuntimeError(f"request {self.sched.pending[0].rid} cannot be admitted: the HBM budget "
+                                       f"is held by results that were kept and not released")
+            self._poll(now, keep_results)
+            if progress and len(self.finished) - reported >= 500:
+                reported = len(self.finished)
+                progress(reported)
+            if not self.inflight and not self.sched.pending and nxt < len(reqs):
+                wait = reqs[nxt].arrival - now()
+                if wait > 0:
+                    time.sleep(min(wait, 0.001))
+        return reqs
+
+    def close(self):
+        for f in self.inflight:
+            f.event.synchronize()
+        self._poll(lambda: 0.0, True)
+        L = batch.lib()
+        for h in self.handles:
+            L.arrow_destroy(h)
+        self.handles = []
+        self.buf = None          # the arena goes back to torch's caching allocator
+
+
+def latency_stats(reqs: list[Request]):
+    lat = np.array([r.latency for r in reqs])
+    t_end = max(r.done for r in reqs)
+    t_start = min(r.arrival for r in reqs)
+    pairs = sum(r.problem.n for r in reqs)
+    return {"requests": len(reqs), "wall_s": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+            "eigenpairs_per_s": pairs / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
