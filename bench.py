@@ -52,6 +52,52 @@ WORKLOADS = {
 }
 
 
+def measured_peaks(binding, dev):
+    """What the device sustains: FP64 FMA issue (arrow_probe_fma), 16-byte streaming stores
+    (arrow_probe_fill, 2 GiB) and a plain copy (arrow_probe_copy, 1 GiB each way), each the best
+    of 5 launches timed with HIP events on torch's current stream."""
+    import ctypes
+
+    import torch
+
+    L = binding.lib()
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+
+    def best(fn, reps=5):
+        fn()
+        t = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            t.append(a.elapsed_time(b) * 1e-3)
+        return min(t)
+
+    blocks, iters = cus * 32, 4096
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=dev)
+    t_fma = best(lambda: binding._check(L.arrow_probe_fma(ctypes.c_void_p(out.data_ptr()), blocks, iters, st),
+                                        "arrow_probe_fma"))
+    fill_bytes = 2 << 30
+    buf = torch.empty(fill_bytes // 8, dtype=torch.float64, device=dev)
+    t_fill = best(lambda: binding._check(L.arrow_probe_fill(ctypes.c_void_p(buf.data_ptr()), fill_bytes, 1.0, st),
+                                         "arrow_probe_fill"))
+    half = fill_bytes // 2
+    src, dst = buf[: half // 8], buf[half // 8:]
+    t_copy = best(lambda: binding._check(L.arrow_probe_copy(ctypes.c_void_p(dst.data_ptr()),
+                                                            ctypes.c_void_p(src.data_ptr()), half, st),
+                                         "arrow_probe_copy"))
+    del out, buf, src, dst
+    torch.cuda.empty_cache()
+    return {"fp64_fma_tflops": blocks * 256 * iters * 16 / t_fma / 1e12,
+            "store_gbs": fill_bytes / t_fill / 1e9,
+            "copy_gbs": 2 * half / t_copy / 1e9,
+            "how": "arrow_probe_fma (8 FMA chains/lane), arrow_probe_fill (2 GiB, 16-B non-temporal stores), "
+                   "arrow_probe_copy (1 GiB read + 1 GiB write); best of 5, HIP events"}
+
+
 def batched_leg(args, binding, workloads, dev):
     """10,000 independent problems (n log-uniform in [16, 1024]; half arrowhead, half DPR1) in one
     hipGraph-captured plan, against the same problems solved one launch sequence each."""
@@ -281,6 +327,10 @@ def main():
     result["info_counts"] = {name: int(np.sum((info & bit) != 0)) for name, bit in
                              (("dd_b", 1), ("remedy_a", 2), ("remedy_b", 4), ("near_zero", 8), ("not_solved", 304))}
 
+    peaks = measured_peaks(binding, dev)
+    result["measured_peaks"] = peaks
+    roof["frac_of_measured"] = roof["achieved"] / peaks["fp64_fma_tflops"]
+    roof_v["frac_of_measured"] = roof_v["achieved"] / peaks["store_gbs"]
     if not args.no_batch:
         result["batched"] = batched_leg(args, binding, workloads, dev)
     if not args.no_serve:

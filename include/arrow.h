@@ -186,11 +186,28 @@ int arrow_solve_batched(arrow_handle_t h, int64_t count, const arrow_desc_t* des
                         double* out_pool, uint32_t* info_pool);
 
 /*
- * Batched schedule: lanes of a wavefront per eigenvalue (4, 8, 16, 32 or 64)
- * for problems of order n <= n_max[e] (first matching entry, n_max strictly
- * increasing, at most 16 entries; larger n use 64).  Filled by the autotuner.
+ * Schedule: how many lanes of a 64-lane wavefront cooperate on one eigenvalue
+ * (64: a wavefront per eigenvalue; fewer: 64/lanes eigenvalues share one
+ * wavefront and its loads of the pole data) for problems of order
+ * n <= n_max[e] (first matching entry; n_max strictly increasing, >= 1; at
+ * most 16 entries).  Results differ between lane counts only in rounding.
+ *
+ *   scope ARROW_SCHEDULE_SINGLE: arrow_eig / dpr1_eig / arrow_svd calls;
+ *     lanes 1, 2, 4, ..., 64.  n beyond the table and entries = 0 use the
+ *     built-in rule (about 8 pole terms per lane, at most 64 lanes).  The
+ *     option ARROW_OPT_LANES, when nonzero, overrides the table.
+ *   scope ARROW_SCHEDULE_BATCH: plans created afterwards; lanes 4, ..., 64;
+ *     n beyond the table uses 64; entries = 0 restores the built-in table
+ *     {24: 4, 48: 8, 96: 16, 192: 32, larger: 64}.
+ *
+ * The package's autotuner measures these tables on the device and the Python
+ * binding loads its result into every handle it creates.
+ * Returns 0, or -1 bad handle, -2 bad scope, -3 bad entries, -4 bad n_max,
+ * -5 bad lanes (the handle is unchanged on error).
  */
-int arrow_set_lanes_table(arrow_handle_t h, int32_t entries, const int32_t* n_max, const int32_t* lanes);
+#define ARROW_SCHEDULE_SINGLE 0
+#define ARROW_SCHEDULE_BATCH 1
+int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const int32_t* n_max, const int32_t* lanes);
 
 /*
  * Diagnostics of the most recent single-problem call on this handle.
@@ -208,6 +225,28 @@ int arrow_set_lanes_table(arrow_handle_t h, int32_t entries, const int32_t* n_ma
  */
 int arrow_last_timing(arrow_handle_t h, double* ms);
 int arrow_last_counters(arrow_handle_t h, int64_t* out);
+
+/*
+ * Calibration kernels (not part of the solve): the rates the device sustains
+ * for the resources the solver is bound by, measured by the caller around
+ * these asynchronous launches on `stream` (a hipStream_t passed as void*).
+ *
+ * arrow_probe_fma:  blocks x 256 threads, each running 8 independent chains of
+ *   `iters` dependent FP64 FMAs (16 * iters FP64 flops per thread); writes one
+ *   double per thread to out[0 .. blocks*256) (device memory, caller-owned).
+ *   Returns -1 out null, -2 blocks outside [1, 2^24], -3 iters < 1.
+ * arrow_probe_fill: streams `bytes` (a positive multiple of 16) of copies of
+ *   `value` to dst (16-byte aligned device memory) with 16-byte non-temporal
+ *   stores.  Returns -1 bad dst, -2 bad bytes.
+ * arrow_probe_copy: copies `bytes` (a positive multiple of 16) from src to dst
+ *   (16-byte aligned, not overlapping) with 16-byte loads and stores: a plain
+ *   copy of known size, to scale hardware traffic counters.  Returns -1 bad
+ *   dst, -2 bad src, -3 bad bytes.
+ * All return ARROW_ERR_HIP if the launch fails.
+ */
+int arrow_probe_fma(double* out, int64_t blocks, int iters, void* stream);
+int arrow_probe_fill(double* dst, int64_t bytes, double value, void* stream);
+int arrow_probe_copy(double* dst, const double* src, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -38,9 +38,8 @@ def _setup(L):
     L.arrow_batch_destroy.argtypes = [P]
     L.arrow_solve_batched.argtypes = [P, I64, P, P, P, P]
     L.arrow_solve_sequential.argtypes = [P, I64, P, P, P, P]
-    L.arrow_set_lanes_table.argtypes = [P, ctypes.c_int32, P, P]
     for f in ("arrow_batch_create", "arrow_batch_run", "arrow_batch_destroy", "arrow_solve_batched",
-              "arrow_solve_sequential", "arrow_set_lanes_table"):
+              "arrow_solve_sequential"):
         getattr(L, f).restype = I
     L._batch_ready = True
     return L
@@ -51,9 +50,8 @@ def lib():
 
 
 def set_lanes_table(n_max, lanes, device=None):
-    a = (ctypes.c_int32 * len(n_max))(*[int(x) for x in n_max])
-    b = (ctypes.c_int32 * len(lanes))(*[int(x) for x in lanes])
-    binding._check(lib().arrow_set_lanes_table(binding.handle(device), len(n_max), a, b), "arrow_set_lanes_table")
+    """Batched schedule of the default handle: lanes per eigenvalue for n <= n_max[e]."""
+    binding.set_lanes_table(binding.SCHEDULE_BATCH, n_max, lanes, device=device)
 
 
 def sorted_len(kind, n):

@@ -7,6 +7,7 @@ There is no fallback: if the library is missing the calls raise.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 import threading
 from dataclasses import dataclass
@@ -15,6 +16,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libarrow.so")
+# lanes-per-eigenvalue tables measured by the autotuner (paper_1302_7203_amd.autotune)
+TUNED_PATH = os.path.join(_HERE, "tuned", "schedule_gfx950.json")
 
 INFO_DD_B = 1
 INFO_REMEDY_A = 2
@@ -36,6 +39,9 @@ OPT_TIMING = 6
 OPT_ROOT = 7
 ROOT_BISECT = 0
 ROOT_RATIONAL = 1
+SCHEDULE_SINGLE = 0
+SCHEDULE_BATCH = 1
+INT32_MAX = 2147483647
 
 
 class ArrowError(RuntimeError):
@@ -68,8 +74,14 @@ def lib():
                 L.arrow_svd.argtypes = [P, I64, P, P, D, P, P, I64, P, I64, P]
                 L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
                 L.arrow_last_counters.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
-                for f in ("arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
-                          "arrow_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing", "arrow_last_counters"):
+                L.arrow_set_lanes_table.argtypes = [P, I, ctypes.c_int32, P, P]
+                L.arrow_probe_fma.argtypes = [P, I64, I, P]
+                L.arrow_probe_fill.argtypes = [P, I64, D, P]
+                L.arrow_probe_copy.argtypes = [P, P, I64, P]
+                for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy",
+                          "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
+                          "arrow_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing", "arrow_last_counters",
+                          "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
                 _lib = L
     return _lib
@@ -80,14 +92,52 @@ def _check(rc, what):
         raise ArrowError(f"{what} returned {rc}")
 
 
+def read_tuned(path: str = TUNED_PATH) -> dict | None:
+    """The autotuner's tables {"single": (n_max, lanes), "batch": (n_max, lanes)}, validated;
+    None when the file does not exist."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    out = {}
+    for scope, gmin in (("single", 1), ("batch", 4)):
+        t = doc[scope]
+        n_max, lanes = [int(x) for x in t["n_max"]], [int(x) for x in t["lanes"]]
+        if not (1 <= len(n_max) == len(lanes) <= 16):
+            raise ArrowError(f"{path}: {scope} table has a bad length")
+        if any(b <= a for a, b in zip(n_max, n_max[1:])) or n_max[0] < 1 or n_max[-1] > INT32_MAX:
+            raise ArrowError(f"{path}: {scope} n_max must increase strictly within [1, 2^31-1]")
+        if any(g < gmin or g > 64 or g & (g - 1) for g in lanes):
+            raise ArrowError(f"{path}: {scope} lanes must be powers of two in [{gmin}, 64]")
+        out[scope] = (n_max, lanes)
+    return out
+
+
+def set_lanes_table(scope: int, n_max, lanes, h: ctypes.c_void_p | None = None, device=None):
+    """Install a lanes-per-eigenvalue table (arrow_set_lanes_table); empty lists restore the default."""
+    h = handle(device) if h is None else h
+    a = (ctypes.c_int32 * max(1, len(n_max)))(*[int(x) for x in n_max])
+    b = (ctypes.c_int32 * max(1, len(lanes)))(*[int(x) for x in lanes])
+    _check(lib().arrow_set_lanes_table(h, scope, len(n_max), a, b), "arrow_set_lanes_table")
+
+
+def apply_tuned(h: ctypes.c_void_p, path: str = TUNED_PATH):
+    """Load the autotuned tables, if any, into handle h."""
+    t = read_tuned(path)
+    if t is not None:
+        set_lanes_table(SCHEDULE_SINGLE, *t["single"], h=h)
+        set_lanes_table(SCHEDULE_BATCH, *t["batch"], h=h)
+
+
 def handle(device: int | torch.device | None = None) -> ctypes.c_void_p:
-    """The per-device default handle (created on first use)."""
+    """The per-device default handle (created on first use, with the autotuned schedule)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     idx = dev.index if dev.index is not None else torch.cuda.current_device()
     if idx not in _handles:
         h = ctypes.c_void_p()
         _check(lib().arrow_create(ctypes.byref(h), idx), "arrow_create")
         _handles[idx] = h
+        apply_tuned(h)
     return _handles[idx]
 
 

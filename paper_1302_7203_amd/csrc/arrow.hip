@@ -249,7 +249,7 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   mark(1);
   hipLaunchKernelGGL(k_prologue<KIND>, dim3(1), dim3(BLOCK), 0, st, D);
   mark(2);
-  const int G = h->lanes ? h->lanes : auto_lanes(D.n);
+  const int G = single_lanes(h, D.n);
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
   const size_t lds = (hot <= h->lds_max) ? hot : 0;
   launch_rc_any<KIND>(G, D, h->opt, st, false, lds);
@@ -295,13 +295,8 @@ int arrow_create(arrow_handle_t* h, int device) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) v = 0;
     p->cus = v > 0 ? v : 1;
   }
-  // default batched schedule: lanes per eigenvalue by order n
-  {
-    const int32_t tn[] = {24, 48, 96, 192, 2147483647};
-    const int32_t tg[] = {4, 8, 16, 32, 64};
-    p->ntab = 5;
-    for (int e = 0; e < 5; ++e) { p->tab_n[e] = tn[e]; p->tab_g[e] = tg[e]; }
-  }
+  p->ntab[ARROW_SCHEDULE_SINGLE] = 0;
+  default_batch_table(p);
   p->magic = HANDLE_MAGIC;
   *h = p;
   return ARROW_OK;

@@ -205,20 +205,27 @@ size_t arrow_batch_workspace_size(int64_t count, const arrow_desc_t* descs) {
   return plan_layout(count, descs).total;
 }
 
-int arrow_set_lanes_table(arrow_handle_t h, int32_t entries, const int32_t* n_max, const int32_t* lanes) {
+int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const int32_t* n_max, const int32_t* lanes) {
   if (!valid(h)) return -1;
-  if (entries < 1 || entries > LANE_TABLE_MAX) return -2;
-  if (!n_max) return -3;
-  if (!lanes) return -4;
+  if (scope != ARROW_SCHEDULE_SINGLE && scope != ARROW_SCHEDULE_BATCH) return -2;
+  if (entries < 0 || entries > LANE_TABLE_MAX) return -3;
+  if (entries == 0) {
+    if (scope == ARROW_SCHEDULE_BATCH) default_batch_table(h);
+    else h->ntab[scope] = 0;
+    return ARROW_OK;
+  }
+  if (!n_max) return -4;
+  if (!lanes) return -5;
+  const int gmin = scope == ARROW_SCHEDULE_BATCH ? 4 : 1;
   for (int e = 0; e < entries; ++e) {
     const int g = lanes[e];
-    if (g != 4 && g != 8 && g != 16 && g != 32 && g != 64) return -4;
-    if (e > 0 && n_max[e] <= n_max[e - 1]) return -3;
+    if (g < gmin || g > 64 || (g & (g - 1)) != 0) return -5;
+    if (n_max[e] < 1 || (e > 0 && n_max[e] <= n_max[e - 1])) return -4;
   }
-  h->ntab = entries;
+  h->ntab[scope] = entries;
   for (int e = 0; e < entries; ++e) {
-    h->tab_n[e] = n_max[e];
-    h->tab_g[e] = lanes[e];
+    h->tab_n[scope][e] = n_max[e];
+    h->tab_g[scope][e] = lanes[e];
   }
   return ARROW_OK;
 }
@@ -285,7 +292,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     D.ws = (double*)(base + wsoff);
     wsoff += align_up(ws_doubles(a.n) * sizeof(double), 256);
     b->descs[(size_t)q] = D;
-    const int G = table_lanes(h, a.n);
+    const int G = batch_lanes(h, a.n);
     lanes[q] = G;
     item_start[q] = (int32_t)items;
     items += (a.n + (WAVE / G) - 1) / (WAVE / G);

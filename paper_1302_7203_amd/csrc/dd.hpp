@@ -83,16 +83,17 @@ __host__ __device__ inline dd dd_div(dd a, dd b) {
 
 __host__ __device__ inline double dd_to_d(dd a) { return a.hi + a.lo; }
 
-// c / e with two quotient digits: q1 = c.hi/e.hi, then the remainder
-// c - q1 e (its leading part c.hi - q1 e.hi is exact through TwoProd) divided
-// once more.  Relative error a few units of 2^-104 -- enough where quotients
-// of one sign are summed, which is the only use.
-__host__ __device__ inline dd dd_div2(dd c, dd e) {
-  const double q1 = c.hi / e.hi;
+// c / e with two quotient digits, given r ~ 1/e.hi to about one ulp:
+// q1 = c.hi r, then the remainder c - q1 e (its leading part c.hi - q1 e.hi is
+// exact through TwoProd) times r once more.  q1 need not be the rounded
+// quotient: the remainder carries its error exactly, so the pair is good to a
+// few units of 2^-104 -- enough where quotients of one sign are summed, which
+// is the only use.
+__host__ __device__ inline dd dd_div2(dd c, dd e, double r) {
+  const double q1 = c.hi * r;
   const dd p = two_prod(q1, e.hi);
-  const double r = (((c.hi - p.hi) - p.lo) + c.lo) - q1 * e.lo;
-  const double q2 = r / e.hi;
-  return fast_two_sum(q1, q2);
+  const double rem = (((c.hi - p.hi) - p.lo) + c.lo) - q1 * e.lo;
+  return fast_two_sum(q1, rem * r);
 }
 
 // s += q for a running sum of terms of one sign: the error of every leading

@@ -24,9 +24,11 @@ struct arrow_handle_s {
   int64_t last_n;
   size_t lds_max;     // bytes of dynamic LDS one block may use
   int cus;            // compute units of the device
-  int ntab;           // batched schedule: lanes per eigenvalue by order n
-  int32_t tab_n[LANE_TABLE_MAX];
-  int32_t tab_g[LANE_TABLE_MAX];
+  // lanes per eigenvalue by order n: [ARROW_SCHEDULE_SINGLE] for single
+  // problems (empty: the built-in rule), [ARROW_SCHEDULE_BATCH] inside batches
+  int ntab[2];
+  int32_t tab_n[2][LANE_TABLE_MAX];
+  int32_t tab_g[2][LANE_TABLE_MAX];
   uint32_t magic;
 };
 
@@ -61,20 +63,36 @@ static inline int ensure_ws(arrow_handle_t h, size_t doubles) {
   return ARROW_OK;
 }
 
-// lanes per eigenvalue for a single problem: about 8 pole terms per lane
-static inline int auto_lanes(int64_t n) {
-  int64_t want = n / 8;
+static inline int table_lookup(const arrow_handle_s* h, int scope, int64_t n, int fallback) {
+  for (int e = 0; e < h->ntab[scope]; ++e)
+    if (n <= h->tab_n[scope][e]) return h->tab_g[scope][e];
+  return fallback;
+}
+
+// lanes per eigenvalue for a single problem: a fixed option, else the tuned
+// table, else about 8 pole terms per lane
+static inline int single_lanes(const arrow_handle_s* h, int64_t n) {
+  if (h->lanes) return h->lanes;
   int g = 1;
-  while (g < 64 && g < want) g <<= 1;
-  return g;
+  while (g < 64 && g < n / 8) g <<= 1;
+  return table_lookup(h, ARROW_SCHEDULE_SINGLE, n, g);
 }
 
 // all launches of one single-problem solve (defined with the single-problem kernels)
 int launch_single(arrow_handle_t h, const ahd::ProbDesc& D);
 
 // lanes per eigenvalue for a problem of order n inside a batch
-static inline int table_lanes(const arrow_handle_s* h, int64_t n) {
-  for (int e = 0; e < h->ntab; ++e)
-    if (n <= h->tab_n[e]) return h->tab_g[e];
-  return 64;
+static inline int batch_lanes(const arrow_handle_s* h, int64_t n) {
+  return table_lookup(h, ARROW_SCHEDULE_BATCH, n, 64);
+}
+
+// the built-in batched table
+static inline void default_batch_table(arrow_handle_s* h) {
+  static const int32_t tn[5] = {24, 48, 96, 192, 2147483647};
+  static const int32_t tg[5] = {4, 8, 16, 32, 64};
+  h->ntab[ARROW_SCHEDULE_BATCH] = 5;
+  for (int e = 0; e < 5; ++e) {
+    h->tab_n[ARROW_SCHEDULE_BATCH][e] = tn[e];
+    h->tab_g[ARROW_SCHEDULE_BATCH][e] = tg[e];
+  }
 }

@@ -174,6 +174,22 @@ __host__ __device__ inline dd gsum_dd(dd v) {
 }
 
 // ---------------------------------------------------------------------------
+// Lane ln's pole indices j = ln, ln + G, ... below m, visited as two runs: the
+// indices below `excl` (f(j, false)) and those above it (f(j, true)); excl
+// itself is skipped.  With excl outside [0, m) there is one run.  Splitting
+// the loop at the excluded pole keeps every iteration free of a per-term test.
+template <int G, class F>
+__host__ __device__ inline void for_terms(int ln, int m, int excl, F&& f) {
+  const int cut = (excl >= 0 && excl < m) ? excl : m;
+  int j = ln;
+#pragma unroll 4
+  for (; j < cut; j += G) f(j, false);
+  if (j == excl) j += G;
+#pragma unroll 4
+  for (; j < m; j += G) f(j, true);
+}
+
+// ---------------------------------------------------------------------------
 // Shift selection (Algorithm 1, first part): eigenvalue k (0-based, descending)
 // lies in (d_k, d_{k-1}); the sign of the Pick function (eq. Pick) at the
 // midpoint of that interval, evaluated in the frame shifted to d_k, tells
@@ -189,7 +205,7 @@ __host__ __device__ inline void select_shift(const Prob& P, int k, int ln, int& 
   const double mid = 0.5 * pdiff<KIND>(P.ds[k - 1], dk);
   double s = 0.0;
 #pragma unroll 4
-  for (int j = ln; j < m; j += G) s += P.ch[j] * recip(pdiff<KIND>(P.ds[j], dk) - mid);
+  for (int j = ln; j < m; j += G) s = fma(P.ch[j], recip(pdiff<KIND>(P.ds[j], dk) - mid), s);
   s = gsum<G>(s);
   const double a = dd_to_d(dd_sub(P.corner, pval_dd<KIND>(dk)));
   const double fmid = (a - mid) - s;
@@ -207,45 +223,41 @@ struct BPass {
   double b, Kb, lo, hi;
 };
 
-template <int KIND, int G>
-__host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, int fp64_b) {
+template <int KIND, int G, bool FP64_B>
+__host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln) {
   const int m = P.m;
   const double di = P.ds[i];
+  const double sg = (double)side;
   dd p1 = {0.0, 0.0}, p2 = {0.0, 0.0};  // sum over j < i (>= 0), j > i (<= 0)
   double f1 = 0.0, f2 = 0.0;            // the same sums in FP64
   double wsum = 0.0;                    // sum_{j != i} |shaft_j| / |e_j|
-  double dmx = -INFINITY, dmn = INFINITY, gmx = -INFINITY, gmn = INFINITY;
+  double dx = -INFINITY, gx = -INFINITY;  // max over j != i of side*delta_j and side*delta_j + |w_j|
   const double rzi = 1.0 / P.dz[i];
-#pragma unroll 2
-  for (int j = ln; j < m; j += G) {
-    if (j == i) continue;
+  for_terms<G>(ln, m, i, [&](int j, bool above) {
     const double ej = pdiff<KIND>(P.ds[j], di);
     const double rj = recip(ej);                    // delta_j, the diagonal of A_i^{-1}
     const double t = P.ch[j] * rj;
-    if (j < i) f1 += t; else f2 += t;
-    if (!fp64_b) {
-      const dd q = dd_div2(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di));
-      if (j < i) dd_acc(p1, q); else dd_acc(p2, q);
+    if (above) f2 += t; else f1 += t;
+    if constexpr (!FP64_B) {
+      const dd q = dd_div2(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
+      if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
     const double wj = P.dz[j] * fabs(rj);           // |w_j| |zeta_i|
     wsum += wj;
-    dmx = fmax(dmx, rj);
-    dmn = fmin(dmn, rj);
-    gmx = fmax(gmx, rj + wj * rzi);
-    gmn = fmin(gmn, rj - wj * rzi);
-  }
+    const double srj = sg * rj;
+    dx = fmax(dx, srj);
+    gx = fmax(gx, fma(wj, rzi, srj));
+  });
   f1 = gsum<G>(f1);
   f2 = gsum<G>(f2);
   wsum = gsum<G>(wsum);
-  dmx = gmax<G>(dmx);
-  dmn = gmin<G>(dmn);
-  gmx = gmax<G>(gmx);
-  gmn = gmin<G>(gmn);
+  dx = gmax<G>(dx);
+  gx = gmax<G>(gx);
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
   const double ci = P.ch[i];
   BPass r;
   double num_abs;
-  if (fp64_b) {
+  if constexpr (FP64_B) {
     // Algorithm 2: b = (-a + sum_{j<i} + sum_{j>i}) / zeta_i^2, all in FP64
     r.b = ((-a.hi + f1) + f2) / ci;
     num_abs = fabs(r.b) * ci;
@@ -262,15 +274,21 @@ __host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, 
   r.Kb = (fabs(a.hi) + fabs(f1) + fabs(f2)) / num_abs;
   // Gershgorin discs of A_i^{-1}: rows j != i (centre delta_j, radius |w_j|),
   // row i (centre 0, radius 1/|zeta_i|), last row (centre b, radius ||w||_1).
+  // On the requested side, in the variable side*nu: the extreme eigenvalue
+  // lies right of every centre and left of every disc's far end.
   const double w1 = (wsum + 1.0) * rzi;
-  if (side > 0) {
-    r.lo = fmax(dmx, 0.0);
-    r.hi = fmax(fmax(gmx, rzi), r.b + w1);
-  } else {
-    r.hi = fmin(dmn, 0.0);
-    r.lo = fmin(fmin(gmn, -rzi), r.b - w1);
-  }
+  const double xl = fmax(dx, 0.0);
+  const double xh = fmax(fmax(gx, rzi), sg * r.b + w1);
+  if (side > 0) { r.lo = xl; r.hi = xh; }
+  else { r.lo = -xh; r.hi = -xl; }
   return r;
+}
+
+// the FP64-only variant is the negative control of Algorithm 2; the choice is
+// made once per call so that the term loop carries no branch
+template <int KIND, int G>
+__host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, int fp64_b) {
+  return fp64_b ? b_pass_t<KIND, G, true>(P, i, side, ln) : b_pass_t<KIND, G, false>(P, i, side, ln);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,12 +312,10 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
   int it = 0;
   while ((hi - lo) / fabs(mid) > 2.0 * EPS && it < MAX_BISECT) {
     double S = 0.0;
-#pragma unroll 4
-    for (int j = ln; j < m; j += G) {
+    for_terms<G>(ln, m, i, [&](int j, bool) {
       const double e = pdiff<KIND>(P.ds[j], di);
-      const double t = P.ch[j] * recip(e * fma(-mid, e, 1.0));
-      S += (j == i) ? 0.0 : t;
-    }
+      S = fma(P.ch[j], recip(e * fma(-mid, e, 1.0)), S);
+    });
     S = gsum<G>(S);
     const double g = (b - mid) - (S - 1.0 / mid) / ci;
     if (g > 0) lo = mid; else hi = mid;
@@ -326,23 +342,21 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
 
 // sums over j != excl of  c_j / (e_j (nu e_j - 1)),  c_j / (nu e_j - 1)^2  and
 // c_j e_j / (nu e_j - 1)^3, with e_j = pdiff(d_j, pv) - s (the pole terms of
-// psi and of its first two derivatives, up to constant factors)
-template <int KIND, int G>
+// psi and of its first two derivatives, up to constant factors); OFF = false
+// when the offset s is known to be zero.
+template <int KIND, int G, bool OFF>
 __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
                                          double& sum, double& dsum, double& d2sum) {
   double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll 4
-  for (int j = ln; j < P.m; j += G) {
-    const double e = pdiff<KIND>(P.ds[j], pv) - s;
+  for_terms<G>(ln, P.m, excl, [&](int j, bool) {
+    const double e = OFF ? pdiff<KIND>(P.ds[j], pv) - s : pdiff<KIND>(P.ds[j], pv);
     const double q = recip(e * fma(nu, e, -1.0));
-    const double t = P.ch[j] * q;
-    const double eq = e * q;               // 1 / (nu e - 1)
-    const double d1 = (t * e) * eq;
-    const double d2 = d1 * (e * eq);
-    a += (j == excl) ? 0.0 : t;
-    b += (j == excl) ? 0.0 : d1;
-    c += (j == excl) ? 0.0 : d2;
-  }
+    const double v = e * q;                // 1 / (nu e - 1)
+    a = fma(P.ch[j], q, a);
+    const double d1 = (P.ch[j] * v) * v;
+    b += d1;
+    c = fma(d1, e * v, c);
+  });
   sum = gsum<G>(a);
   dsum = gsum<G>(b);
   d2sum = gsum<G>(c);
@@ -387,14 +401,14 @@ __host__ __device__ inline double bits_mid(double lo, double hi) {
 
 // Next point of the safeguarded iteration and whether to stop.  During the
 // rational phase the second-order candidate is taken when it lies inside the
-// bracket, else the nearest-pole candidate, else the midpoint.  A candidate
-// step that is still large and no less than 0.3 times the previous step shows
-// linear (slow) progress: the midpoint is taken instead.  Stop when a
+// bracket, else the nearest-pole candidate, else the midpoint.  Candidates
+// that make slow progress across a bracket spanning decades are replaced by
+// the midpoint (see below).  Stop when a
 // candidate no longer moves x, when |h| is down to its rounding level hnoise,
 // or when the bracket is within 4 ulps.
 __host__ __device__ inline double rational_next(double x, double h, double hnoise, double psi_x, double dpsi_x,
                                                 double d2psi_x, double y, double c0, int kappa, double lo, double hi,
-                                                int it, double prev_step, int* done) {
+                                                int it, double prev_step, int hi_open, int* done) {
   *done = 0;
   if ((hi - lo) <= 4.0 * EPS * fabs(x)) { *done = 1; return x; }
   if (it < RATIONAL_TO_BISECT) {
@@ -408,11 +422,18 @@ __host__ __device__ inline double rational_next(double x, double h, double hnois
       *done = 1;
       return (cand > lo && cand < hi) ? cand : x;
     }
-    // a bracket spanning decades above a positive end: slow linear steps are
-    // replaced by its (near-geometric) bit-pattern midpoint
+    // the zero may sit at an upper bound that was never evaluated (to within
+    // rounding): go there rather than bisect towards it
+    if (hi_open && cand >= hi) return hi;
+    // a bracket spanning decades above a positive end: slow steps -- no less
+    // than 0.3 times the previous one, or, right of the zero, a move left by
+    // less than a factor 4 -- are replaced by its (near-geometric) bit-pattern
+    // midpoint; far from the zero a sum of poles spread over many decades
+    // makes the one-pole model advance by a nearly constant factor per step
     const bool decades = lo > 0.0 && hi > 16.0 * lo;
     const double step = fabs(cand - x);
-    const bool slow = decades && it >= 2 && step > 0.3 * prev_step && step > 1e-3 * fabs(x);
+    const bool slow = decades && step > 1e-3 * fabs(x) &&
+                      ((it >= 2 && step > 0.3 * prev_step) || (it >= 1 && h < 0 && cand > 0.25 * x));
     if (cand > lo && cand < hi && !slow) return cand;
   }
   return (lo > 0.0 && hi > 16.0 * lo) ? bits_mid(lo, hi) : 0.5 * (lo + hi);
@@ -431,12 +452,28 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
   const double y = sg * ymax_nu;
   const double c0 = sg * b;
   double x = xhi;
+  int hi_open = 0;   // xhi is a bound that has not been evaluated
+  if (y <= 0.0) {
+    // exterior eigenvalue: every other pole of psi_x lies left of 0 and its
+    // term is positive for x > 0, so h(x) >= c0 - x + rci / x and the zero of
+    // that two-by-two model (the corner block of A_i^{-1}) bounds the wanted
+    // zero from below.  Across the decades between it and the Gershgorin bound
+    // the iteration starts from the bit-pattern midpoint.
+    const double r = sqrt(c0 * c0 + 4.0 * rci);
+    const double x2 = (c0 >= 0.0) ? 0.5 * (c0 + r) : 2.0 * rci / (r - c0);
+    xlo = fmax(xlo, x2 * (1.0 - 4.0 * EPS));
+    if (xlo > 0.0 && xhi > 16.0 * xlo) {
+      x = bits_mid(xlo, xhi);
+      hi_open = 1;
+    }
+  }
   int it = 0;
   double prev_step = INFINITY;
   for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
+    if (x >= xhi) hi_open = 0;
     const double nu = sg * x;
     double s1, s2, s3;
-    psi_pass<KIND, G>(P, di, 0.0, i, nu, ln, s1, s2, s3);
+    psi_pass<KIND, G, false>(P, di, 0.0, i, nu, ln, s1, s2, s3);
     const double rnu = 1.0 / nu;
     const double psi = (s1 + rnu) * rci;                       // psi(nu)
     const double dpsi = -(s2 + rnu * rnu) * rci;               // psi'(nu)
@@ -447,7 +484,8 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     if (h == 0) break;
     const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi_x));
     int done = 0;
-    const double xn = rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 1, xlo, xhi, it, prev_step, &done);
+    const double xn =
+        rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 1, xlo, xhi, it, prev_step, hi_open, &done);
     prev_step = fabs(xn - x);
     x = xn;
     if (done) { ++it; break; }
@@ -474,9 +512,8 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
   double usum = 0.0, dmx = -INFINITY, dmn = INFINITY;
   for (int j = ln; j < m; j += G) {
     const dd e = dd_add_d(pdiff_dd<KIND>(P.ds[j], pv), -s);
-    fs = dd_add(fs, dd_div(dd{P.ch[j], P.cl[j]}, e));
-    const double eh = e.hi;
-    const double Dj = recip(eh);
+    const double Dj = recip(e.hi);
+    fs = dd_add(fs, dd_div2(dd{P.ch[j], P.cl[j]}, e, Dj));
     usum += P.ch[j] * Dj * Dj;
     dmx = fmax(dmx, Dj);
     dmn = fmin(dmn, Dj);
@@ -509,7 +546,7 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
     for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
       const double nu = sg * x;
       double s1, s2, s3;
-      psi_pass<KIND, G>(P, pv, s, -1, nu, ln, s1, s2, s3);
+      psi_pass<KIND, G, true>(P, pv, s, -1, nu, ln, s1, s2, s3);
       const double rnu = 1.0 / nu;
       const double psi_x = sg * (s1 + rnu);
       const double dpsi_x = -(s2 + rnu * rnu);
@@ -520,7 +557,7 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
       const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(psi_x));
       int done = 0;
       const double xn =
-          rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 0, xlo, xhi, it, prev_step, &done);
+          rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 0, xlo, xhi, it, prev_step, 0, &done);
       prev_step = fabs(xn - x);
       x = xn;
       if (done) { ++it; break; }
@@ -534,7 +571,7 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
 #pragma unroll 4
     for (int j = ln; j < m; j += G) {
       const double e = pdiff<KIND>(P.ds[j], pv) - s;
-      S += P.ch[j] * recip(e * fma(-mid, e, 1.0));
+      S = fma(P.ch[j], recip(e * fma(-mid, e, 1.0)), S);
     }
     S = gsum<G>(S);
     const double phi = 1.0 + rho * (S - 1.0 / mid);

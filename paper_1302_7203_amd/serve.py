@@ -188,6 +188,7 @@ class Server:
             h = ctypes.c_void_p()
             binding._check(L.arrow_create(ctypes.byref(h), self.device.index or 0), "arrow_create")
             binding._check(L.arrow_set_stream(h, ctypes.c_void_p(s.cuda_stream)), "arrow_set_stream")
+            binding.apply_tuned(h)
             self.handles.append(h)
         self.staging = torch.empty(staging_bytes // 8 * streams, dtype=torch.float64).pin_memory()
         self.slot_doubles = staging_bytes // 8
