@@ -52,6 +52,25 @@ WORKLOADS = {
 }
 
 
+def profiled_traffic(workload, prefix):
+    """HBM bytes per launch of the kernel whose name starts with `prefix`, from the committed
+    rocprofv3 counter summary of this workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy
+    probe); None when there is none or the kernel sources changed since it was taken."""
+    from paper_1302_7203_amd import profiling
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("source_sha256") != profiling.source_hash():
+        return None
+    for name, k in doc["kernels"].items():
+        if name.startswith(prefix) and "hbm_bytes" in k:
+            return k["hbm_bytes"]
+    return None
+
+
 def measured_peaks(binding, dev):
     """What the device sustains: FP64 FMA issue (arrow_probe_fma), 16-byte streaming stores
     (arrow_probe_fill, 2 GiB) and a plain copy (arrow_probe_copy, 1 GiB each way), each the best
@@ -293,12 +312,13 @@ def main():
     root_flops = m * (f_iter * cnt["root_bisect"] + F_DD * cnt["root_dd"] + F_SELECT * cnt["root_plain"])
     root_s = stages_ms[2] * 1e-3
     roof = {"kernel": "k_root", "bound": "alu", "achieved": root_flops / root_s / 1e12,
-            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": None}
+            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
+            "traffic": profiled_traffic(args.workload, "k_root<")}
     roof["frac"] = roof["achieved"] / roof["peak"]
     vec_bytes = 8.0 * n * n + 16.0 * n
     vec_s = stages_ms[4] * 1e-3
     roof_v = {"kernel": "k_vec", "bound": "hbm", "achieved": vec_bytes / vec_s / 1e9, "peak": PEAK_HBM / 1e9,
-              "unit": "GB/s", "traffic": None}
+              "unit": "GB/s", "traffic": profiled_traffic(args.workload, "k_vec<")}
     roof_v["frac"] = roof_v["achieved"] / roof_v["peak"]
 
     result = {

@@ -1,15 +1,21 @@
 // libarrow: gfx950 kernels and the C ABI declared in include/arrow.h.
 //
-// One call runs five launches on the handle's stream:
-//   k_sort      rank of every pole (symmetric permutation to decreasing order, Sec. 1)
+// One call runs these launches on the handle's stream:
+//   k_front     sortedness check; for sorted input also the copy to the
+//               workspace and the prologue (the next three then return at once)
+//   k_rank      rank of every pole (symmetric permutation to decreasing order, Sec. 1)
+//   k_scatter   the permuted copy
 //   k_prologue  shaft weights and corner of the (reduced) arrowhead in double-double
-//   k_root      per eigenvalue: shift selection, b, bisection (Algorithms 1-3, Theorem 6)
-//   k_check     per eigenvalue: K_nu test and remedies (Algorithm 5, Remarks 1-2), norm
+//   k_root      per eigenvalue: shift selection, b, root of the inverse (Algorithms 1-3, Theorem 6)
+//   k_check     per eigenvalue: K_nu test (Algorithm 5), norm; repairs are deferred
+//   k_repair    the deferred repairs (Remarks 1-2, DPR1 re-measure), a block per eigenvalue
 //   k_vec       eigenvector entries, streamed to HBM (eq. eigenvecAi, Algorithm 4)
 // k_root / k_check give G lanes of a wavefront to each eigenvalue (G = 64: one
 // wavefront per eigenvalue); k_vec is bound by the n^2 FP64 stores.
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -41,18 +47,34 @@ constexpr int SORT_CHUNK = 2048;
 
 __host__ __device__ inline uint32_t* rank_array(const Ws& w, int64_t n) { return w.st + n; }
 
+// One block of FRONT_BLOCK threads: whether the input already is in that
+// order (the usual case); if it is, the copy to the workspace and the whole
+// prologue are done here and the sort and prologue kernels that follow return
+// at once, else the rank array is cleared for them.
+constexpr int FRONT_BLOCK = 1024;
+
 template <int KIND>
-__global__ __launch_bounds__(1024) void k_sortcheck(ProbDesc D) {
+__global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
   const Ws w = ws_view(D.ws, D.n);
   const int ms = sorted_count(D);
-  uint32_t* rank = rank_array(w, D.n);
   int bad = 0;
-  for (int j = threadIdx.x; j < ms; j += blockDim.x) {
-    rank[j] = 0;
-    if (j + 1 < ms && !(sort_key<KIND>(D.d[j]) > sort_key<KIND>(D.d[j + 1]))) bad = 1;
-  }
+  for (int j = threadIdx.x; j + 1 < ms; j += FRONT_BLOCK)
+    if (!(sort_key<KIND>(D.d[j]) > sort_key<KIND>(D.d[j + 1]))) bad = 1;
   bad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) w.hdr[5] = bad ? 1.0 : 0.0;
+  if (bad) {
+    uint32_t* rank = rank_array(w, D.n);
+    for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) rank[j] = 0;
+    if (threadIdx.x == 0) w.hdr[5] = 1.0;
+    return;
+  }
+  for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
+    w.ds[j] = D.d[j];
+    w.zs[j] = D.z[j];
+    w.st[j] = input_status<KIND>(D, j, false);
+  }
+  __syncthreads();
+  prologue_block<KIND, FRONT_BLOCK>(D);
+  if (threadIdx.x == 0) w.hdr[5] = 0.0;
 }
 
 template <int KIND>
@@ -92,22 +114,20 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(ProbDesc D) {
   const Ws w = ws_view(D.ws, D.n);
   const int ms = sorted_count(D);
   const int j = blockIdx.x * BLOCK + threadIdx.x;
-  if (j >= ms) return;
-  int r = j;
-  bool dup = false;
-  if (w.hdr[5] != 0.0) {
-    const uint32_t raw = rank_array(w, D.n)[j];
-    r = (int)(raw & 0x3fffffffu);
-    dup = (raw >> 30) & 1u;
-  }
+  if (j >= ms || w.hdr[5] == 0.0) return;   // sorted input: k_front copied it
+  const uint32_t raw = rank_array(w, D.n)[j];
+  const int r = (int)(raw & 0x3fffffffu);
+  const bool dup = (raw >> 30) & 1u;
   w.ds[r] = D.d[j];
   w.zs[r] = D.z[j];
   w.st[j] = input_status<KIND>(D, j, dup);
 }
 
 template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_prologue(ProbDesc D) {
-  prologue_block<KIND>(D);
+__global__ __launch_bounds__(FRONT_BLOCK) void k_prologue(ProbDesc D) {
+  const Ws w = ws_view(D.ws, D.n);
+  if (w.hdr[5] == 0.0) return;   // sorted input: k_front did it
+  prologue_block<KIND, FRONT_BLOCK>(D);
 }
 
 // Root and check stages: ROOT_BLOCK threads per block, G lanes per
@@ -143,30 +163,60 @@ __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
   const int gid = blockIdx.x * ROOT_BLOCK + threadIdx.x;
   const int k = gid / G;
   if (k >= D.n) return;
-  if constexpr (STAGE) check_body<KIND, G, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
-  else check_body<KIND, G>(D, opt, k, gid % G);
+  if constexpr (STAGE) check_body<KIND, G, true, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
+  else check_body<KIND, G, false, true>(D, opt, k, gid % G);
+}
+
+// The eigenvalues k_check deferred (Remarks 1 and 2, the DPR1 re-measure),
+// one block of REPAIR_BLOCK lanes each: the repairs are a handful of
+// eigenvalues with several O(n) passes apiece, so they get whole blocks and
+// their own launch instead of stretching k_check.  Blocks beyond the list
+// length exit at once; the rest loop over the list.
+constexpr int REPAIR_BLOCK = 256;
+
+template <int KIND, bool STAGE>
+__global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt) {
+  extern __shared__ double lds[];
+  const Ws w = ws_view(D.ws, D.n);
+  const uint32_t count = *repair_count(w);
+  if (blockIdx.x >= count) return;
+  if constexpr (STAGE) stage_hot(D, lds);
+  const uint32_t* list = repair_list(w, D.n);
+  for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    const int k = (int)list[q];
+    if constexpr (STAGE) check_body<KIND, REPAIR_BLOCK, true>(D, opt, k, threadIdx.x, lds, lds + sorted_count(D));
+    else check_body<KIND, REPAIR_BLOCK>(D, opt, k, threadIdx.x);
+  }
 }
 
 // Eigenvector stage: a block owns VEC_TILE rows (kept in registers) of
-// VEC_COLS consecutive columns and streams those columns to HBM.
+// VEC_COLS consecutive columns and streams those columns to HBM.  W = 2 lets
+// each lane write two consecutive rows with one 16-byte non-temporal store
+// (n and the leading dimensions even, V and U 16-byte aligned); W = 1 writes
+// one row per store.
 constexpr int VEC_RPT = 4;                     // rows per thread
 constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
 constexpr int VEC_COLS = 16;                   // columns per block
+typedef double v2d __attribute__((ext_vector_type(2)));
 
-template <int KIND>
+template <int KIND, int W>
 __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles) {
+  static_assert(W == 1 || W == 2, "one or two rows per store");
+  constexpr int PER = VEC_RPT / W;             // stores per column per thread
   const int ct = blockIdx.x / row_tiles;
   const int rt = blockIdx.x - ct * row_tiles;
   const int n = D.n;
   const Ws w = ws_view(D.ws, n);
   double dr[VEC_RPT], num[VEC_RPT];
 #pragma unroll
-  for (int q = 0; q < VEC_RPT; ++q) {
-    const int r = rt * VEC_TILE + q * BLOCK + threadIdx.x;
-    const bool in = r < n;
-    const bool body = (KIND == KIND_DPR1) ? in : (r < n - 1);
-    dr[q] = body ? D.d[r] : 0.0;
-    num[q] = body ? ((KIND == KIND_SVD) ? dr[q] * D.z[r] : D.z[r]) : 0.0;
+  for (int q = 0; q < PER; ++q) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W + e;
+      const bool body = (KIND == KIND_DPR1) ? (r < n) : (r < n - 1);
+      dr[q * W + e] = body ? D.d[r] : 0.0;
+      num[q * W + e] = body ? ((KIND == KIND_SVD) ? dr[q * W + e] * D.z[r] : D.z[r]) : 0.0;
+    }
   }
   const int c0 = ct * VEC_COLS;
   const int c1 = min(n, c0 + VEC_COLS);
@@ -176,12 +226,23 @@ __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles) {
     double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
     const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
 #pragma unroll
-    for (int q = 0; q < VEC_RPT; ++q) {
-      const int r = rt * VEC_TILE + q * BLOCK + threadIdx.x;
-      if (r < n) {
-        const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);
-        __builtin_nontemporal_store(v, vc + r);
-        if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
+    for (int q = 0; q < PER; ++q) {
+      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W;
+      if (r < n) {   // W = 2: n is even, so r + 1 < n as well
+        if constexpr (W == 1) {
+          const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);
+          __builtin_nontemporal_store(v, vc + r);
+          if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
+        } else {
+          const double v0 = vec_entry<KIND>(dr[2 * q], num[2 * q], false, pv, s, mu, inrm);
+          const double v1 = vec_entry<KIND>(dr[2 * q + 1], num[2 * q + 1], r + 1 == n - 1, pv, s, mu, inrm);
+          const v2d vv = {v0, v1};
+          __builtin_nontemporal_store(vv, (v2d*)(vc + r));
+          if (KIND == KIND_SVD && uc) {
+            const v2d uu = {svd_left(D, sigma, v0, r), svd_left(D, sigma, v1, r + 1)};
+            __builtin_nontemporal_store(uu, (v2d*)(uc + r));
+          }
+        }
       }
     }
   }
@@ -239,15 +300,15 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   };
   const int ms = sorted_count(D);
   mark(0);
+  hipLaunchKernelGGL(k_front<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
   if (ms > 0) {
     const unsigned jt = (unsigned)((ms + BLOCK - 1) / BLOCK);
     const unsigned lc = (unsigned)((ms + SORT_CHUNK - 1) / SORT_CHUNK);
-    hipLaunchKernelGGL(k_sortcheck<KIND>, dim3(1), dim3(1024), 0, st, D);
     hipLaunchKernelGGL(k_rank<KIND>, dim3(jt, lc), dim3(BLOCK), 0, st, D);
     hipLaunchKernelGGL(k_scatter<KIND>, dim3(jt), dim3(BLOCK), 0, st, D);
   }
   mark(1);
-  hipLaunchKernelGGL(k_prologue<KIND>, dim3(1), dim3(BLOCK), 0, st, D);
+  hipLaunchKernelGGL(k_prologue<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
   mark(2);
   const int G = single_lanes(h, D.n);
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
@@ -255,12 +316,22 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   launch_rc_any<KIND>(G, D, h->opt, st, false, lds);
   mark(3);
   launch_rc_any<KIND>(G, D, h->opt, st, true, lds);
+  {
+    // deferred repairs; the block reductions add a little static LDS
+    const size_t lds_r = (hot + 4096 <= h->lds_max) ? hot : 0;
+    const dim3 grid((unsigned)std::min<int64_t>(D.n, h->cus));
+    if (lds_r > 0) hipLaunchKernelGGL((k_repair<KIND, true>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
+    else hipLaunchKernelGGL((k_repair<KIND, false>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
+  }
   mark(4);
   if (D.V) {
     const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
     const int col_chunks = (D.n + VEC_COLS - 1) / VEC_COLS;
-    hipLaunchKernelGGL(k_vec<KIND>, dim3((unsigned)((int64_t)row_tiles * col_chunks)), dim3(BLOCK), 0, st, D,
-                       row_tiles);
+    const dim3 grid((unsigned)((int64_t)row_tiles * col_chunks));
+    const bool pair = (D.n % 2 == 0) && (D.ldv % 2 == 0) && (((uintptr_t)D.V & 15) == 0) &&
+                      (!D.U || ((D.ldu % 2 == 0) && (((uintptr_t)D.U & 15) == 0)));
+    if (pair) hipLaunchKernelGGL((k_vec<KIND, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles);
+    else hipLaunchKernelGGL((k_vec<KIND, 1>), grid, dim3(BLOCK), 0, st, D, row_tiles);
   }
   mark(5);
   h->have_last = tm ? 1 : 0;

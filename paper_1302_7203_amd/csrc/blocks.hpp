@@ -12,11 +12,11 @@ namespace ahd {
 constexpr int BLOCK = 256;
 
 // Shaft weights and corner of the (reduced) arrowhead in double-double, the
-// problem flags, and whether some pole is exactly zero.  One block, BLOCK threads.
-template <int KIND>
+// problem flags, and whether some pole is exactly zero.  One block of NT threads.
+template <int KIND, int NT = BLOCK>
 __device__ inline void prologue_block(const ProbDesc& D) {
-  __shared__ double shi[BLOCK], slo[BLOCK];
-  __shared__ uint32_t sst[BLOCK];
+  __shared__ double shi[NT], slo[NT];
+  __shared__ uint32_t sst[NT];
   const Ws w = ws_view(D.ws, D.n);
   const int ms = sorted_count(D);
   const int m = D.n - 1;
@@ -24,11 +24,11 @@ __device__ inline void prologue_block(const ProbDesc& D) {
   uint32_t st = 0;
   uint32_t zp = 0;
   dd acc = {0.0, 0.0};
-  for (int j = t; j < ms; j += BLOCK) {
+  for (int j = t; j < ms; j += NT) {
     st |= w.st[j];
     acc = dd_add(acc, corner_term<KIND>(D, w, j));
   }
-  for (int j = t; j < m; j += BLOCK) {
+  for (int j = t; j < m; j += NT) {
     prologue_elem<KIND>(D, w, j);
     zp |= (w.ds[j] == 0.0) ? 1u : 0u;
   }
@@ -36,7 +36,7 @@ __device__ inline void prologue_block(const ProbDesc& D) {
   slo[t] = acc.lo;
   sst[t] = st | (zp << 31);
   __syncthreads();
-  for (int o = BLOCK / 2; o > 0; o >>= 1) {
+  for (int o = NT / 2; o > 0; o >>= 1) {
     if (t < o) {
       const dd a = dd_add(dd{shi[t], slo[t]}, dd{shi[t + o], slo[t + o]});
       shi[t] = a.hi;
@@ -51,6 +51,7 @@ __device__ inline void prologue_block(const ProbDesc& D) {
     w.hdr[1] = c.lo;
     w.hdr[2] = (sst[0] >> 31) ? 1.0 : 0.0;
     *prob_flags(w) = sst[0] & 0x7fffffffu;
+    *repair_count(w) = 0u;
   }
   __syncthreads();
 }

@@ -216,8 +216,28 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
 // ---------------------------------------------------------------------------
 // K_nu test and remedies (Algorithm 5, last part; Remarks 1 and 2), then the
 // eigenvector norm.  Writes the final shift pair and the caller's outputs.
+//
+// DEFER: an eigenvalue that needs one of the O(n)-per-step repairs (Remark 1,
+// Remark 2, the DPR1 re-measure from d_n) is only appended to the problem's
+// repair list and left for a second launch, which runs check_body on the
+// listed eigenvalues with wider lane groups; everything else is finished here.
+// The list reuses the sort's rank array, free once the poles are sorted; its
+// length sits in hdr[6] and is cleared by the prologue.
 
-template <int KIND, int G, bool HOT = false>
+__host__ __device__ inline uint32_t* repair_count(const Ws& w) { return (uint32_t*)(w.hdr + 6); }
+__host__ __device__ inline uint32_t* repair_list(const Ws& w, int64_t n) { return w.st + n; }
+
+__host__ __device__ inline void defer_repair(const Ws& w, int64_t n, int k, int ln) {
+  if (ln != 0) return;
+#if defined(__HIP_DEVICE_COMPILE__)
+  const uint32_t at = atomicAdd(repair_count(w), 1u);
+#else
+  const uint32_t at = (*repair_count(w))++;
+#endif
+  repair_list(w, n)[at] = (uint32_t)k;
+}
+
+template <int KIND, int G, bool HOT = false, bool DEFER = false>
 __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln,
                                            const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);
@@ -250,6 +270,12 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     const double dist_o = fabs(pdiff<KIND>(w.pv1[o], di) + w.mu1[o]);
     const double knu = fabs(mu) / fmin(fabs(mu), dist_o);
     const bool zero_pole = w.hdr[2] != 0.0;
+    if constexpr (DEFER) {
+      if ((quot > opt.tau_zero && !zero_pole) || knu > opt.tau_nu) {
+        defer_repair(w, D.n, k, ln);
+        return;
+      }
+    }
     if (quot > opt.tau_zero && !zero_pole) {
       // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
       int z0 = 0, it = 0;
@@ -303,8 +329,12 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       const double gap = P.ds[P.nsorted - 2] - dn;
       const double tau = (pv - dn) + s + mu;
       if (tau < 0.5 * gap) {
+        if constexpr (DEFER) {
+          defer_repair(w, D.n, k, ln);
+          return;
+        }
         int it = 0;
-        const double t2 = dpr1_from_last_pole<G>(P, gap, ln, &it);
+        const double t2 = dpr1_from_last_pole<G>(P, tau, ln, &it);
         pv = dn; s = 0.0; mu = t2;
         fl |= INFO_POLE_SHIFT;
         c_it += it;

@@ -128,15 +128,35 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;   // lane i <-> 7 - i within 8
 constexpr int DPP_MIRROR = 0x140;        // lane i <-> 15 - i within 16
 
+#if defined(__HIP_DEVICE_COMPILE__)
+// Groups wider than a wavefront are whole blocks (blockDim.x == G): after the
+// wavefront butterfly, lane 0 of each wavefront posts its value to LDS and
+// every lane combines the NW posted values in wavefront order, so all lanes
+// again hold identical bits.  Every lane of the block must reach the call.
+template <int NW, class Op>
+__device__ inline double block_combine(double v, Op op) {
+  __shared__ double slot[NW];
+  if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = slot[0];
+#pragma unroll
+  for (int q = 1; q < NW; ++q) r = op(r, slot[q]);
+  __syncthreads();
+  return r;
+}
+#endif
+
 template <int G, class Op>
 __host__ __device__ inline double greduce(double v, Op op) {
+  static_assert(G <= 64 || G % 64 == 0, "a group is part of a wavefront or whole wavefronts");
 #if defined(__HIP_DEVICE_COMPILE__)
   if constexpr (G >= 2) v = op(v, dpp<DPP_QUAD_XOR1>(v));
   if constexpr (G >= 4) v = op(v, dpp<DPP_QUAD_XOR2>(v));
   if constexpr (G >= 8) v = op(v, dpp<DPP_HALF_MIRROR>(v));
   if constexpr (G >= 16) v = op(v, dpp<DPP_MIRROR>(v));
-  if constexpr (G >= 32) v = op(v, __shfl_xor(v, 16, G));
-  if constexpr (G >= 64) v = op(v, __shfl_xor(v, 32, G));
+  if constexpr (G >= 32) v = op(v, __shfl_xor(v, 16, G > 64 ? 64 : G));
+  if constexpr (G >= 64) v = op(v, __shfl_xor(v, 32, 64));
+  if constexpr (G > 64) v = block_combine<G / 64>(v, op);
 #endif
   return v;
 }
@@ -163,12 +183,27 @@ __host__ __device__ inline double gmin(double v) { return greduce<G>(v, OpMin())
 template <int G>
 __host__ __device__ inline dd gsum_dd(dd v) {
 #if defined(__HIP_DEVICE_COMPILE__)
+  constexpr int W = G > 64 ? 64 : G;
   if constexpr (G >= 2) v = dd_add(v, dd{dpp<DPP_QUAD_XOR1>(v.hi), dpp<DPP_QUAD_XOR1>(v.lo)});
   if constexpr (G >= 4) v = dd_add(v, dd{dpp<DPP_QUAD_XOR2>(v.hi), dpp<DPP_QUAD_XOR2>(v.lo)});
   if constexpr (G >= 8) v = dd_add(v, dd{dpp<DPP_HALF_MIRROR>(v.hi), dpp<DPP_HALF_MIRROR>(v.lo)});
   if constexpr (G >= 16) v = dd_add(v, dd{dpp<DPP_MIRROR>(v.hi), dpp<DPP_MIRROR>(v.lo)});
-  if constexpr (G >= 32) v = dd_add(v, dd{__shfl_xor(v.hi, 16, G), __shfl_xor(v.lo, 16, G)});
-  if constexpr (G >= 64) v = dd_add(v, dd{__shfl_xor(v.hi, 32, G), __shfl_xor(v.lo, 32, G)});
+  if constexpr (G >= 32) v = dd_add(v, dd{__shfl_xor(v.hi, 16, W), __shfl_xor(v.lo, 16, W)});
+  if constexpr (G >= 64) v = dd_add(v, dd{__shfl_xor(v.hi, 32, W), __shfl_xor(v.lo, 32, W)});
+  if constexpr (G > 64) {
+    constexpr int NW = G / 64;
+    __shared__ double slot_hi[NW], slot_lo[NW];
+    if ((threadIdx.x & 63) == 0) {
+      slot_hi[threadIdx.x >> 6] = v.hi;
+      slot_lo[threadIdx.x >> 6] = v.lo;
+    }
+    __syncthreads();
+    dd r = {slot_hi[0], slot_lo[0]};
+#pragma unroll
+    for (int q = 1; q < NW; ++q) r = dd_add(r, dd{slot_hi[q], slot_lo[q]});
+    __syncthreads();
+    v = r;
+  }
 #endif
   return v;
 }
@@ -510,14 +545,14 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
   const int m = P.m;
   dd fs = {0.0, 0.0};
   double usum = 0.0, dmx = -INFINITY, dmn = INFINITY;
-  for (int j = ln; j < m; j += G) {
+  for_terms<G>(ln, m, -1, [&](int j, bool) {
     const dd e = dd_add_d(pdiff_dd<KIND>(P.ds[j], pv), -s);
     const double Dj = recip(e.hi);
     fs = dd_add(fs, dd_div2(dd{P.ch[j], P.cl[j]}, e, Dj));
     usum += P.ch[j] * Dj * Dj;
     dmx = fmax(dmx, Dj);
     dmn = fmin(dmn, Dj);
-  }
+  });
   fs = gsum_dd<G>(fs);
   usum = gsum<G>(usum);
   dmx = gmax<G>(dmx);
@@ -587,33 +622,70 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
 // ---------------------------------------------------------------------------
 // DPR1 only: the smallest eigenvalue lies in (d_n, d_{n-1}) and may sit much
 // closer to d_n, which is not a pole of the reduced arrowhead.  Re-measure it
-// from d_n: tau = lambda - d_n in (0, d_{n-1} - d_n) is the zero of
-//   phi(d_n + tau) = 1 + rho (sum_{j<n} u_j^2 / ((d_j - d_n) - tau) - u_n^2 / tau),
-// whose terms inside the bracket are all positive except the last.
+// from d_n: tau = lambda - d_n is the zero in (0, d_{n-1} - d_n) of
+//   phi(d_n + tau) = 1 + rho (sum_{j<n} u_j^2 / (e_j - tau) - u_n^2 / tau),
+// e_j = d_j - d_n.  In x = 1 / tau, with u_j^2/(e_j - 1/x) = u_j^2/e_j +
+// u_j^2/(e_j (x e_j - 1)), dividing by rho u_n^2 gives the form the rational
+// iteration solves,
+//   h(x) = c0 - x + psi(x),  c0 = (1/rho + sum_j u_j^2/e_j) / u_n^2,
+//   psi(x) = sum_j u_j^2 / (e_j (x e_j - 1)) / u_n^2,
+// with every term positive right of the nearest pole y = 1/(d_{n-1} - d_n).
+// For x >= 2/e_j each term is at most 2 u_j^2 / (e_j^2 x), so x <= c0 + Q/x
+// with Q = 2 sum_j u_j^2/e_j^2 / u_n^2 bounds the zero from above (or it is
+// below 2y).  tau_est, the first pass's estimate, is the starting point.
 
 template <int G>
-__host__ __device__ inline double dpr1_from_last_pole(const Prob& P, double hi, int ln, int* iters) {
-  const int n = P.nsorted;
-  const double dn = P.ds[n - 1];
-  const double un = P.zs[n - 1];
-  const double un2 = un * un;
-  double lo = 0.0;
-  double mid = 0.5 * (lo + hi);
+__host__ __device__ inline double dpr1_from_last_pole(const Prob& P, double tau_est, int ln, int* iters) {
+  const int m = P.nsorted - 1;          // the poles d_1 .. d_{n-1}
+  const double dn = P.ds[m];
+  const double un = P.zs[m];
+  const double ru = 1.0 / (un * un);
+  const double y = 1.0 / (P.ds[m - 1] - dn);
+  double K = 0.0, Q = 0.0;
+  for_terms<G>(ln, m, -1, [&](int j, bool) {
+    const double r = recip(P.ds[j] - dn);
+    const double cr = (P.zs[j] * P.zs[j]) * r;
+    K += cr;
+    Q = fma(cr, r, Q);
+  });
+  K = gsum<G>(K);
+  Q = gsum<G>(Q);
+  const double c0 = (1.0 / P.rho + K) * ru;
+  const double q2 = 2.0 * Q * ru;
+  double xlo = y;
+  double xhi = fmax(2.0 * y, 0.5 * (c0 + sqrt(c0 * c0 + 4.0 * q2))) * (1.0 + 8.0 * EPS);
+  double x = 1.0 / tau_est;
+  if (!(x > xlo && x < xhi)) x = xhi;
   int it = 0;
-  while ((hi - lo) / fabs(mid) > 2.0 * EPS && it < MAX_BISECT) {
-    double S = 0.0;
-    for (int j = ln; j < n - 1; j += G) {
-      const double u = P.zs[j];
-      S += (u * u) / ((P.ds[j] - dn) - mid);
-    }
-    S = gsum<G>(S);
-    const double phi = 1.0 + P.rho * (S - un2 / mid);
-    if (phi < 0) lo = mid; else hi = mid;
-    mid = 0.5 * (lo + hi);
-    ++it;
+  double prev_step = INFINITY;
+  for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
+    double a = 0.0, b = 0.0, c = 0.0;
+    for_terms<G>(ln, m, -1, [&](int j, bool) {
+      const double e = P.ds[j] - dn;
+      const double q = recip(e * fma(x, e, -1.0));
+      const double v = e * q;                 // 1 / (x e - 1)
+      const double u2 = P.zs[j] * P.zs[j];
+      a = fma(u2, q, a);
+      const double d1 = (u2 * v) * v;
+      b += d1;
+      c = fma(d1, e * v, c);
+    });
+    a = gsum<G>(a);
+    b = gsum<G>(b);
+    c = gsum<G>(c);
+    const double psi = a * ru, dpsi = -b * ru, d2psi = 2.0 * c * ru;
+    const double h = c0 - x + psi;
+    if (h > 0) xlo = x; else xhi = x;
+    if (h == 0) break;
+    const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi));
+    int done = 0;
+    const double xn = rational_next(x, h, hnoise, psi, dpsi, d2psi, y, c0, 1, xlo, xhi, it, prev_step, 0, &done);
+    prev_step = fabs(xn - x);
+    x = xn;
+    if (done) { ++it; break; }
   }
   *iters = it;
-  return hi;
+  return 1.0 / x;
 }
 
 // ---------------------------------------------------------------------------
