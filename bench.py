@@ -201,7 +201,7 @@ def serving_leg(args, dev):
             got[r.rid] = (ks, lam[kt].cpu().numpy(), V[:, kt].cpu().numpy(),
                           None if U is None else U[:, kt].cpu().numpy())
 
-    srv = serve.Server(hbm_budget=budget, device=dev, streams=3, on_done=grab)
+    srv = serve.Server(hbm_budget=budget, device=dev, streams=3, max_batch=args.serve_max_batch, on_done=grab)
     srv.run([(0.0, p) for p in probs[:200]])                     # warm-up
     torch.cuda.synchronize(dev)
     sat = serve.latency_stats(srv.run([(0.0, p) for p in probs]))
@@ -223,6 +223,7 @@ def serving_leg(args, dev):
     torch.cuda.empty_cache()
 
     res = {"workload": SERVE_DESC, "requests": len(probs), "eigenpairs": pairs, "hbm_budget_gib": args.serve_budget_gib,
+           "max_batch": args.serve_max_batch,
            "saturated_batched": {k: sat[k] for k in ("solves_per_s", "eigenpairs_per_s", "wall_s")},
            "saturated_per_solve_launch": {k: per_solve[k] for k in ("solves_per_s", "eigenpairs_per_s", "wall_s")},
            "speedup_vs_per_solve": sat["eigenpairs_per_s"] / per_solve["eigenpairs_per_s"],
@@ -266,6 +267,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-batch", type=int, default=4096, help="most requests one launch may take")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -336,7 +338,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "problems_per_step": 1, "parallelism": "single GPU",
                    "root_finder": args.root},
-        "stages_ms": {k: float(v) for k, v in zip(("sort", "prologue", "root", "check", "vectors"), stages_ms)},
+        "stages_ms": {k: float(v) for k, v in zip(("front", "sort", "root", "check", "vectors"), stages_ms)},
         "counters": cnt,
         "roofline": roof,
         "roofline_vector": roof_v,

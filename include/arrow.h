@@ -213,10 +213,12 @@ int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const in
  * Diagnostics of the most recent single-problem call on this handle.
  *
  * arrow_last_timing: ms[0..4] receive the elapsed times (milliseconds, from
- *   HIP events on the handle's stream) of the stages sort, prologue, root
- *   (shift, b, bisection), check (K_nu, remedies, norm) and vectors.  Needs
- *   ARROW_OPT_TIMING set before that call; waits for it to finish.  Returns
- *   ARROW_ERR_STATE when no timed call exists.
+ *   HIP events on the handle's stream) of the stages front (sortedness check;
+ *   for input already in decreasing order also the copy and the shaft weights
+ *   and corner), sort (input not in that order: rank sort, copy, weights and
+ *   corner), root (shift, b, root of the inverse), check (K_nu, repairs, norm)
+ *   and vectors.  Needs ARROW_OPT_TIMING set before that call; waits for it to
+ *   finish.  Returns ARROW_ERR_STATE when no timed call exists.
  * arrow_last_counters: out[0..6] receive, summed over all eigenvalues, the
  *   bisection steps, double-double O(n) passes and plain O(n) passes executed
  *   by the root stage (out[0..2]) and by the check stage (out[3..5]), and the

@@ -34,7 +34,8 @@ from . import batch, binding, workloads
 
 SINGLE_NS = [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384]
 LANES_SINGLE = [1, 2, 4, 8, 16, 32, 64]
-BATCH_BUCKETS = [(8, 24), (24, 48), (48, 96), (96, 192), (192, 384), (384, 768), (768, 1536), (1536, 4096)]
+BATCH_BUCKETS = [(8, 24), (24, 48), (48, 96), (96, 192), (192, 384), (384, 768), (768, 1536), (1536, 3072),
+                 (3072, 8192)]
 LANES_BATCH = [4, 8, 16, 32, 64]
 BATCH_PAIRS = 400_000
 

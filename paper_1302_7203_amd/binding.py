@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libarrow.so")
+# the in-tree build; ARROW_LIBRARY may name another build of the same sources
+LIB_PATH = os.environ.get("ARROW_LIBRARY") or os.path.join(_HERE, "libarrow.so")
 # lanes-per-eigenvalue tables measured by the autotuner (paper_1302_7203_amd.autotune)
 TUNED_PATH = os.path.join(_HERE, "tuned", "schedule_gfx950.json")
 
@@ -146,7 +147,7 @@ def set_option(option: int, value: float, device=None):
 
 
 def last_timing(device=None) -> list[float]:
-    """Stage times (ms) of the last timed call: sort, prologue, root, check, vectors."""
+    """Stage times (ms) of the last timed call: front, sort, root, check, vectors."""
     ms = (ctypes.c_double * 5)()
     _check(lib().arrow_last_timing(handle(device), ms), "arrow_last_timing")
     return list(ms)

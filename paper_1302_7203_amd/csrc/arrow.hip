@@ -2,10 +2,10 @@
 //
 // One call runs these launches on the handle's stream:
 //   k_front     sortedness check; for sorted input also the copy to the
-//               workspace and the prologue (the next three then return at once)
-//   k_rank      rank of every pole (symmetric permutation to decreasing order, Sec. 1)
-//   k_scatter   the permuted copy
-//   k_prologue  shaft weights and corner of the (reduced) arrowhead in double-double
+//               workspace and the prologue: shaft weights and corner of the
+//               (reduced) arrowhead in double-double
+//   k_sort      unsorted input only: rank of every pole (symmetric permutation
+//               to decreasing order, Sec. 1), the permuted copy, the prologue
 //   k_root      per eigenvalue: shift selection, b, root of the inverse (Algorithms 1-3, Theorem 6)
 //   k_check     per eigenvalue: K_nu test (Algorithm 5), norm; repairs are deferred
 //   k_repair    the deferred repairs (Remarks 1-2, DPR1 re-measure), a block per eigenvalue
@@ -49,9 +49,11 @@ __host__ __device__ inline uint32_t* rank_array(const Ws& w, int64_t n) { return
 
 // One block of FRONT_BLOCK threads: whether the input already is in that
 // order (the usual case); if it is, the copy to the workspace and the whole
-// prologue are done here and the sort and prologue kernels that follow return
-// at once, else the rank array is cleared for them.
+// prologue are done here and k_sort returns at once, else the rank array and
+// k_sort's completion counter are cleared for it.
 constexpr int FRONT_BLOCK = 1024;
+
+__host__ __device__ inline uint32_t* sort_done(const Ws& w) { return (uint32_t*)(w.hdr + 7); }
 
 template <int KIND>
 __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
@@ -64,7 +66,10 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
   if (bad) {
     uint32_t* rank = rank_array(w, D.n);
     for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) rank[j] = 0;
-    if (threadIdx.x == 0) w.hdr[5] = 1.0;
+    if (threadIdx.x == 0) {
+      w.hdr[5] = 1.0;
+      *sort_done(w) = 0u;
+    }
     return;
   }
   for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
@@ -77,12 +82,18 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
   if (threadIdx.x == 0) w.hdr[5] = 0.0;
 }
 
+// Unsorted input: the rank of every key over a 2-D grid of (key tile,
+// comparison chunk) blocks, accumulated with atomics; the last block to finish
+// (a completion count) then holds every rank, scatters the poles into
+// decreasing order and runs the prologue.
 template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_rank(ProbDesc D) {
+__global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   __shared__ double tile[BLOCK];
+  __shared__ int last;
   const Ws w = ws_view(D.ws, D.n);
-  if (w.hdr[5] == 0.0) return;  // already sorted
+  if (w.hdr[5] == 0.0) return;  // already sorted: k_front did everything
   const int ms = sorted_count(D);
+  uint32_t* rank = rank_array(w, D.n);
   const int j = blockIdx.x * BLOCK + threadIdx.x;
   const double kj = (j < ms) ? sort_key<KIND>(D.d[j]) : NAN;
   const int l0 = blockIdx.y * SORT_CHUNK;
@@ -103,31 +114,25 @@ __global__ __launch_bounds__(BLOCK) void k_rank(ProbDesc D) {
     __syncthreads();
   }
   if (j < ms) {
-    uint32_t* rank = rank_array(w, D.n);
     if (cnt) atomicAdd(&rank[j], cnt);
     if (dup) atomicOr(&rank[j], 1u << 30);
   }
-}
-
-template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_scatter(ProbDesc D) {
-  const Ws w = ws_view(D.ws, D.n);
-  const int ms = sorted_count(D);
-  const int j = blockIdx.x * BLOCK + threadIdx.x;
-  if (j >= ms || w.hdr[5] == 0.0) return;   // sorted input: k_front copied it
-  const uint32_t raw = rank_array(w, D.n)[j];
-  const int r = (int)(raw & 0x3fffffffu);
-  const bool dup = (raw >> 30) & 1u;
-  w.ds[r] = D.d[j];
-  w.zs[r] = D.z[j];
-  w.st[j] = input_status<KIND>(D, j, dup);
-}
-
-template <int KIND>
-__global__ __launch_bounds__(FRONT_BLOCK) void k_prologue(ProbDesc D) {
-  const Ws w = ws_view(D.ws, D.n);
-  if (w.hdr[5] == 0.0) return;   // sorted input: k_front did it
-  prologue_block<KIND, FRONT_BLOCK>(D);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(sort_done(w), 1u) == gridDim.x * gridDim.y - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int q = threadIdx.x; q < ms; q += BLOCK) {
+    const uint32_t raw = __hip_atomic_load(&rank[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int r = (int)(raw & 0x3fffffffu);
+    w.ds[r] = D.d[q];
+    w.zs[r] = D.z[q];
+    w.st[q] = input_status<KIND>(D, q, (raw >> 30) & 1u);
+  }
+  __threadfence();
+  __syncthreads();
+  prologue_block<KIND, BLOCK>(D);
 }
 
 // Root and check stages: ROOT_BLOCK threads per block, G lanes per
@@ -138,8 +143,23 @@ constexpr int ROOT_BLOCK = 512;
 __device__ inline void stage_hot(const ProbDesc& D, double* lds) {
   const Ws w = ws_view(D.ws, D.n);
   const int ns = sorted_count(D), m = D.n - 1;
-  for (int j = threadIdx.x; j < ns; j += blockDim.x) lds[j] = w.ds[j];
-  for (int j = threadIdx.x; j < m; j += blockDim.x) lds[ns + j] = w.ch[j];
+  const int top = ns > m ? ns : m;
+  // four rows of both arrays in flight per thread before the LDS stores
+  for (int j0 = threadIdx.x; j0 < top; j0 += 4 * blockDim.x) {
+    double a[4], c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + q * blockDim.x;
+      a[q] = (j < ns) ? w.ds[j] : 0.0;
+      c[q] = (j < m) ? w.ch[j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + q * blockDim.x;
+      if (j < ns) lds[j] = a[q];
+      if (j < m) lds[ns + j] = c[q];
+    }
+  }
   __syncthreads();
 }
 
@@ -178,74 +198,24 @@ template <int KIND, bool STAGE>
 __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt) {
   extern __shared__ double lds[];
   const Ws w = ws_view(D.ws, D.n);
-  const uint32_t count = *repair_count(w);
+  const uint32_t count = min(*repair_count(w), (uint32_t)D.n);
   if (blockIdx.x >= count) return;
   if constexpr (STAGE) stage_hot(D, lds);
   const uint32_t* list = repair_list(w, D.n);
   for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
     const int k = (int)list[q];
+    if (k < 0 || k >= D.n) continue;
     if constexpr (STAGE) check_body<KIND, REPAIR_BLOCK, true>(D, opt, k, threadIdx.x, lds, lds + sorted_count(D));
     else check_body<KIND, REPAIR_BLOCK>(D, opt, k, threadIdx.x);
   }
 }
 
-// Eigenvector stage: a block owns VEC_TILE rows (kept in registers) of
-// VEC_COLS consecutive columns and streams those columns to HBM.  W = 2 lets
-// each lane write two consecutive rows with one 16-byte non-temporal store
-// (n and the leading dimensions even, V and U 16-byte aligned); W = 1 writes
-// one row per store.
-constexpr int VEC_RPT = 4;                     // rows per thread
-constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
-constexpr int VEC_COLS = 16;                   // columns per block
-typedef double v2d __attribute__((ext_vector_type(2)));
-
+// Eigenvector stage (vec_tile in blocks.hpp): a block owns VEC_TILE rows of
+// VEC_COLS consecutive columns.
 template <int KIND, int W>
 __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles) {
-  static_assert(W == 1 || W == 2, "one or two rows per store");
-  constexpr int PER = VEC_RPT / W;             // stores per column per thread
   const int ct = blockIdx.x / row_tiles;
-  const int rt = blockIdx.x - ct * row_tiles;
-  const int n = D.n;
-  const Ws w = ws_view(D.ws, n);
-  double dr[VEC_RPT], num[VEC_RPT];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-#pragma unroll
-    for (int e = 0; e < W; ++e) {
-      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W + e;
-      const bool body = (KIND == KIND_DPR1) ? (r < n) : (r < n - 1);
-      dr[q * W + e] = body ? D.d[r] : 0.0;
-      num[q * W + e] = body ? ((KIND == KIND_SVD) ? dr[q * W + e] * D.z[r] : D.z[r]) : 0.0;
-    }
-  }
-  const int c0 = ct * VEC_COLS;
-  const int c1 = min(n, c0 + VEC_COLS);
-  for (int col = c0; col < c1; ++col) {
-    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
-    double* vc = D.V + (size_t)col * (size_t)D.ldv;
-    double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
-    const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W;
-      if (r < n) {   // W = 2: n is even, so r + 1 < n as well
-        if constexpr (W == 1) {
-          const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);
-          __builtin_nontemporal_store(v, vc + r);
-          if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
-        } else {
-          const double v0 = vec_entry<KIND>(dr[2 * q], num[2 * q], false, pv, s, mu, inrm);
-          const double v1 = vec_entry<KIND>(dr[2 * q + 1], num[2 * q + 1], r + 1 == n - 1, pv, s, mu, inrm);
-          const v2d vv = {v0, v1};
-          __builtin_nontemporal_store(vv, (v2d*)(vc + r));
-          if (KIND == KIND_SVD && uc) {
-            const v2d uu = {svd_left(D, sigma, v0, r), svd_left(D, sigma, v1, r + 1)};
-            __builtin_nontemporal_store(uu, (v2d*)(uc + r));
-          }
-        }
-      }
-    }
-  }
+  vec_tile<KIND, W>(D, blockIdx.x - ct * row_tiles, ct);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,14 +271,12 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   const int ms = sorted_count(D);
   mark(0);
   hipLaunchKernelGGL(k_front<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
+  mark(1);
   if (ms > 0) {
     const unsigned jt = (unsigned)((ms + BLOCK - 1) / BLOCK);
     const unsigned lc = (unsigned)((ms + SORT_CHUNK - 1) / SORT_CHUNK);
-    hipLaunchKernelGGL(k_rank<KIND>, dim3(jt, lc), dim3(BLOCK), 0, st, D);
-    hipLaunchKernelGGL(k_scatter<KIND>, dim3(jt), dim3(BLOCK), 0, st, D);
+    hipLaunchKernelGGL(k_sort<KIND>, dim3(jt, lc), dim3(BLOCK), 0, st, D);
   }
-  mark(1);
-  hipLaunchKernelGGL(k_prologue<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
   mark(2);
   const int G = single_lanes(h, D.n);
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);

@@ -6,8 +6,11 @@
 //               items from an atomic queue and runs the first pass (shift,
 //               b, root of the inverse) on them; problems are queued by
 //               decreasing order n so the long items start first
-//   k_b_stage   the same queue again for the K_nu test, remedies and norms
-//   k_b_vec     flat map of every problem's n*n vector entries onto blocks
+//   k_b_stage   the same queue again for the K_nu test and norms; eigenvalues
+//               that need a repair (Remarks 1-2, DPR1 re-measure) are listed
+//   k_b_repair  the listed repairs, a block per eigenvalue
+//   k_b_vec     every problem's vector tiles (row tiles for large n, flat
+//               column-major runs for small n) mapped onto blocks
 //
 // A wavefront gives G lanes to each eigenvalue, so one item covers 64/G
 // consecutive eigenvalues of one problem; G comes from the handle's table of
@@ -31,13 +34,14 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int STAGE_BLOCK = 256;
-constexpr int VEC_CHUNK = 1024;   // vector entries per k_b_vec block
+constexpr int VEC_TALL_MIN = 512; // n from which vectors are written in row tiles
 
 struct BatchArgs {
   const ProbDesc* descs;     // problems in queue order
   const int32_t* item_start; // count + 1 prefix sums of items
   const int32_t* lanes;      // G per problem
-  const int32_t* vec_start;  // count + 1 prefix sums of vector chunks
+  const int32_t* vec_start;  // count + 1 prefix sums of vector tiles
+  const int32_t* vec_mode;   // per problem: 0 flat tiles, 1 row tiles, 2 row tiles with 16-byte stores
   uint32_t* counters;        // [0] first-pass queue, [1] check queue
   int32_t count;
   int32_t total_items;
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
 
 template <bool CHECK, int KIND, int G>
 __device__ inline void run_item(const ProbDesc& D, const Options& opt, int k, int ln) {
-  if (CHECK) check_body<KIND, G>(D, opt, k, ln);
+  if (CHECK) check_body<KIND, G, false, true>(D, opt, k, ln);   // repairs listed for k_b_repair
   else root_body<KIND, G>(D, opt, k, ln);
 }
 
@@ -86,8 +90,10 @@ __device__ inline void run_kind(const ProbDesc& D, const Options& opt, int G, in
   }
 }
 
+// at least four wavefronts per SIMD: the pole loads come from L2 and need company to hide
 template <bool CHECK>
-__global__ __launch_bounds__(STAGE_BLOCK) void k_b_stage(BatchArgs B, Options opt) {
+__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_stage(BatchArgs B,
+                                                                                                 Options opt) {
   const int lane = threadIdx.x & (WAVE - 1);
   for (;;) {
     int item = 0;
@@ -109,36 +115,53 @@ __global__ __launch_bounds__(STAGE_BLOCK) void k_b_stage(BatchArgs B, Options op
   }
 }
 
-template <int KIND>
-__device__ inline void vec_chunk(const ProbDesc& D, int64_t base) {
-  const int n = D.n;
-  const uint32_t nn = (uint32_t)n * (uint32_t)n;
-  const Ws w = ws_view(D.ws, n);
-#pragma unroll
-  for (int q = 0; q < VEC_CHUNK / BLOCK; ++q) {
-    const int64_t e64 = base + q * BLOCK + threadIdx.x;
-    if (e64 >= nn) break;
-    const uint32_t e = (uint32_t)e64;
-    const uint32_t col = e / (uint32_t)n;
-    const int r = (int)(e - col * (uint32_t)n);
-    const bool body = (KIND == KIND_DPR1) ? true : (r < n - 1);
-    const double dr = body ? D.d[r] : 0.0;
-    const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[r] : D.z[r]) : 0.0;
-    const double v = vec_entry<KIND>(dr, num, r == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
-    __builtin_nontemporal_store(v, D.V + e);
-    if (KIND == KIND_SVD && D.U) __builtin_nontemporal_store(svd_left(D, D.lam[col], v, r), D.U + e);
+// The repairs the check stage deferred (each problem keeps its own list in its
+// workspace, as in the single-problem path): `per` blocks of REPAIR_BLOCK
+// lanes per problem stride over that problem's list, each listed eigenvalue
+// run by a whole block.  Blocks beyond a problem's list length return at once.
+constexpr int REPAIR_BLOCK = 256;
+
+__global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options opt, int per) {
+  const int p = (int)blockIdx.x / per;
+  const int x = (int)blockIdx.x - p * per;
+  const ProbDesc D = B.descs[p];
+  const Ws w = ws_view(D.ws, D.n);
+  const uint32_t c = min(*repair_count(w), (uint32_t)D.n);
+  if ((uint32_t)x >= c) return;
+  const uint32_t* list = repair_list(w, D.n);
+  for (uint32_t q = (uint32_t)x; q < c; q += (uint32_t)per) {
+    const int k = (int)list[q];
+    if (k < 0 || k >= D.n) continue;
+    switch (D.kind) {
+      case KIND_ARROW: check_body<KIND_ARROW, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
+      case KIND_DPR1: check_body<KIND_DPR1, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
+      default: check_body<KIND_SVD, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
+    }
   }
 }
 
+template <int KIND>
+__device__ inline void vec_one(const ProbDesc& D, int t, int mode) {
+  if (mode == 0) {
+    vec_flat<KIND>(D, t);
+  } else {
+    const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
+    const int ct = t / row_tiles;
+    if (mode == 2) vec_tile<KIND, 2>(D, t - ct * row_tiles, ct);
+    else vec_tile<KIND, 1>(D, t - ct * row_tiles, ct);
+  }
+}
+
+// every problem's vectors: its tiles are a contiguous range of blocks
 __global__ __launch_bounds__(BLOCK) void k_b_vec(BatchArgs B) {
   const int p = find_problem(B.vec_start, B.count, (int)blockIdx.x);
   const ProbDesc D = B.descs[p];
-  if (!D.V) return;
-  const int64_t base = (int64_t)((int)blockIdx.x - B.vec_start[p]) * VEC_CHUNK;
+  const int t = (int)blockIdx.x - B.vec_start[p];
+  const int mode = B.vec_mode[p];
   switch (D.kind) {
-    case KIND_ARROW: vec_chunk<KIND_ARROW>(D, base); break;
-    case KIND_DPR1: vec_chunk<KIND_DPR1>(D, base); break;
-    default: vec_chunk<KIND_SVD>(D, base); break;
+    case KIND_ARROW: vec_one<KIND_ARROW>(D, t, mode); break;
+    case KIND_DPR1: vec_one<KIND_DPR1>(D, t, mode); break;
+    default: vec_one<KIND_SVD>(D, t, mode); break;
   }
 }
 
@@ -152,11 +175,12 @@ struct arrow_batch_s {
   int64_t count;
   int flags;
   int32_t total_items, total_vec;
+  int repair_per;       // k_b_repair blocks per problem
   void* dev;            // device block: counters, descriptors, tables, workspaces
   int own_dev;          // dev allocated by the plan
   size_t dev_bytes;
   std::vector<ProbDesc> descs;
-  std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1)
+  std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1), vec_mode (count)
   BatchArgs args;
   int persistent_blocks;
   hipGraph_t graph;
@@ -179,7 +203,7 @@ static Layout plan_layout(int64_t count, const arrow_desc_t* descs) {
   L.off_desc = off;
   off = align_up(off + (size_t)count * sizeof(ProbDesc), 256);
   L.off_tab = off;
-  off = align_up(off + (size_t)(3 * count + 2) * sizeof(int32_t), 256);
+  off = align_up(off + (size_t)(4 * count + 2) * sizeof(int32_t), 256);
   L.off_ws = off;
   for (int64_t p = 0; p < count; ++p) off += align_up(ws_doubles(descs[p].n) * sizeof(double), 256);
   L.total = off;
@@ -268,10 +292,11 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t c) { return descs[a].n > descs[c].n; });
   b->descs.resize((size_t)count);
-  b->tabs.assign((size_t)(3 * count + 2), 0);
+  b->tabs.assign((size_t)(4 * count + 2), 0);
   int32_t* item_start = b->tabs.data();
   int32_t* lanes = item_start + count + 1;
   int32_t* vec_start = lanes + count;
+  int32_t* vec_mode = vec_start + count + 1;
   char* base = (char*)b->dev;
   size_t wsoff = L.off_ws;
   int64_t items = 0, vchunks = 0;
@@ -297,7 +322,17 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     item_start[q] = (int32_t)items;
     items += (a.n + (WAVE / G) - 1) / (WAVE / G);
     vec_start[q] = (int32_t)vchunks;
-    if (D.V) vchunks += ((int64_t)a.n * a.n + VEC_CHUNK - 1) / VEC_CHUNK;
+    if (D.V) {
+      const int64_t n = a.n;
+      if (n < VEC_TALL_MIN) {
+        vec_mode[q] = 0;
+        vchunks += (n * n + VEC_FLAT - 1) / VEC_FLAT;
+      } else {
+        const bool pair = (n % 2 == 0) && (((uintptr_t)D.V & 15) == 0) && (!D.U || (((uintptr_t)D.U & 15) == 0));
+        vec_mode[q] = pair ? 2 : 1;
+        vchunks += ((n + VEC_TILE - 1) / VEC_TILE) * ((n + VEC_COLS - 1) / VEC_COLS);
+      }
+    }
   }
   item_start[count] = (int32_t)items;
   vec_start[count] = (int32_t)vchunks;
@@ -307,6 +342,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     return -2;
   }
   b->total_items = (int32_t)items;
+  b->repair_per = (int)std::max<int64_t>(1, 1024 / count);
   b->total_vec = (int32_t)vchunks;
   hipStream_t st = h->stream;
   if (hipMemcpyAsync(base + L.off_desc, b->descs.data(), (size_t)count * sizeof(ProbDesc), hipMemcpyHostToDevice,
@@ -322,6 +358,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   A.item_start = (const int32_t*)(base + L.off_tab);
   A.lanes = A.item_start + count + 1;
   A.vec_start = A.lanes + count;
+  A.vec_mode = A.vec_start + count + 1;
   A.counters = (uint32_t*)base;
   A.count = (int32_t)count;
   A.total_items = b->total_items;
@@ -340,6 +377,8 @@ static int batch_launch(arrow_batch_s* b, hipStream_t st) {
   hipLaunchKernelGGL(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), 0, st, A);
   hipLaunchKernelGGL((k_b_stage<false>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
   hipLaunchKernelGGL((k_b_stage<true>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
+  hipLaunchKernelGGL(k_b_repair, dim3((unsigned)(b->count * b->repair_per)), dim3(REPAIR_BLOCK), 0, st, A, opt,
+                     b->repair_per);
   if (b->total_vec > 0) hipLaunchKernelGGL(k_b_vec, dim3((unsigned)b->total_vec), dim3(BLOCK), 0, st, A);
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }

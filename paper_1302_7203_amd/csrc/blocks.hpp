@@ -103,4 +103,96 @@ __device__ inline void sort_block(const ProbDesc& D) {
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Eigenvector entries (eq. eigenvecAi, Algorithm 4), streamed to HBM.
+//
+// vec_tile: the block owns rows [rt*VEC_TILE, ...) of columns [ct*VEC_COLS,
+// ...): each thread keeps its rows' d_r and numerators in registers and
+// writes one entry per column.  W = 2 lets a lane write two consecutive rows
+// with one 16-byte non-temporal store (n and the leading dimensions even, V
+// and U 16-byte aligned); W = 1 writes one row per store.
+constexpr int VEC_RPT = 4;                     // rows per thread
+constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
+constexpr int VEC_COLS = 16;                   // columns per block
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+template <int KIND, int W>
+__device__ inline void vec_tile(const ProbDesc& D, int rt, int ct) {
+  static_assert(W == 1 || W == 2, "one or two rows per store");
+  constexpr int PER = VEC_RPT / W;             // stores per column per thread
+  const int n = D.n;
+  const Ws w = ws_view(D.ws, n);
+  double dr[VEC_RPT], num[VEC_RPT];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W + e;
+      const bool body = (KIND == KIND_DPR1) ? (r < n) : (r < n - 1);
+      dr[q * W + e] = body ? D.d[r] : 0.0;
+      num[q * W + e] = body ? ((KIND == KIND_SVD) ? dr[q * W + e] * D.z[r] : D.z[r]) : 0.0;
+    }
+  }
+  const int c0 = ct * VEC_COLS;
+  const int c1 = min(n, c0 + VEC_COLS);
+  for (int col = c0; col < c1; ++col) {
+    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
+    double* vc = D.V + (size_t)col * (size_t)D.ldv;
+    double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
+    const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W;
+      if (r < n) {   // W = 2: n is even, so r + 1 < n as well
+        if constexpr (W == 1) {
+          const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);
+          __builtin_nontemporal_store(v, vc + r);
+          if (KIND == KIND_SVD && uc) __builtin_nontemporal_store(svd_left(D, sigma, v, r), uc + r);
+        } else {
+          const double v0 = vec_entry<KIND>(dr[2 * q], num[2 * q], false, pv, s, mu, inrm);
+          const double v1 = vec_entry<KIND>(dr[2 * q + 1], num[2 * q + 1], r + 1 == n - 1, pv, s, mu, inrm);
+          const v2d vv = {v0, v1};
+          __builtin_nontemporal_store(vv, (v2d*)(vc + r));
+          if (KIND == KIND_SVD && uc) {
+            const v2d uu = {svd_left(D, sigma, v0, r), svd_left(D, sigma, v1, r + 1)};
+            __builtin_nontemporal_store(uu, (v2d*)(uc + r));
+          }
+        }
+      }
+    }
+  }
+}
+
+// vec_flat, for small n (a row tile would leave most threads idle): tile t is
+// the column-major entries [t*VEC_FLAT, (t+1)*VEC_FLAT) of the n x n block
+// (ld = n), BLOCK consecutive entries per step; a thread finds its (row,
+// column) once and then steps it without dividing.
+constexpr int VEC_FLAT = 4096;
+
+template <int KIND>
+__device__ inline void vec_flat(const ProbDesc& D, int t) {
+  const int n = D.n;
+  const Ws w = ws_view(D.ws, n);
+  const int64_t nn = (int64_t)n * n;
+  int64_t e = (int64_t)t * VEC_FLAT + threadIdx.x;
+  if (e >= nn) return;
+  int col = (int)(e / n);
+  int row = (int)(e - (int64_t)col * n);
+  const int q = BLOCK / n, rem = BLOCK - q * n;
+  for (int step = 0; step < VEC_FLAT / BLOCK && e < nn; ++step, e += BLOCK) {
+    const bool body = (KIND == KIND_DPR1) ? true : (row < n - 1);
+    const double dr = body ? D.d[row] : 0.0;
+    const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[row] : D.z[row]) : 0.0;
+    const double v = vec_entry<KIND>(dr, num, row == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
+    __builtin_nontemporal_store(v, D.V + e);
+    if (KIND == KIND_SVD && D.U) __builtin_nontemporal_store(svd_left(D, D.lam[col], v, row), D.U + e);
+    row += rem;
+    col += q;
+    if (row >= n) {
+      row -= n;
+      ++col;
+    }
+  }
+}
+
 }  // namespace ahd

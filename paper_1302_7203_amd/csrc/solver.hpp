@@ -213,14 +213,19 @@ __host__ __device__ inline dd gsum_dd(dd v) {
 // indices below `excl` (f(j, false)) and those above it (f(j, true)); excl
 // itself is skipped.  With excl outside [0, m) there is one run.  Splitting
 // the loop at the excluded pole keeps every iteration free of a per-term test.
+#ifndef AHD_TERM_UNROLL
+#define AHD_TERM_UNROLL 4
+#endif
+constexpr int TERM_UNROLL = AHD_TERM_UNROLL;   // terms per unrolled loop trip
+
 template <int G, class F>
 __host__ __device__ inline void for_terms(int ln, int m, int excl, F&& f) {
   const int cut = (excl >= 0 && excl < m) ? excl : m;
   int j = ln;
-#pragma unroll 4
+#pragma unroll TERM_UNROLL
   for (; j < cut; j += G) f(j, false);
   if (j == excl) j += G;
-#pragma unroll 4
+#pragma unroll TERM_UNROLL
   for (; j < m; j += G) f(j, true);
 }
 

@@ -84,13 +84,13 @@ def _up(nbytes: int) -> int:
 
 # Arena bytes a batch needs once, whatever its size: the plan's counter block and the
 # rounding of its descriptor, table, input and workspace chunks to ALIGN.
-BATCH_OVERHEAD = 6 * ALIGN
+BATCH_OVERHEAD = 8 * ALIGN
 
 
 def request_parts(pr: Problem, vectors=True):
     """(outputs, info, rest): arena bytes of a request's results, of its info words, and of
     its share of the batch's input chunk and plan workspace (inputs, solver workspace,
-    104-byte descriptor and three table words)."""
+    104-byte descriptor and four table words)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
     rest = 16 * _ms(pr) + _up(8 * (16 + 19 * pr.n)) + 128
