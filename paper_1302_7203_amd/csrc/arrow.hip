@@ -210,12 +210,12 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt
   }
 }
 
-// Eigenvector stage (vec_tile in blocks.hpp): a block owns VEC_TILE rows of
-// VEC_COLS consecutive columns.
-template <int KIND, int W>
-__global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles) {
+// Eigenvector stage (vec_tile in blocks.hpp): a block owns BLOCK*RPT rows of
+// `cols` consecutive columns.
+template <int KIND, int W, int RPT>
+__global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles, int cols) {
   const int ct = blockIdx.x / row_tiles;
-  vec_tile<KIND, W>(D, blockIdx.x - ct * row_tiles, ct);
+  vec_tile<KIND, W, RPT>(D, blockIdx.x - ct * row_tiles, ct, cols);
 }
 
 // ---------------------------------------------------------------------------
@@ -293,13 +293,22 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   }
   mark(4);
   if (D.V) {
-    const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
-    const int col_chunks = (D.n + VEC_COLS - 1) / VEC_COLS;
+    const VecShape sh = vec_shape(D.n);
+    const int row_tiles = (int)((D.n + (int64_t)BLOCK * sh.rpt - 1) / ((int64_t)BLOCK * sh.rpt));
+    const int col_chunks = (D.n + sh.cols - 1) / sh.cols;
     const dim3 grid((unsigned)((int64_t)row_tiles * col_chunks));
     const bool pair = (D.n % 2 == 0) && (D.ldv % 2 == 0) && (((uintptr_t)D.V & 15) == 0) &&
                       (!D.U || ((D.ldu % 2 == 0) && (((uintptr_t)D.U & 15) == 0)));
-    if (pair) hipLaunchKernelGGL((k_vec<KIND, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles);
-    else hipLaunchKernelGGL((k_vec<KIND, 1>), grid, dim3(BLOCK), 0, st, D, row_tiles);
+    if (sh.rpt == 8) {
+      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      else hipLaunchKernelGGL((k_vec<KIND, 1, 8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    } else if (sh.rpt == 2) {
+      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      else hipLaunchKernelGGL((k_vec<KIND, 1, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    } else {
+      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      else hipLaunchKernelGGL((k_vec<KIND, 1, 4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    }
   }
   mark(5);
   h->have_last = tm ? 1 : 0;

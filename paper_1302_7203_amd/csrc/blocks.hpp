@@ -106,35 +106,53 @@ __device__ inline void sort_block(const ProbDesc& D) {
 // ---------------------------------------------------------------------------
 // Eigenvector entries (eq. eigenvecAi, Algorithm 4), streamed to HBM.
 //
-// vec_tile: the block owns rows [rt*VEC_TILE, ...) of columns [ct*VEC_COLS,
-// ...): each thread keeps its rows' d_r and numerators in registers and
-// writes one entry per column.  W = 2 lets a lane write two consecutive rows
-// with one 16-byte non-temporal store (n and the leading dimensions even, V
-// and U 16-byte aligned); W = 1 writes one row per store.
-constexpr int VEC_RPT = 4;                     // rows per thread
+// vec_tile: the block owns rows [rt*BLOCK*RPT, ...) of columns [ct*cols,
+// ...): each thread keeps its RPT rows' d_r and numerators in registers and
+// writes one entry per row and column.  W = 2 lets a lane write two
+// consecutive rows with one 16-byte non-temporal store (n and the leading
+// dimensions even, V and U 16-byte aligned); W = 1 writes one row per store.
+// The measured best tile shape depends on n (vec_shape).
+constexpr int VEC_RPT = 4;                     // rows per thread (batched path, and n <= 4096)
 constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
-constexpr int VEC_COLS = 16;                   // columns per block
+constexpr int VEC_COLS = 16;                   // columns per block (batched path)
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-template <int KIND, int W>
-__device__ inline void vec_tile(const ProbDesc& D, int rt, int ct) {
+struct VecShape {
+  int rpt, cols;
+};
+
+// rows per thread and columns per block for a single problem of order n:
+// tall tiles for large n, wide ones around n = 4096, and for smaller n narrow
+// ones so that the grid keeps a few hundred blocks
+__host__ __device__ inline VecShape vec_shape(int64_t n) {
+  if (n > 4096) return VecShape{8, 16};
+  if (n > 2048) return VecShape{4, 32};
+  if (n > 1024) return VecShape{4, 8};
+  if (n > 512) return VecShape{4, 4};
+  return VecShape{2, n >= 512 ? 2 : 1};
+}
+
+template <int KIND, int W, int RPT = VEC_RPT>
+__device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VEC_COLS) {
   static_assert(W == 1 || W == 2, "one or two rows per store");
-  constexpr int PER = VEC_RPT / W;             // stores per column per thread
+  static_assert(RPT % W == 0, "rows per thread");
+  constexpr int PER = RPT / W;                 // stores per column per thread
+  constexpr int TILE = BLOCK * RPT;
   const int n = D.n;
   const Ws w = ws_view(D.ws, n);
-  double dr[VEC_RPT], num[VEC_RPT];
+  double dr[RPT], num[RPT];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
 #pragma unroll
     for (int e = 0; e < W; ++e) {
-      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W + e;
+      const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W + e;
       const bool body = (KIND == KIND_DPR1) ? (r < n) : (r < n - 1);
       dr[q * W + e] = body ? D.d[r] : 0.0;
       num[q * W + e] = body ? ((KIND == KIND_SVD) ? dr[q * W + e] * D.z[r] : D.z[r]) : 0.0;
     }
   }
-  const int c0 = ct * VEC_COLS;
-  const int c1 = min(n, c0 + VEC_COLS);
+  const int c0 = ct * cols;
+  const int c1 = min(n, c0 + cols);
   for (int col = c0; col < c1; ++col) {
     const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
     double* vc = D.V + (size_t)col * (size_t)D.ldv;
@@ -142,7 +160,7 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct) {
     const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int r = rt * VEC_TILE + q * BLOCK * W + threadIdx.x * W;
+      const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W;
       if (r < n) {   // W = 2: n is even, so r + 1 < n as well
         if constexpr (W == 1) {
           const double v = vec_entry<KIND>(dr[q], num[q], r == n - 1, pv, s, mu, inrm);

@@ -110,6 +110,39 @@ def test_uniform_16384_sampled(gpu, oracle_lib):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("kind", [W.KIND_ARROW, W.KIND_DPR1, W.KIND_SVD])
+def test_odd_order_above_4096_sampled(gpu, kind, oracle_lib):
+    """n = 5001: the tall vector tiles with one row per store (odd n), for every kind."""
+    torch, binding, _ = gpu
+    rng = np.random.default_rng(5001 + kind)
+    n = 5001
+    if kind == W.KIND_ARROW:
+        pr = W.uniform_arrow(n, rng)
+        out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+        ks = np.unique(np.r_[0, 1, 2500, n - 2, n - 1, rng.integers(0, n, 12)])
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+        rl, rV, V = ref.lam, ref.vec, out.V
+    elif kind == W.KIND_DPR1:
+        pr = W.dpr1(n, rng)
+        out = binding.dpr1_eig(torch.from_numpy(pr.d).cuda(), torch.from_numpy(pr.z).cuda(), pr.scalar)
+        ks = np.unique(np.r_[0, 1, 2500, n - 2, n - 1, rng.integers(0, n, 12)])
+        ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar, ks=ks)
+        rl, rV, V = ref.lam, ref.vec, out.V
+    else:
+        pr = W.svd_arrow(n, rng)
+        out = binding.arrow_svd(torch.from_numpy(pr.d).cuda(), torch.from_numpy(pr.z).cuda(), pr.scalar)
+        ks = np.unique(np.r_[0, 1, 2500, n - 2, n - 1, rng.integers(0, n, 12)])
+        ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar, ks=ks)
+        rl, rV, V = ref.sigma, ref.V, out.V
+        assert_close(out.U[:, torch.from_numpy(ks).cuda()].cpu().numpy(), ref.U, "U columns")
+    torch.cuda.synchronize()
+    kt = torch.from_numpy(ks).to(out.lam.device)
+    assert_close(out.lam[kt].cpu().numpy(), rl, "values")
+    assert_close(V[:, kt].cpu().numpy(), rV, "vector columns")
+    del out
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
 def test_every_lane_count(gpu, lanes, oracle_lib):
     _, binding, _ = gpu
