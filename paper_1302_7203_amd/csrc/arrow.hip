@@ -188,30 +188,31 @@ __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
 }
 
 // The eigenvalues k_check deferred (Remarks 1 and 2, the DPR1 re-measure),
-// one block of REPAIR_BLOCK lanes each: the repairs are a handful of
-// eigenvalues with several O(n) passes apiece, so they get whole blocks and
-// their own launch instead of stretching k_check.  Blocks beyond the list
-// length exit at once; the rest loop over the list.
+// GR lanes each (GR = REPAIR_BLOCK: a block per eigenvalue; GR = 64: a
+// wavefront per eigenvalue, REPAIR_BLOCK/64 of them sharing the block's staged
+// arrays): the repairs are a handful of eigenvalues with several O(n) passes
+// apiece, so they get their own launch instead of stretching k_check.
+// Groups beyond the list length skip the work.
 constexpr int REPAIR_BLOCK = 256;
 
-template <int KIND, bool STAGE>
+template <int KIND, bool STAGE, int GR>
 __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt) {
   extern __shared__ double lds[];
+  constexpr int PER = REPAIR_BLOCK / GR;       // repairs per block
   const Ws w = ws_view(D.ws, D.n);
   const uint32_t count = min(*repair_count(w), (uint32_t)D.n);
-  if (blockIdx.x >= count) return;
+  if (blockIdx.x * PER >= count) return;
   if constexpr (STAGE) stage_hot(D, lds);
   const uint32_t* list = repair_list(w, D.n);
-  for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+  const int grp = threadIdx.x / GR, ln = threadIdx.x % GR;
+  for (uint32_t q = blockIdx.x * PER + grp; q < count; q += gridDim.x * PER) {
     const int k = (int)list[q];
     if (k < 0 || k >= D.n) continue;
-    if constexpr (STAGE) check_body<KIND, REPAIR_BLOCK, true>(D, opt, k, threadIdx.x, lds, lds + sorted_count(D));
-    else check_body<KIND, REPAIR_BLOCK>(D, opt, k, threadIdx.x);
+    if constexpr (STAGE) check_body<KIND, GR, true>(D, opt, k, ln, lds, lds + sorted_count(D));
+    else check_body<KIND, GR>(D, opt, k, ln);
   }
 }
 
-// Eigenvector stage (vec_tile in blocks.hpp): a block owns BLOCK*RPT rows of
-// `cols` consecutive columns.
 template <int KIND, int W, int RPT>
 __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles, int cols) {
   const int ct = blockIdx.x / row_tiles;
@@ -287,9 +288,10 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   {
     // deferred repairs; the block reductions add a little static LDS
     const size_t lds_r = (hot + 4096 <= h->lds_max) ? hot : 0;
-    const dim3 grid((unsigned)std::min<int64_t>(D.n, h->cus));
-    if (lds_r > 0) hipLaunchKernelGGL((k_repair<KIND, true>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
-    else hipLaunchKernelGGL((k_repair<KIND, false>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
+    constexpr int GR = REPAIR_BLOCK;   // a block per repair (measured faster than a wavefront for n >= 4096)
+    const dim3 grid((unsigned)std::min<int64_t>((D.n + REPAIR_BLOCK / GR - 1) / (REPAIR_BLOCK / GR), h->cus));
+    if (lds_r > 0) hipLaunchKernelGGL((k_repair<KIND, true, GR>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
+    else hipLaunchKernelGGL((k_repair<KIND, false, GR>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
   }
   mark(4);
   if (D.V) {

@@ -279,7 +279,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     if (quot > opt.tau_zero && !zero_pole) {
       // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
       int z0 = 0, it = 0;
-      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root);
+      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root, 1.0 / lam1);
       pv = 0.0; s = 0.0; mu = z0 ? 0.0 : m2;
       fl |= INFO_NEAR_ZERO;
       c_it += it; c_dd += 1;
@@ -301,8 +301,11 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
           const BPass bp = b_pass<KIND, G>(P, i2, -side, ln, opt.fp64_b);
           int it = 0;
           const int side2 = -side;
+          // first-pass lambda seen from the other pole: 1 / (lambda - d_i2)
+          const double nu_est = 1.0 / (pdiff<KIND>(di, d2) + mu);
           const double nu = (opt.root == ROOT_RATIONAL)
-              ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it)
+              ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it,
+                                          nu_est)
               : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
           pv = d2; s = 0.0; mu = 1.0 / nu;
           fl |= INFO_REMEDY_A;
@@ -315,7 +318,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
         // 2^-10 |mu| away from lambda
         s = mu - mu * (1.0 / 1024.0);
         int z0 = 0, it = 0;
-        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root);
+        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s));
         pv = di; mu = z0 ? 0.0 : m2;
         fl |= INFO_REMEDY_B;
         c_it += it; c_dd += 1;

@@ -482,7 +482,8 @@ __host__ __device__ inline double rational_next(double x, double h, double hnois
 // extreme eigenvalue of A_i^{-1} on the given side, by the rational iteration
 template <int KIND, int G>
 __host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
-                                                   double hi, double ymax_nu, int ln, int* iters) {
+                                                   double hi, double ymax_nu, int ln, int* iters,
+                                                   double nu_est = NAN) {
   const double sg = (double)side;
   const double di = P.ds[i];
   const double rci = 1.0 / P.ch[i];
@@ -507,6 +508,10 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
       hi_open = 1;
     }
   }
+  // an estimate (a repair re-solving a known eigenvalue from another shift)
+  // inside the bracket is the better start
+  const double x_est = sg * nu_est;
+  if (x_est > xlo && x_est < xhi) x = x_est;
   int it = 0;
   double prev_step = INFINITY;
   for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
@@ -546,7 +551,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
 
 template <int KIND, int G>
 __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double s, int ln, int* zero,
-                                               int* iters, int method) {
+                                               int* iters, int method, double nu_est = NAN) {
   const int m = P.m;
   dd fs = {0.0, 0.0};
   double usum = 0.0, dmx = -INFINITY, dmn = INFINITY;
@@ -582,6 +587,8 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
     const double y = (rho > 0) ? lo : -hi;
     const double c0 = -1.0 / fabs(rho);
     double x = xhi;
+    const double x_est = sg * nu_est;   // a known estimate inside the bracket is the better start
+    if (x_est > xlo && x_est < xhi) x = x_est;
     double prev_step = INFINITY;
     for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
       const double nu = sg * x;
