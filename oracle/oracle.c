@@ -41,6 +41,7 @@
  *
  * No code here follows the printed listings of the paper.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -239,10 +240,12 @@ typedef struct { double key; int64_t idx; } keyed_t;
 
 static int cmp_desc(const void *a, const void *b) {
   double x = ((const keyed_t *)a)->key, y = ((const keyed_t *)b)->key;
-  return (x > y) ? -1 : (x < y) ? 1 : 0;
+  int64_t i = ((const keyed_t *)a)->idx, j = ((const keyed_t *)b)->idx;
+  return (x > y) ? -1 : (x < y) ? 1 : (i < j) ? -1 : (i > j) ? 1 : 0;
 }
 
-/* order[i] = caller index of the i-th largest key; 1 if two keys are equal. */
+/* order[i] = caller index of the i-th largest key (equal keys in caller
+ * order); returns 1 if two keys are equal. */
 static int sort_desc(int64_t m, const double *key, int64_t *order) {
   keyed_t *t = (keyed_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof *t);
   if (!t) return -100;
@@ -265,7 +268,194 @@ static void set_threads(int nthreads) {
 #endif
 }
 
-static int finite(double x) { return x == x && x - x == 0; }
+static int finite_d(double x) { return x == x && x - x == 0; }
+
+/*
+ * Reducible arrowhead (Sec. 1): some z_j = 0 or some d_i = d_j.
+ *
+ *   - z_j = 0: d_j is an eigenvalue, eigenvector the unit vector e_j; row and
+ *     column j are deleted.
+ *   - d_i = d_j: a rotation in the (i, j) plane sends z_j to 0 and z_i to
+ *     hypot(z_i, z_j); then d_j is deflated as above, with the rotated-out
+ *     direction as its eigenvector.
+ *
+ * Conventions (there is a whole eigenspace to choose from, so they are
+ * stated): equal poles are visited in caller order; the first with a nonzero
+ * z absorbs the others one at a time; the eigenvector left by absorbing z_t
+ * into the accumulated direction u (norm rho) is (z_t u - rho e_t) / hypot,
+ * so its entry on row t is negative.  The eigenvalues of the deleted rows are
+ * merged with those of the irreducible rest in descending order; on equal
+ * double values the eigenvalue of the irreducible rest comes first.  The
+ * rest's eigenvectors are eq. (Aeigenvec) over all caller rows, which the
+ * rotations carry back exactly: z_j / (d_j - l) on each merged pole, 0 where
+ * z_j = 0.  A deflated pair reports tau = 0 and pole = its own row.
+ */
+typedef struct {
+  double value;
+  int64_t row;     /* caller row of the deflated member */
+  int64_t first;   /* sorted position of the run's first nonzero member, -1: unit vector */
+  int64_t pos;     /* sorted position of the member */
+} defl_t;
+
+static int arrow_eig_reducible(int64_t n, const double *d, const double *z, double alpha,
+                               const int64_t *order, int64_t nk, const int64_t *ks,
+                               double *lam, double *lam_lo, double *tau, double *tau_lo,
+                               int64_t *pole, double *V, double *relerr) {
+  const int64_t m = n - 1;
+  R *dq = (R *)malloc((size_t)m * sizeof *dq);
+  R *cq = (R *)malloc((size_t)m * sizeof *cq);
+  int64_t *rep = (int64_t *)malloc((size_t)m * sizeof *rep);
+  defl_t *it = (defl_t *)malloc((size_t)m * sizeof *it);
+  int64_t *src = (int64_t *)malloc((size_t)n * sizeof *src);   /* column -> root k >= 0, or -1 - item */
+  if (!dq || !cq || !rep || !it || !src) {
+    free(dq); free(cq); free(rep); free(it); free(src);
+    return -100;
+  }
+  int64_t mr = 0, nd = 0;
+  for (int64_t j = 0; j < m;) {
+    int64_t e = j;
+    while (e < m && d[order[e]] == d[order[j]]) ++e;
+    int64_t first = -1;
+    R c = 0;
+    for (int64_t q = j; q < e; ++q) {
+      double zq = z[order[q]];
+      if (zq == 0) {
+        defl_t t = { d[order[q]], order[q], -1, q };
+        it[nd++] = t;
+      } else if (first < 0) {
+        first = q;
+        c = (R)zq * (R)zq;
+      } else {
+        defl_t t = { d[order[q]], order[q], first, q };
+        it[nd++] = t;
+        c += (R)zq * (R)zq;
+      }
+    }
+    if (first >= 0) {
+      dq[mr] = (R)d[order[j]];
+      cq[mr] = c;
+      rep[mr] = order[first];
+      ++mr;
+    }
+    j = e;
+  }
+  /* the irreducible rest */
+  R zsum = 0, up = (R)alpha, lowb = (R)alpha;
+  for (int64_t j = 0; j < mr; ++j) {
+    R zz = sqrtq(cq[j]);
+    zsum += zz;
+    if (dq[j] + zz > up) up = dq[j] + zz;
+    if (dq[j] - zz < lowb) lowb = dq[j] - zz;
+  }
+  if ((R)alpha + zsum > up) up = (R)alpha + zsum;
+  if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
+  secular_t sec = { KIND_ARROW, mr, dq, cq, (R)alpha };
+  /* Merge: both lists descend; on equal double values the rest's eigenvalue
+   * comes first.  Item s goes to column s + c_s, c_s = number of roots whose
+   * double rounding is >= delta_s = number of roots above x, the midpoint of
+   * delta_s and the next double below it.  With P poles above x, that is P,
+   * plus 1 if the root in x's interval lies above x, i.e. if f(x) > 0 (f
+   * decreases on each interval).  A sign lost in rounding error is settled by
+   * solving that root.  The rest's roots fill the other columns in order. */
+  int64_t *cs = (int64_t *)malloc((size_t)(nd > 0 ? nd : 1) * sizeof *cs);
+  if (!cs) { free(dq); free(cq); free(rep); free(it); free(src); return -100; }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t b = 0; b < nd; ++b) {
+    double v = it[b].value;
+    R x = (R)v / 2 + (R)nextafter(v, -INFINITY) / 2;
+    int64_t P = 0;
+    while (P < mr && dq[P] > x) ++P;
+    R err;
+    R g = g_plain(&sec, x, &err);
+    int64_t c = P;
+    if (g > err) c = P + 1;
+    else if (g >= -err) {
+      root_t r;
+      if (mr == 0) r.lam = (R)alpha;
+      else solve_root(&sec, P, up, lowb, &r);
+      if ((double)r.lam >= v) c = P + 1;
+    }
+    cs[b] = c;
+  }
+  for (int64_t col = 0; col < n; ++col) src[col] = 0;
+  for (int64_t b = 0; b < nd; ++b) src[b + cs[b]] = -1 - b;
+  for (int64_t col = 0, a = 0; col < n; ++col)
+    if (src[col] >= 0) src[col] = a++;
+  free(cs);
+  int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t col = ks ? ks[i] : i;
+    double *out = V ? V + i * n : NULL;
+    if (src[col] >= 0) {
+      root_t rr;
+      if (mr == 0) {
+        rr.p = -1; rr.tau = (R)alpha; rr.lam = (R)alpha; rr.relerr = 0;
+      } else {
+        solve_root(&sec, src[col], up, lowb, &rr);
+      }
+      const root_t *r = &rr;
+      if (lam || lam_lo) split(r->lam, lam ? &lam[i] : NULL, lam_lo ? &lam_lo[i] : NULL);
+      if (tau || tau_lo) split(r->tau, tau ? &tau[i] : NULL, tau_lo ? &tau_lo[i] : NULL);
+      if (pole) pole[i] = r->p >= 0 ? rep[r->p] : -1;
+      if (relerr) relerr[i] = r->relerr;
+      if (out) {
+        R dp = r->p >= 0 ? dq[r->p] : 0, nrm2 = 1;
+        for (int64_t j = 0; j < m; ++j) {
+          if (z[j] == 0) continue;
+          R x = (R)z[j] / (((R)d[j] - dp) - r->tau);
+          nrm2 += x * x;
+        }
+        R nrm = sqrtq(nrm2);
+        for (int64_t j = 0; j < m; ++j)
+          out[j] = z[j] == 0 ? 0.0 : (double)(((R)z[j] / (((R)d[j] - dp) - r->tau)) / nrm);
+        out[m] = (double)(-1 / nrm);
+      }
+    } else {
+      const defl_t *t = &it[-1 - src[col]];
+      if (lam) lam[i] = t->value;
+      if (lam_lo) lam_lo[i] = 0;
+      if (tau) tau[i] = 0;
+      if (tau_lo) tau_lo[i] = 0;
+      if (pole) pole[i] = t->row;
+      if (relerr) relerr[i] = 0;
+      if (out) {
+        for (int64_t j = 0; j < n; ++j) out[j] = 0;
+        if (t->first < 0) {
+          out[t->row] = 1.0;
+        } else {
+          /* absorb the run's nonzero members before t into u, one rotation each */
+          R *u = (R *)calloc((size_t)m, sizeof *u);
+          if (!u) {
+#pragma omp atomic write
+            fail = 1;
+            continue;
+          }
+          int64_t f = order[t->first];
+          R rho = fabsq((R)z[f]);
+          u[f] = z[f] > 0 ? 1 : -1;
+          for (int64_t q = t->first + 1; q < t->pos; ++q) {
+            int64_t row = order[q];
+            if (z[row] == 0) continue;
+            R h = sqrtq(rho * rho + (R)z[row] * (R)z[row]);
+            R cs = rho / h, sn = (R)z[row] / h;
+            for (int64_t j = 0; j < m; ++j) u[j] *= cs;
+            u[row] += sn;
+            rho = h;
+          }
+          int64_t row = order[t->pos];
+          R h = sqrtq(rho * rho + (R)z[row] * (R)z[row]);
+          R cs = rho / h, sn = (R)z[row] / h;
+          for (int64_t j = 0; j < m; ++j) out[j] = (double)(sn * u[j]);
+          out[row] = (double)(-cs);
+          free(u);
+        }
+      }
+    }
+  }
+  free(dq); free(cq); free(rep); free(it); free(src);
+  return fail ? -100 : 0;
+}
 
 /*
  * Arrowhead eigenpairs.  d, z: n-1 entries in any order; alpha: corner.
@@ -278,17 +468,19 @@ static int finite(double x) { return x == x && x - x == 0; }
  *                 rows in caller order, last row = the corner coordinate,
  *                 sign fixed by x_n = -1 (eq. Aeigenvec)
  *   relerr        relative uncertainty of the located zero
- * Returns 0, -1 bad argument, 1 reducible (zero z_j or repeated d_j).
+ * A reducible matrix (zero z_j or repeated d_j) is deflated first, as
+ * described at arrow_eig_reducible.  Returns 0, or -1 for a bad argument.
  */
 int oracle_arrow_eig(int64_t n, const double *d, const double *z, double alpha,
                      int64_t nk, const int64_t *ks,
                      double *lam, double *lam_lo, double *tau, double *tau_lo,
                      int64_t *pole, double *V, double *relerr, int nthreads) {
-  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(alpha)) return -1;
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(alpha)) return -1;
   const int64_t m = n - 1;
+  int zero = 0;
   for (int64_t j = 0; j < m; ++j) {
-    if (!finite(d[j]) || !finite(z[j])) return -1;
-    if (z[j] == 0) return 1;
+    if (!finite_d(d[j]) || !finite_d(z[j])) return -1;
+    if (z[j] == 0) zero = 1;
   }
   for (int64_t i = 0; i < nk; ++i) {
     int64_t k = ks ? ks[i] : i;
@@ -311,7 +503,13 @@ int oracle_arrow_eig(int64_t n, const double *d, const double *z, double alpha,
   R *cq = (R *)malloc((size_t)m * sizeof *cq);
   if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
   int dup = sort_desc(m, d, order);
-  if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  if (dup < 0) { free(order); free(dq); free(cq); return dup; }
+  if (dup || zero) {
+    set_threads(nthreads);
+    int rc = arrow_eig_reducible(n, d, z, alpha, order, nk, ks, lam, lam_lo, tau, tau_lo, pole, V, relerr);
+    free(order); free(dq); free(cq);
+    return rc;
+  }
   R zsum = 0, up = -1e4000Q, lowb = 1e4000Q;
   for (int64_t j = 0; j < m; ++j) {
     dq[j] = (R)d[order[j]];
@@ -366,9 +564,9 @@ int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
                     int64_t nk, const int64_t *ks,
                     double *lam, double *lam_lo, double *tau, double *tau_lo,
                     int64_t *pole, double *Q, double *relerr, int nthreads) {
-  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(rho) || !(rho > 0)) return -1;
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(rho) || !(rho > 0)) return -1;
   for (int64_t j = 0; j < n; ++j) {
-    if (!finite(d[j]) || !finite(u[j])) return -1;
+    if (!finite_d(d[j]) || !finite_d(u[j])) return -1;
     if (u[j] == 0) return 1;
   }
   for (int64_t i = 0; i < nk; ++i) {
@@ -431,10 +629,10 @@ int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
                      int64_t nk, const int64_t *ks,
                      double *sigma, double *sigma_lo, double *U, double *V,
                      double *relerr, int nthreads) {
-  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite(alpha)) return -1;
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(alpha)) return -1;
   const int64_t m = n - 1;
   for (int64_t j = 0; j < m; ++j) {
-    if (!finite(d[j]) || !finite(z[j])) return -1;
+    if (!finite_d(d[j]) || !finite_d(z[j])) return -1;
     if (z[j] == 0 || d[j] == 0) return 1;
   }
   for (int64_t i = 0; i < nk; ++i) {

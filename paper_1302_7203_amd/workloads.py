@@ -16,6 +16,7 @@ only by ranges), so these laws stand in for its workloads:
             [1e-8, 1]; alpha = 1e-3  (forces the double-double element b)
   dpr1      d as ``uniform``, u = g/||g|| with g ~ N(0, I), rho ~ U(0.1, 10)
   svd       d ~ U(0, 1) sorted with min gap >= 1e-6, z ~ U(0.1, 1), alpha ~ U(0, 1)
+  reducible ``uniform`` with some z_j = 0, repeated poles and signed z, shuffled
 """
 from __future__ import annotations
 
@@ -150,6 +151,26 @@ def serving_requests(count=2200, nmin=32, nmax=8192, rate=1.0, seed=SEED_BASE + 
             pr = svd_arrow(n, rng)
         out.append((t, pr))
     return out
+
+
+def reducible_arrow(n, rng, zero_frac=0.1, repeat_every=97, triple=True):
+    """A reducible arrowhead (Sec. 1) in random order: ``uniform`` poles and
+    shaft, then a fraction ``zero_frac`` of the shaft entries set to 0 (random
+    signs on the rest), every ``repeat_every``-th pole repeated in the next
+    slot, and, if ``triple``, one pole taken three times."""
+    m = n - 1
+    d = _sorted_with_gap(rng, m, -1.0, 1.0)
+    z = rng.uniform(0.1, 1.0, m) * rng.choice([-1.0, 1.0], m)
+    if m > 0:
+        z[rng.choice(m, int(zero_frac * m), replace=False)] = 0.0
+    for i in range(0, m - 1, repeat_every):
+        d[i + 1] = d[i]
+    if triple and m >= 8:
+        c = m // 2
+        d[c + 1] = d[c + 2] = d[c]
+    perm = rng.permutation(m)
+    alpha = float(rng.uniform(-1.0, 1.0))
+    return Problem(KIND_ARROW, n, d[perm].copy(), z[perm].copy(), alpha)
 
 
 def shuffled(pr: Problem, seed: int) -> Problem:

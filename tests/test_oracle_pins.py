@@ -256,11 +256,81 @@ def test_special_and_invariances(oracle_lib):
     assert np.array_equal(fl.vec[other], base.vec[other])
 
 
-def test_reducible_rejected(oracle_lib):
-    with pytest.raises(oracle.oracle.OracleError):
-        oracle.arrow_eig(np.array([1.0, 1.0]), np.array([1.0, 2.0]), 0.0)
-    with pytest.raises(oracle.oracle.OracleError):
-        oracle.arrow_eig(np.array([1.0, 2.0]), np.array([0.0, 2.0]), 0.0)
+# ---------------------------------------------------------------------------
+# reducible input (Sec. 1): deflation
+
+# (d, z, alpha): unsorted, with a zero shaft entry and a pole taken three
+# times; a diagonal matrix; all poles equal; a zero pole with a zero shaft
+# entry beside an equal pair
+REDUCIBLE = [
+    (np.array([1.0, 3.0, 1.0, 0.5, 1.0, -2.0]), np.array([2.0, 1.0, -1.5, 3.0, 0.25, 0.0]), 0.3),
+    (np.array([0.5, -1.0, 2.0]), np.array([0.0, 0.0, 0.0]), 0.7),
+    (np.array([2.0, 2.0, 2.0, 2.0]), np.array([1.0, -2.0, 0.5, 3.0]), -1.0),
+    (np.array([0.0, 1.0, 0.0, 1.0]), np.array([0.0, 1.0, 1.0, 2.0]), 0.0),
+]
+_EXACT = {}
+
+
+def _exact_reducible(i):
+    if i not in _EXACT:
+        d, z, a = REDUCIBLE[i]
+        _EXACT[i] = brute.exact_eigvals(brute.dense_arrow(d, z, a))
+    return _EXACT[i]
+
+
+def _deflation_failures(i, r):
+    """What the mathematics fixes for REDUCIBLE[i] and the oracle's result r."""
+    d, z, a = REDUCIBLE[i]
+    n = d.size + 1
+    bad = []
+    for k, e in enumerate(_exact_reducible(i)):       # rounded once: within half an ulp
+        if abs(F(r.lam[k]) - e) > abs(e) * Fraction(1, 2 ** 53) + Fraction(1, 2 ** 399):   # the bisection floor
+            bad.append(f"lambda_{k}")
+    A = brute.arrow_np(d, z, a).astype(np.longdouble)
+    V = r.vec.astype(np.longdouble)
+    tol = 4 * n * 2.0 ** -53
+    if np.max(np.abs(V.T @ V - np.eye(n))) > tol:
+        bad.append("orthonormal")
+    if np.max(np.abs(A @ V - V * r.lam.astype(np.longdouble))) > tol * float(np.max(np.abs(A))):
+        bad.append("residual")
+    # z_j = 0: the eigenpair (d_j, e_j)
+    for j in np.flatnonzero(z == 0):
+        e = np.zeros(n)
+        e[j] = 1.0
+        if not any(r.lam[k] == d[j] and np.array_equal(r.vec[:, k], e) for k in range(n)):
+            bad.append(f"unit vector e_{j}")
+    for k in range(n):
+        p = int(r.pole[k])
+        if r.tau[k] == 0 and p >= 0 and z[p] != 0:
+            # a direction removed from a run of equal poles: supported on the
+            # run, negative on its own row
+            off = (d != d[p]) & (r.vec[:-1, k] != 0)
+            if off.any() or r.vec[-1, k] != 0 or not r.vec[p, k] < 0:
+                bad.append(f"rotation vector {k}")
+        elif r.tau[k] != 0 and not r.vec[-1, k] < 0:
+            bad.append(f"corner sign {k}")
+    return bad
+
+
+@pytest.mark.parametrize("i", range(len(REDUCIBLE)))
+def test_deflation_pins(i, oracle_lib):
+    d, z, a = REDUCIBLE[i]
+    r = oracle.arrow_eig(d, z, a)
+    assert _deflation_failures(i, r) == []
+
+
+def test_deflation_larger_random(oracle_lib):
+    """n = 60 with zero shaft entries and repeated poles: against mpmath's dense solver at 40 digits."""
+    pr = W.reducible_arrow(60, np.random.default_rng(31), zero_frac=0.15, repeat_every=7)
+    r = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    lam, _ = brute.mp_eigsy(brute.arrow_np(pr.d, pr.z, pr.scalar), dps=40)
+    for k in range(pr.n):
+        assert abs(mp.mpf(float(r.lam[k])) - lam[k]) <= abs(lam[k]) * mp.mpf(2.0 ** -53) + mp.mpf("1e-30")
+    A = brute.arrow_np(pr.d, pr.z, pr.scalar).astype(np.longdouble)
+    V = r.vec.astype(np.longdouble)
+    assert np.max(np.abs(V.T @ V - np.eye(pr.n))) < 1e-14
+    assert np.max(np.abs(A @ V - V * r.lam.astype(np.longdouble))) < 1e-14
+    assert np.all(np.diff(r.lam) <= 0)
 
 
 # ---------------------------------------------------------------------------
@@ -356,7 +426,11 @@ _MUTANTS = {
     "dpr1_dropped_rho": ("cq[j] = (R)rho * (uu * uu);", "cq[j] = (uu * uu);"),
     "svd_corner_alpha_not_squared": ("R corner = (R)alpha * (R)alpha,", "R corner = (R)alpha,"),
     "svd_u_times_d": ("uc[j] = (double)(sg * v / dj);", "uc[j] = (double)(sg * v * dj);"),
-    "ascending_order": ("return (x > y) ? -1 : (x < y) ? 1 : 0;", "return (x < y) ? -1 : (x > y) ? 1 : 0;"),
+    "ascending_order": ("return (x > y) ? -1 : (x < y) ? 1 :", "return (x < y) ? -1 : (x > y) ? 1 :"),
+    "deflation_rotation_sign": ("out[row] = (double)(-cs);", "out[row] = (double)(cs);"),
+    "deflation_weight_dropped": ("c += (R)zq * (R)zq;", "c += 0;"),
+    "deflation_unit_row_sorted": ("out[t->row] = 1.0;", "out[t->pos] = 1.0;"),
+    "deflation_merge_count": ("if (g > err) c = P + 1;", "if (g < -err) c = P + 1;"),
     "vector_tau_sign": ("R x = (R)z[j] / (((R)d[j] - dp) - r.tau);\n        col[j]",
                         "R x = (R)z[j] / (((R)d[j] - dp) + r.tau);\n        col[j]"),
 }
@@ -406,8 +480,20 @@ def _quick_pins(lib):
     return failed
 
 
+def _quick_deflation_pins(lib):
+    failed = []
+    for i in range(len(REDUCIBLE)):
+        d, z, a = REDUCIBLE[i]
+        try:
+            if _deflation_failures(i, oracle.arrow_eig(d, z, a, lib=lib)):
+                failed.append(f"deflation {i}")
+        except oracle.oracle.OracleError:
+            failed.append(f"deflation {i} error")
+    return failed
+
+
 def test_pins_catch_planted_mistakes(oracle_lib):
-    assert _quick_pins(None) == []
+    assert _quick_pins(None) == [] and _quick_deflation_pins(None) == []
     src = open(os.path.join(os.path.dirname(oracle.oracle.__file__), "oracle.c")).read()
     tmp = tempfile.mkdtemp(prefix="oracle_mut_")
     try:
@@ -418,6 +504,6 @@ def test_pins_catch_planted_mistakes(oracle_lib):
                 f.write(src.replace(old, new))
             so = os.path.join(tmp, f"lib_{name}.so")
             subprocess.run(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-o", so, path, "-lquadmath"], check=True)
-            assert _quick_pins(so) != [], f"planted mistake '{name}' not caught"
+            assert _quick_pins(so) + _quick_deflation_pins(so) != [], f"planted mistake '{name}' not caught"
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
