@@ -48,12 +48,14 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_INFO_REMEDY_A 2u    /* shifted to the other neighbouring pole (Remark 2(a)) */
 #define ARROW_INFO_REMEDY_B 4u    /* DPR1 inverse at a shift near lambda (Remark 2(b)) */
 #define ARROW_INFO_NEAR_ZERO 8u   /* eigenvalue closest to 0 taken from A^{-1} (Remark 1) */
-#define ARROW_INFO_REDUCIBLE 16u  /* some z_j = 0 or d_i = d_j (Sec. 1): not solved, outputs NaN */
+#define ARROW_INFO_REDUCIBLE 16u  /* dpr1_eig / arrow_svd: some z_j = 0 or d_i = d_j (Sec. 1):
+                                     not solved, outputs NaN (arrow_eig deflates instead) */
 #define ARROW_INFO_NONFINITE 32u  /* non-finite input: not solved, outputs NaN */
 #define ARROW_INFO_KB_LARGE 64u   /* K_b (eq. K2) beyond what double-double resolves */
 #define ARROW_INFO_KNU_LARGE 128u /* reserved */
 #define ARROW_INFO_BAD_INPUT 256u /* arrow_svd: some d_j = 0: not solved, outputs NaN */
 #define ARROW_INFO_POLE_SHIFT 512u /* dpr1_eig: smallest eigenvalue measured from the pole d_n */
+#define ARROW_INFO_DEFLATED 1024u  /* arrow_eig: eigenpair deflated from a reducible matrix (Sec. 1) */
 
 /* options for arrow_set_option */
 #define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 10) */
@@ -96,6 +98,17 @@ size_t arrow_workspace_size(int64_t n);
  *           real arithmetic, where shift_k is the pole the eigenvalue was
  *           computed from (Remark 3); this pair carries ~32 digits.
  *   info:   optional, n uint32 ARROW_INFO_* bits.
+ * Reducible input (Sec. 1: some z_j = 0, or d_i = d_j) is deflated on the
+ * device: a pole d_j with z_j = 0 is an eigenvalue with the unit vector e_j;
+ * r > 1 equal poles with nonzero z are merged by rotations into one pole
+ * with shaft (sum z^2)^(1/2), and the r - 1 directions the rotations remove
+ * are eigenvectors for that pole: for the run's t-th nonzero member
+ * (sorted order, ties in caller order), entries z_i z_t / (R_{t-1} R_t) on
+ * the run's earlier rows and -R_{t-1}/R_t on its own row, R_t^2 = sum of
+ * z_i^2 up to t.  These eigenpairs carry ARROW_INFO_DEFLATED, shift = the
+ * pole, mu = 0.  The irreducible rest is solved as above, its vectors given
+ * by eq. (Aeigenvec) on every row (0 where z_j = 0).  Columns are the merge
+ * of both sets in descending order; on equal values the solved one first.
  */
 int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
               double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info);

@@ -3,12 +3,14 @@
 // One call runs these launches on the handle's stream:
 //   k_front     sortedness check; for sorted input also the copy to the
 //               workspace and the prologue: shaft weights and corner of the
-//               (reduced) arrowhead in double-double
+//               (reduced) arrowhead in double-double, and the deflation of a
+//               reducible arrowhead (Sec. 1)
 //   k_sort      unsorted input only: rank of every pole (symmetric permutation
 //               to decreasing order, Sec. 1), the permuted copy, the prologue
 //   k_root      per eigenvalue: shift selection, b, root of the inverse (Algorithms 1-3, Theorem 6)
 //   k_check     per eigenvalue: K_nu test (Algorithm 5), norm; repairs are deferred
-//   k_repair    the deferred repairs (Remarks 1-2, DPR1 re-measure), a block per eigenvalue
+//   k_repair    the deferred repairs (Remarks 1-2, DPR1 re-measure), a block per eigenvalue;
+//               then the eigenpairs a reducible arrowhead deflated (Sec. 1) are placed
 //   k_vec       eigenvector entries, streamed to HBM (eq. eigenvecAi, Algorithm 4)
 // k_root / k_check give G lanes of a wavefront to each eigenvalue (G = 64: one
 // wavefront per eigenvalue); k_vec is bound by the n^2 FP64 stores.
@@ -31,7 +33,7 @@ static_assert(ARROW_INFO_DD_B == INFO_DD_B && ARROW_INFO_REMEDY_A == INFO_REMEDY
                   ARROW_INFO_REMEDY_B == INFO_REMEDY_B && ARROW_INFO_NEAR_ZERO == INFO_NEAR_ZERO &&
                   ARROW_INFO_REDUCIBLE == INFO_REDUCIBLE && ARROW_INFO_NONFINITE == INFO_NONFINITE &&
                   ARROW_INFO_KB_LARGE == INFO_KB_LARGE && ARROW_INFO_BAD_INPUT == INFO_BAD_INPUT &&
-                  ARROW_INFO_POLE_SHIFT == INFO_POLE_SHIFT,
+                  ARROW_INFO_POLE_SHIFT == INFO_POLE_SHIFT && ARROW_INFO_DEFLATED == INFO_DEFLATED,
               "info bits");
 
 
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
     w.ds[j] = D.d[j];
     w.zs[j] = D.z[j];
     w.st[j] = input_status<KIND>(D, j, false);
+    if (KIND == KIND_ARROW) w.iperm[j] = j;
   }
   __syncthreads();
   prologue_block<KIND, FRONT_BLOCK>(D);
@@ -129,6 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
     w.ds[r] = D.d[q];
     w.zs[r] = D.z[q];
     w.st[q] = input_status<KIND>(D, q, (raw >> 30) & 1u);
+    if (KIND == KIND_ARROW) w.iperm[q] = r;
   }
   __threadfence();
   __syncthreads();
@@ -192,7 +196,9 @@ __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
 // wavefront per eigenvalue, REPAIR_BLOCK/64 of them sharing the block's staged
 // arrays): the repairs are a handful of eigenvalues with several O(n) passes
 // apiece, so they get their own launch instead of stretching k_check.
-// Groups beyond the list length skip the work.
+// Groups beyond the list length skip the work.  When the arrowhead was
+// deflated, the last block to finish then places the deflated eigenpairs
+// among the solved ones, whose values are all final at that point.
 constexpr int REPAIR_BLOCK = 256;
 
 template <int KIND, bool STAGE, int GR>
@@ -201,15 +207,19 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt
   constexpr int PER = REPAIR_BLOCK / GR;       // repairs per block
   const Ws w = ws_view(D.ws, D.n);
   const uint32_t count = min(*repair_count(w), (uint32_t)D.n);
-  if (blockIdx.x * PER >= count) return;
-  if constexpr (STAGE) stage_hot(D, lds);
-  const uint32_t* list = repair_list(w, D.n);
-  const int grp = threadIdx.x / GR, ln = threadIdx.x % GR;
-  for (uint32_t q = blockIdx.x * PER + grp; q < count; q += gridDim.x * PER) {
-    const int k = (int)list[q];
-    if (k < 0 || k >= D.n) continue;
-    if constexpr (STAGE) check_body<KIND, GR, true>(D, opt, k, ln, lds, lds + sorted_count(D));
-    else check_body<KIND, GR>(D, opt, k, ln);
+  if (blockIdx.x * PER < count) {
+    if constexpr (STAGE) stage_hot(D, lds);
+    const uint32_t* list = repair_list(w, D.n);
+    const int grp = threadIdx.x / GR, ln = threadIdx.x % GR;
+    for (uint32_t q = blockIdx.x * PER + grp; q < count; q += gridDim.x * PER) {
+      const int k = (int)list[q];
+      if (k < 0 || k >= D.n) continue;
+      if constexpr (STAGE) check_body<KIND, GR, true>(D, opt, k, ln, lds, lds + sorted_count(D));
+      else check_body<KIND, GR>(D, opt, k, ln);
+    }
+  }
+  if constexpr (KIND == KIND_ARROW) {
+    if (deflated_count(w) > 0) place_deflated_last(D, w, gridDim.x);
   }
 }
 

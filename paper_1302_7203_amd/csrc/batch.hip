@@ -8,7 +8,8 @@
 //               decreasing order n so the long items start first
 //   k_b_stage   the same queue again for the K_nu test and norms; eigenvalues
 //               that need a repair (Remarks 1-2, DPR1 re-measure) are listed
-//   k_b_repair  the listed repairs, a block per eigenvalue
+//   k_b_repair  the listed repairs, a block per eigenvalue; then the
+//               eigenpairs of a deflated arrowhead (Sec. 1) are placed
 //   k_b_vec     every problem's vector tiles (row tiles for large n, flat
 //               column-major runs for small n) mapped onto blocks
 //
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))
 // The repairs the check stage deferred (each problem keeps its own list in its
 // workspace, as in the single-problem path): `per` blocks of REPAIR_BLOCK
 // lanes per problem stride over that problem's list, each listed eigenvalue
-// run by a whole block.  Blocks beyond a problem's list length return at once.
+// run by a whole block.  Blocks beyond a problem's list length skip the repairs.
 constexpr int REPAIR_BLOCK = 256;
 
 __global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options opt, int per) {
@@ -127,7 +128,6 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options 
   const ProbDesc D = B.descs[p];
   const Ws w = ws_view(D.ws, D.n);
   const uint32_t c = min(*repair_count(w), (uint32_t)D.n);
-  if ((uint32_t)x >= c) return;
   const uint32_t* list = repair_list(w, D.n);
   for (uint32_t q = (uint32_t)x; q < c; q += (uint32_t)per) {
     const int k = (int)list[q];
@@ -138,6 +138,8 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options 
       default: check_body<KIND_SVD, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
     }
   }
+  // a deflated arrowhead: the last of its `per` blocks places the deflated eigenpairs
+  if (D.kind == KIND_ARROW && deflated_count(w) > 0) place_deflated_last(D, w, (uint32_t)per);
 }
 
 template <int KIND>

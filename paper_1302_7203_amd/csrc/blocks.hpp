@@ -11,6 +11,49 @@ namespace ahd {
 
 constexpr int BLOCK = 256;
 
+// Deflation of a reducible arrowhead (see deflate_run) by one block: thread t
+// takes the runs that start in its chunk of the sorted poles; a block-wide
+// scan of the per-chunk counts gives every run its reduced index and item
+// numbers.  The kept poles are gathered in pv1 (free until the first pass)
+// and copied back over the sorted poles, which the runs read until then.
+template <int NT>
+__device__ inline void deflate_block(const Ws& w, int m) {
+  __shared__ int kc[NT], ic[NT];
+  const int t = threadIdx.x;
+  const int chunk = (m + NT - 1) / NT;
+  const int j0 = min(m, t * chunk), j1 = min(m, j0 + chunk);
+  int keep = 0, items = 0;
+  for (int j = j0; j < j1; ++j) {
+    if (!run_start(w.ds, j)) continue;
+    const DeflCount c = deflate_count(w, m, j);
+    keep += c.keep;
+    items += c.items;
+  }
+  kc[t] = keep;
+  ic[t] = items;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {   // inclusive scan
+    const int a = (t >= o) ? kc[t - o] : 0, b = (t >= o) ? ic[t - o] : 0;
+    __syncthreads();
+    kc[t] += a;
+    ic[t] += b;
+    __syncthreads();
+  }
+  int r = kc[t] - keep, q = ic[t] - items;
+  const int mr = kc[NT - 1], nd = ic[NT - 1];
+  int zp = 0;
+  for (int j = j0; j < j1; ++j)
+    if (run_start(w.ds, j)) zp |= deflate_run(w, m, j, r, q, w.pv1) ? 1 : 0;
+  zp = __syncthreads_or(zp);
+  for (int j = t; j < mr; j += NT) w.ds[j] = w.pv1[j];
+  if (t == 0) {
+    w.hdr[8] = (double)mr;
+    w.hdr[9] = (double)nd;
+    w.hdr[2] = zp ? 1.0 : 0.0;
+    *prob_flags(w) = 0u;
+  }
+}
+
 // Shaft weights and corner of the (reduced) arrowhead in double-double, the
 // problem flags, and whether some pole is exactly zero.  One block of NT threads.
 template <int KIND, int NT = BLOCK>
@@ -45,13 +88,20 @@ __device__ inline void prologue_block(const ProbDesc& D) {
     }
     __syncthreads();
   }
+  const uint32_t flags = sst[0] & 0x7fffffffu;
   if (t == 0) {
     const dd c = dd_add(corner_base<KIND>(D, w), dd{shi[0], slo[0]});
     w.hdr[0] = c.hi;
     w.hdr[1] = c.lo;
     w.hdr[2] = (sst[0] >> 31) ? 1.0 : 0.0;
-    *prob_flags(w) = sst[0] & 0x7fffffffu;
+    *prob_flags(w) = flags;
     *repair_count(w) = 0u;
+    *place_done(w) = 0u;
+    w.hdr[8] = (double)m;
+    w.hdr[9] = 0.0;
+  }
+  if constexpr (KIND == KIND_ARROW) {
+    if (flags == INFO_REDUCIBLE) deflate_block<NT>(w, m);
   }
   __syncthreads();
 }
@@ -72,6 +122,7 @@ __device__ inline void sort_block(const ProbDesc& D) {
       w.ds[j] = D.d[j];
       w.zs[j] = D.z[j];
       w.st[j] = input_status<KIND>(D, j, false);
+      if (KIND == KIND_ARROW) w.iperm[j] = j;
     }
     __syncthreads();
     return;
@@ -98,6 +149,7 @@ __device__ inline void sort_block(const ProbDesc& D) {
       w.ds[rank] = D.d[j];
       w.zs[rank] = D.z[j];
       w.st[j] = input_status<KIND>(D, j, dup);
+      if (KIND == KIND_ARROW) w.iperm[j] = rank;
     }
   }
   __syncthreads();
@@ -153,9 +205,29 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
   }
   const int c0 = ct * cols;
   const int c1 = min(n, c0 + cols);
+  const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
   for (int col = c0; col < c1; ++col) {
-    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
     double* vc = D.V + (size_t)col * (size_t)D.ldv;
+    if (KIND == KIND_ARROW && nd > 0) {
+      const int it = w.cm[col];
+      if (it >= 0 && it < nd) {   // a deflated eigenvector (the whole block takes this branch)
+        auto entry = [&](int r, double zr) { return r < n - 1 ? deflated_entry(w, it, w.iperm[r], zr) : 0.0; };
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W;
+          if (r < n) {
+            if constexpr (W == 1) {
+              __builtin_nontemporal_store(entry(r, num[q]), vc + r);
+            } else {
+              const v2d vv = {entry(r, num[2 * q]), entry(r + 1, num[2 * q + 1])};
+              __builtin_nontemporal_store(vv, (v2d*)(vc + r));
+            }
+          }
+        }
+        continue;
+      }
+    }
+    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
     double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
     const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
 #pragma unroll
@@ -197,11 +269,14 @@ __device__ inline void vec_flat(const ProbDesc& D, int t) {
   int col = (int)(e / n);
   int row = (int)(e - (int64_t)col * n);
   const int q = BLOCK / n, rem = BLOCK - q * n;
+  const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
   for (int step = 0; step < VEC_FLAT / BLOCK && e < nn; ++step, e += BLOCK) {
     const bool body = (KIND == KIND_DPR1) ? true : (row < n - 1);
     const double dr = body ? D.d[row] : 0.0;
     const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[row] : D.z[row]) : 0.0;
-    const double v = vec_entry<KIND>(dr, num, row == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
+    const int it = (KIND == KIND_ARROW && nd > 0) ? w.cm[col] : -1;
+    const double v = (it >= 0 && it < nd) ? (body ? deflated_entry(w, it, w.iperm[row], num) : 0.0)
+                               : vec_entry<KIND>(dr, num, row == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
     __builtin_nontemporal_store(v, D.V + e);
     if (KIND == KIND_SVD && D.U) __builtin_nontemporal_store(svd_left(D, D.lam[col], v, row), D.U + e);
     row += rem;
@@ -211,6 +286,22 @@ __device__ inline void vec_flat(const ProbDesc& D, int t) {
       ++col;
     }
   }
+}
+
+// The deflated eigenpairs are placed among the solved ones once every block
+// of the launch that finishes the solved eigenvalues is done: each block
+// counts itself in the workspace, and the last to arrive places them.  Every
+// one of the `blocks` blocks must call this.
+__device__ inline void place_deflated_last(const ProbDesc& D, const Ws& w, uint32_t blocks) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(place_done(w), 1u) == blocks - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nd = deflated_count(w);
+  for (int s = threadIdx.x; s < nd; s += blockDim.x) place_deflated(D, w, s);
 }
 
 }  // namespace ahd

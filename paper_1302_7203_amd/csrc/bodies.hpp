@@ -30,7 +30,7 @@ struct ProbDesc {
   double* ws;          // workspace of ws_doubles(n) doubles
 };
 
-__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 19; }
+__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 24; }
 
 // Workspace of one problem.
 struct Ws {
@@ -52,6 +52,17 @@ struct Ws {
   double* inrm;     // final 1 / ||x||
   int32_t* cnt;     // per eigenvalue, 6 counters: (bisection steps, double-double passes, plain O(n)
                     // passes) of k_root, then the same three of k_check
+  // deflation of a reducible arrowhead (Sec. 1): hdr[8] = poles m' of the
+  // irreducible problem that the root and check stages solve, hdr[9] = number
+  // of deflated eigenpairs, hdr[10] = completion count of the repair launch
+  double* lr;       // the irreducible problem's eigenvalues, by its index
+  double* dv;       // deflated eigenvalues, descending
+  double* da;       // per deflated eigenpair: factor of the earlier rows of its run ...
+  double* db;       // ... and its own entry (see deflate_run)
+  int32_t* dm;      // per deflated eigenpair: its row (sorted index)
+  int32_t* df;      // ... and the first nonzero row of its run (-1: a unit vector)
+  int32_t* cm;      // per output column: deflated eigenpair index, or -1
+  int32_t* iperm;   // caller row -> sorted index
 };
 
 __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
@@ -75,6 +86,14 @@ __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
   w.mu = p; p += N;
   w.inrm = p; p += N;
   w.cnt = (int32_t*)p; p += 3 * N;
+  w.lr = p; p += N;
+  w.dv = p; p += N;
+  w.da = p; p += N;
+  w.db = p; p += N;
+  w.dm = (int32_t*)p;
+  w.df = w.dm + N; p += N;
+  w.cm = (int32_t*)p;
+  w.iperm = w.cm + N; p += N;
   return w;
 }
 
@@ -84,6 +103,22 @@ __host__ __device__ inline int sorted_count(const ProbDesc& D) {
   return D.kind == KIND_DPR1 ? D.n : D.n - 1;
 }
 
+// poles of the problem the root and check stages solve: the arrowhead itself,
+// or, once a reducible one is deflated, the irreducible remainder
+__host__ __device__ inline int reduced_m(const Ws& w) { return (int)w.hdr[8]; }
+__host__ __device__ inline int deflated_count(const Ws& w) { return (int)w.hdr[9]; }
+__host__ __device__ inline uint32_t* place_done(const Ws& w) { return (uint32_t*)(w.hdr + 10); }
+
+// number of entries of the descending a[0..len) that are > x (strict) or >= x
+__host__ __device__ inline int count_above(const double* a, int len, double x, bool or_equal) {
+  int lo = 0, hi = len;   // a[0..lo) qualify, a[hi..len) do not
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (or_equal ? (a[mid] >= x) : (a[mid] > x)) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // HOT: hot_d / hot_c are copies of the sorted poles and shaft weights (in LDS)
 // used by the O(n) passes in place of the workspace arrays.  A compile-time
 // choice, so that the compiler knows which memory the passes read.
@@ -91,9 +126,9 @@ template <bool HOT = false>
 __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const double* hot_d = nullptr,
                                           const double* hot_c = nullptr) {
   Prob P;
-  P.n = D.n;
-  P.m = D.n - 1;
-  P.nsorted = sorted_count(D);
+  P.m = reduced_m(w);
+  P.n = P.m + 1;
+  P.nsorted = (D.kind == KIND_DPR1) ? P.n : P.m;
   P.ds = w.ds;
   P.zs = w.zs;
   P.ch = w.ch;
@@ -168,6 +203,113 @@ __host__ __device__ inline dd corner_base(const ProbDesc& D, const Ws& w) {
 }
 
 // ---------------------------------------------------------------------------
+// Deflation of a reducible arrowhead (Sec. 1).  A zero shaft entry z_j makes
+// d_j an eigenvalue with the unit vector e_j as eigenvector.  Poles equal to
+// d_j that carry nonzero shaft entries are merged, by rotations in their
+// planes, into one pole whose shaft entry is the root of their sum of squares;
+// each direction a rotation removes is an eigenvector for d_j.  What is left
+// is an irreducible arrowhead, which the root and check stages solve.
+//
+// Equal poles are adjacent in the sorted order; a run of them is handled by
+// the thread that owns its first element.  Within a run, the members are
+// taken in sorted order: the first nonzero member carries the merged pole,
+// each zero member is a unit-vector item, and each later nonzero member t is
+// a rotation item whose eigenvector has the entries
+//     z_i z_t / (R_{t-1} R_t)   at the run's earlier rows i,
+//     -R_{t-1} / R_t            at row t,
+// where R_t^2 sums z_i^2 over the run's rows up to t (the direction that the
+// rotation folding z_t into the merged pole leaves behind; its own entry is
+// negative).  Items are numbered in the order of the runs, then of the rows.
+// The reduced eigenvectors keep eq. (Aeigenvec) over the caller's rows: the
+// rotation carries x of the merged pole back to z_i / (d_i - lambda) on each
+// member, and to 0 on the zero members.
+
+struct DeflCount {
+  int keep, items;   // 1 if the run keeps a pole; its deflated eigenpairs
+};
+
+__host__ __device__ inline bool run_start(const double* ds, int j) { return j == 0 || ds[j] != ds[j - 1]; }
+
+__host__ __device__ inline DeflCount deflate_count(const Ws& w, int m, int j) {
+  const double dj = w.ds[j];
+  bool nz = false;
+  int e = j;
+  for (; e < m && w.ds[e] == dj; ++e) nz |= w.zs[e] != 0.0;
+  const int keep = nz ? 1 : 0;
+  return DeflCount{keep, (e - j) - keep};
+}
+
+// sqrt of a double-double, to about one ulp
+__host__ __device__ inline double dd_sqrt_d(dd x) {
+  const double s = sqrt(x.hi);
+  return s == 0.0 ? 0.0 : s + (fma(-s, s, x.hi) + x.lo) * (0.5 / s);
+}
+
+// the run starting at sorted index j: its pole goes to reduced index r (poles
+// into pole_out, weights into ch/cl/dz, which no other run reads), its items
+// to q, q+1, ...; r and q are advanced past them.  Returns whether the kept
+// pole is exactly zero.
+__host__ __device__ inline bool deflate_run(const Ws& w, int m, int j, int& r, int& q, double* pole_out) {
+  const double dj = w.ds[j];
+  dd R2 = {0.0, 0.0};
+  double rp = 0.0;   // R of the members so far
+  int f = -1;
+  for (int e = j; e < m && w.ds[e] == dj; ++e) {
+    const double ze = w.zs[e];
+    if (ze == 0.0) {
+      w.dv[q] = dj; w.dm[q] = e; w.df[q] = -1; w.da[q] = 0.0; w.db[q] = 1.0;
+      ++q;
+      continue;
+    }
+    const dd z2 = two_prod(ze, ze);
+    if (f < 0) {
+      f = e;
+      R2 = z2;
+      rp = fabs(ze);
+      continue;
+    }
+    R2 = dd_add(R2, z2);
+    const double rt = dd_sqrt_d(R2);
+    w.dv[q] = dj; w.dm[q] = e; w.df[q] = f;
+    w.da[q] = ze / (rp * rt);
+    w.db[q] = -(rp / rt);
+    ++q;
+    rp = rt;
+  }
+  if (f < 0) return false;
+  pole_out[r] = dj;
+  w.ch[r] = R2.hi;
+  w.cl[r] = R2.lo;
+  w.dz[r] = rp;
+  ++r;
+  return dj == 0.0;
+}
+
+// entry of the deflated eigenvector s at the sorted row j, z_r the caller's
+// shaft entry of that row
+__host__ __device__ inline double deflated_entry(const Ws& w, int s, int j, double zr) {
+  const int t = w.dm[s], f = w.df[s];
+  if (j == t) return w.db[s];
+  return (f >= 0 && j >= f && j < t) ? zr * w.da[s] : 0.0;
+}
+
+// Output columns are the merge of the reduced eigenvalues (descending, as
+// computed) with the deflated ones (descending); on a tie the reduced one
+// comes first.  Reduced eigenvalue k goes to column k + #{deflated > lambda_k},
+// deflated item s to column s + #{reduced >= delta_s}.
+__host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, int s) {
+  const int np = reduced_m(w) + 1;
+  const double v = w.dv[s];
+  const int col = s + count_above(w.lr, np, v, true);
+  D.lam[col] = v;
+  if (D.shift) D.shift[col] = v;
+  if (D.mu) D.mu[col] = 0.0;
+  if (D.info) D.info[col] = INFO_DEFLATED;
+  w.pv[col] = v; w.sf[col] = 0.0; w.mu[col] = 0.0; w.inrm[col] = 0.0;
+  w.cm[col] = s;
+}
+
+// ---------------------------------------------------------------------------
 // first pass for eigenvalue k: shift, b, bisection (Algorithm 5 without the
 // final K_nu test).
 
@@ -177,6 +319,10 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   const Ws w = ws_view(D.ws, D.n);
   const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
+  if (k >= P.n) {   // past the order of a deflated problem
+    if (ln == 0) { w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0; }
+    return;
+  }
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
       w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0;
@@ -243,6 +389,10 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   const Ws w = ws_view(D.ws, D.n);
   const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
+  if (k >= P.n) {
+    if (ln == 0) { w.cnt[6 * k + 3] = 0; w.cnt[6 * k + 4] = 0; w.cnt[6 * k + 5] = 0; }
+    return;
+  }
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
       w.pv[k] = NAN; w.sf[k] = NAN; w.mu[k] = NAN; w.inrm[k] = NAN;
@@ -349,17 +499,26 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     w.cnt[6 * k + 3] = c_it;
     w.cnt[6 * k + 4] = c_dd;
     w.cnt[6 * k + 5] = c_plain;
-    w.pv[k] = pv;
-    w.sf[k] = s;
-    w.mu[k] = mu;
-    w.inrm[k] = inrm;
     const dd sh = dd_add_d(pval_dd<KIND>(pv), s);
     const double lam = dd_to_d(dd_add_d(sh, mu));
-    if constexpr (KIND == KIND_SVD) D.lam[k] = sqrt(fmax(lam, 0.0));
-    else D.lam[k] = lam;
-    if (D.shift) D.shift[k] = dd_to_d(sh);
-    if (D.mu) D.mu[k] = mu;
-    if (D.info) D.info[k] = fl;
+    int col = k;   // output column: k unless eigenpairs were deflated
+    if constexpr (KIND == KIND_ARROW) {
+      const int nd = deflated_count(w);
+      if (nd > 0) {
+        col = k + count_above(w.dv, nd, lam, false);
+        w.lr[k] = lam;
+        w.cm[col] = -1;
+      }
+    }
+    w.pv[col] = pv;
+    w.sf[col] = s;
+    w.mu[col] = mu;
+    w.inrm[col] = inrm;
+    if constexpr (KIND == KIND_SVD) D.lam[col] = sqrt(fmax(lam, 0.0));
+    else D.lam[col] = lam;
+    if (D.shift) D.shift[col] = dd_to_d(sh);
+    if (D.mu) D.mu[col] = mu;
+    if (D.info) D.info[col] = fl;
   }
 }
 
@@ -375,6 +534,7 @@ __host__ __device__ inline double vec_elem(const ProbDesc& D, double pv, double 
     return (D.z[r] * inrm) * recip(((D.d[r] - pv) - s) - mu);
   } else {
     if (r == n - 1) return -inrm;
+    if (KIND == KIND_ARROW && D.z[r] == 0.0) return 0.0;   // a deflated row
     const double num = (KIND == KIND_SVD) ? D.d[r] * D.z[r] : D.z[r];
     return (num * inrm) * recip((pdiff<KIND>(D.d[r], pv) - s) - mu);
   }
@@ -389,6 +549,7 @@ __host__ __device__ inline double vec_entry(double dr, double num, bool last, do
     return (num * inrm) * recip(((dr - pv) - s) - mu);
   } else {
     if (last) return -inrm;
+    if (KIND == KIND_ARROW && num == 0.0) return 0.0;   // a deflated row
     return (num * inrm) * recip((pdiff<KIND>(dr, pv) - s) - mu);
   }
 }

@@ -38,6 +38,7 @@ constexpr uint32_t INFO_KB_LARGE = 64u;   // K_b beyond what double-double resol
 constexpr uint32_t INFO_KNU_LARGE = 128u; // K_nu above threshold after the remedies
 constexpr uint32_t INFO_BAD_INPUT = 256u; // kind-specific domain error (SVD: d_j = 0)
 constexpr uint32_t INFO_POLE_SHIFT = 512u;// DPR1 eigenvalue re-measured from the pole d_n
+constexpr uint32_t INFO_DEFLATED = 1024u; // eigenpair deflated from a reducible arrowhead (Sec. 1)
 constexpr uint32_t INFO_NOT_SOLVED = INFO_REDUCIBLE | INFO_NONFINITE | INFO_BAD_INPUT;
 
 constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 3

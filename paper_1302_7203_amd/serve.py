@@ -93,7 +93,7 @@ def request_parts(pr: Problem, vectors=True):
     104-byte descriptor and four table words)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 16 * _ms(pr) + _up(8 * (16 + 19 * pr.n)) + 128
+    rest = 16 * _ms(pr) + _up(8 * (16 + 24 * pr.n)) + 128
     return out, info, rest
 
 

@@ -157,14 +157,15 @@ def reducible_arrow(n, rng, zero_frac=0.1, repeat_every=97, triple=True):
     """A reducible arrowhead (Sec. 1) in random order: ``uniform`` poles and
     shaft, then a fraction ``zero_frac`` of the shaft entries set to 0 (random
     signs on the rest), every ``repeat_every``-th pole repeated in the next
-    slot, and, if ``triple``, one pole taken three times."""
+    slot (0: none), and, if ``triple``, one pole taken three times."""
     m = n - 1
     d = _sorted_with_gap(rng, m, -1.0, 1.0)
     z = rng.uniform(0.1, 1.0, m) * rng.choice([-1.0, 1.0], m)
     if m > 0:
         z[rng.choice(m, int(zero_frac * m), replace=False)] = 0.0
-    for i in range(0, m - 1, repeat_every):
-        d[i + 1] = d[i]
+    if repeat_every > 0:
+        for i in range(0, m - 1, repeat_every):
+            d[i + 1] = d[i]
     if triple and m >= 8:
         c = m // 2
         d[c + 1] = d[c + 2] = d[c]

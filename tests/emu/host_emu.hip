@@ -29,6 +29,7 @@ static void run(ProbDesc D, const Options& opt, double* U) {
     w.ds[rank] = D.d[j];
     w.zs[rank] = D.z[j];
     w.st[j] = input_status<KIND>(D, j, dup);
+    if (KIND == KIND_ARROW) w.iperm[j] = rank;
   }
   uint32_t st = 0;
   int zp = 0;
@@ -46,15 +47,34 @@ static void run(ProbDesc D, const Options& opt, double* U) {
   w.hdr[1] = c.lo;
   w.hdr[2] = zp ? 1.0 : 0.0;
   *prob_flags(w) = st;
+  w.hdr[8] = (double)(D.n - 1);
+  w.hdr[9] = 0.0;
+  if (KIND == KIND_ARROW && st == INFO_REDUCIBLE) {
+    // deflation, one run after another (the device splits the runs over a block)
+    const int m = D.n - 1;
+    int r = 0, q = 0;
+    bool zr = false;
+    for (int j = 0; j < m; ++j)
+      if (run_start(w.ds, j)) zr |= deflate_run(w, m, j, r, q, w.pv1);
+    for (int j = 0; j < r; ++j) w.ds[j] = w.pv1[j];
+    w.hdr[8] = (double)r;
+    w.hdr[9] = (double)q;
+    w.hdr[2] = zr ? 1.0 : 0.0;
+    *prob_flags(w) = 0u;
+  }
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < D.n; ++k) root_body<KIND, 1>(D, opt, k, 0);
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < D.n; ++k) check_body<KIND, 1>(D, opt, k, 0);
+  const int nd = deflated_count(w);
+  for (int s = 0; s < nd; ++s) place_deflated(D, w, s);
   if (D.V) {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < D.n; ++k) {
+      const int it = (nd > 0 && w.cm[k] < nd) ? w.cm[k] : -1;
       for (int r = 0; r < D.n; ++r) {
-        const double v = vec_elem<KIND>(D, w.pv[k], w.sf[k], w.mu[k], w.inrm[k], r);
+        const double v = it >= 0 ? (r < D.n - 1 ? deflated_entry(w, it, w.iperm[r], D.z[r]) : 0.0)
+                                 : vec_elem<KIND>(D, w.pv[k], w.sf[k], w.mu[k], w.inrm[k], r);
         D.V[(size_t)k * D.ldv + r] = v;
         if (KIND == KIND_SVD && U) U[(size_t)k * D.ldv + r] = svd_left(D, D.lam[k], v, r);
       }

@@ -99,8 +99,39 @@ def test_svd(n, oracle_lib):
     assert_close(r["U"], ref.U, "U")
 
 
-def test_reducible_reported(oracle_lib):
-    r = emu.solve(0, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+REDUCIBLE = [
+    (np.array([1.0, 3.0, 1.0, 0.5, 1.0, -2.0]), np.array([2.0, 1.0, -1.5, 3.0, 0.25, 0.0]), 0.3),
+    (np.array([0.5, -1.0, 2.0]), np.array([0.0, 0.0, 0.0]), 0.7),
+    (np.array([2.0, 2.0, 2.0, 2.0]), np.array([1.0, -2.0, 0.5, 3.0]), -1.0),
+    (np.array([0.0, 1.0, 0.0, 1.0]), np.array([0.0, 1.0, 1.0, 2.0]), 0.0),
+]
+
+
+@pytest.mark.parametrize("i", range(len(REDUCIBLE)))
+def test_reducible_deflated(i, oracle_lib):
+    """Deflation of zero shaft entries and repeated poles (Sec. 1) against the oracle's."""
+    d, z, a = REDUCIBLE[i]
+    r = emu.solve(0, d, z, a)
+    ref = oracle.arrow_eig(d, z, a)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "V")
+    assert np.array_equal((r["info"] & 1024) != 0, ref.tau == 0)
+    assert_close(r["shift"] + r["mu"], ref.lam, "shift+mu")
+
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (9, 2), (300, 3), (1001, 4)])
+def test_reducible_random(n, seed, oracle_lib):
+    pr = W.reducible_arrow(n, np.random.default_rng(seed), zero_frac=0.2, repeat_every=5)
+    r = emu.solve(0, pr.d, pr.z, pr.scalar)
+    ks = np.arange(0, n, max(1, n // 60))
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+    assert_close(r["lam"][ks], ref.lam, "lambda")
+    assert_close(r["V"][:, ks], ref.vec, "V")
+
+
+def test_other_kinds_reducible_reported(oracle_lib):
+    """DPR1 and SVD inputs that are reducible are reported, not solved."""
+    r = emu.solve(1, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 1.0)
     assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))
-    r = emu.solve(0, np.array([1.0, 0.7, 0.5]), np.array([1.0, 0.0, 3.0]), 0.0)
-    assert np.all(r["info"] & 16)
+    r = emu.solve(2, np.array([1.0, 0.7, 0.5]), np.array([1.0, 0.0, 3.0]), 0.5)
+    assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))

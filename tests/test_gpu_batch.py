@@ -25,8 +25,10 @@ def _mixed(count, seed, nmin=16, nmax=300):
         n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
         k = p % 3
         out.append(W.uniform_arrow(n, rng) if k == 0 else W.dpr1(n, rng) if k == 1 else W.svd_arrow(n, rng))
-    # a graded problem and the edge orders
+    # a graded problem, two reducible ones (deflated, Sec. 1) and the edge orders
     out.append(W.graded_arrow(200, rng, clusters=4, cluster_size=8))
+    out.append(W.reducible_arrow(40, rng))
+    out.append(W.reducible_arrow(150, rng, zero_frac=0.3, repeat_every=4))
     out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
     return out
 
@@ -109,14 +111,27 @@ def test_graph_replays_equal_eager(env):
 def test_bad_problem_is_isolated(env, oracle_lib):
     torch, batch, dev = env
     probs = _mixed(6, 5)
-    bad = W.Problem(W.KIND_ARROW, 4, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+    bad = W.Problem(W.KIND_ARROW, 4, np.array([1.0, np.inf, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
     probs.insert(3, bad)
     b = batch.Batch(probs, device=dev)
     b.run()
     torch.cuda.synchronize()
     lam, V, U, info = b.result(3)
-    assert bool((info.cpu() & 16).all()) and bool(torch.isnan(lam).all())
+    assert bool((info.cpu() & 32).all()) and bool(torch.isnan(lam).all())
     _check(b, probs, torch, idx=[p for p in range(len(probs)) if p != 3])
+    b.close()
+
+
+def test_reducible_row_tiles(env, oracle_lib):
+    """Deflated problems large enough for the row-tiled vector kernel, odd (one row per
+    store) and even (16-byte stores), beside ordinary problems."""
+    torch, batch, dev = env
+    rng = np.random.default_rng(61)
+    probs = [W.reducible_arrow(701, rng), W.uniform_arrow(600, rng), W.reducible_arrow(1024, rng, zero_frac=0.2),
+             W.dpr1(520, rng)]
+    b = batch.Batch(probs, device=dev)
+    b.run()
+    _check(b, probs, torch)
     b.close()
 
 

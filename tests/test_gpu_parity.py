@@ -188,11 +188,71 @@ def test_repeat_is_bitwise_deterministic(gpu):
     assert bool((a.V == b.V).all())
 
 
-def test_reducible_and_nonfinite_reported(gpu):
-    out = _arrow(gpu, np.array([1.0, 1.0, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
+REDUCIBLE = [
+    (np.array([1.0, 3.0, 1.0, 0.5, 1.0, -2.0]), np.array([2.0, 1.0, -1.5, 3.0, 0.25, 0.0]), 0.3),
+    (np.array([0.5, -1.0, 2.0]), np.array([0.0, 0.0, 0.0]), 0.7),
+    (np.array([2.0, 2.0, 2.0, 2.0]), np.array([1.0, -2.0, 0.5, 3.0]), -1.0),
+    (np.array([0.0, 1.0, 0.0, 1.0]), np.array([0.0, 1.0, 1.0, 2.0]), 0.0),
+]
+
+
+@pytest.mark.parametrize("i", range(len(REDUCIBLE)))
+def test_reducible_deflated(gpu, i, oracle_lib):
+    """Zero shaft entries and repeated poles are deflated (Sec. 1), as in the oracle."""
+    d, z, a = REDUCIBLE[i]
+    out = _arrow(gpu, d, z, a, pairs=True)
+    ref = oracle.arrow_eig(d, z, a)
+    assert_close(_np(out.lam), ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
+    assert_close(_np(out.shift) + _np(out.mu), ref.lam, "shift+mu")
+    assert np.array_equal((_np(out.info) & 1024) != 0, ref.tau == 0)
+
+
+@pytest.mark.parametrize("n", [2, 9, 300, 513, 1000, 4096, 5001])
+def test_reducible_sizes_sampled(gpu, n, oracle_lib):
+    """Every vector-tile shape, odd and even n, with ~10% zero shaft entries and
+    repeated poles, unsorted; ~60 sampled columns plus every deflated one."""
+    pr = W.reducible_arrow(n, np.random.default_rng(n), zero_frac=0.1, repeat_every=13)
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar, pairs=True)
+    info = _np(out.info)
+    defl = np.flatnonzero(info & 1024)
+    assert defl.size >= int(0.1 * (n - 1))
+    ks = np.union1d(np.arange(0, n, max(1, n // 60)), defl)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+    assert_close(_np(out.lam)[ks], ref.lam, "lambda")
+    assert_close(_np(out.V)[:, ks], ref.vec, "V")
+    assert np.array_equal(info[ks] & 1024 != 0, ref.tau == 0)
+    assert np.all(np.diff(_np(out.lam)) <= 0)
+
+
+def test_reducible_sorted_input(gpu, oracle_lib):
+    """Strictly decreasing poles with zero shaft entries: the one-kernel front end deflates."""
+    rng = np.random.default_rng(77)
+    pr = W.reducible_arrow(700, rng, zero_frac=0.3, repeat_every=0, triple=False)
+    o = np.argsort(-pr.d, kind="stable")
+    d, z = pr.d[o].copy(), pr.z[o].copy()
+    assert np.all(np.diff(d) < 0)
+    out = _arrow(gpu, d, z, pr.scalar)
+    ks = np.arange(0, 700, 7)
+    ref = oracle.arrow_eig(d, z, pr.scalar, ks=ks)
+    assert_close(_np(out.lam)[ks], ref.lam, "lambda")
+    assert_close(_np(out.V)[:, ks], ref.vec, "V")
+
+
+def test_reducible_other_kinds_and_nonfinite_reported(gpu):
+    _, binding, dev = gpu
+    import torch
+    t = lambda a: torch.from_numpy(np.asarray(a, dtype=np.float64)).to(dev)   # noqa: E731
+    out = binding.dpr1_eig(t([1.0, 1.0, 0.5]), t([1.0, 2.0, 3.0]), 1.0)
+    torch.cuda.synchronize(dev)
+    assert np.all(_np(out.info) & 16) and np.all(np.isnan(_np(out.lam)))
+    out = binding.arrow_svd(t([1.0, 0.7, 0.5]), t([1.0, 0.0, 3.0]), 0.5)
+    torch.cuda.synchronize(dev)
     assert np.all(_np(out.info) & 16) and np.all(np.isnan(_np(out.lam)))
     out = _arrow(gpu, np.array([1.0, np.inf, 0.5]), np.array([1.0, 2.0, 3.0]), 0.0)
     assert np.all(_np(out.info) & 32)
+    out = _arrow(gpu, np.array([1.0, 1.0, np.nan]), np.array([0.0, 2.0, 3.0]), 0.0)
+    assert np.all(_np(out.info) & 32) and np.all(np.isnan(_np(out.lam)))
     # a good call after a bad one is unaffected
     pr = W.uniform_arrow(50, np.random.default_rng(1))
     ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
