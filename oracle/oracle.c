@@ -17,7 +17,7 @@
  *     one in each interval of the interlacing property         (Sec. 1, eq. (interlace))
  *   eigenvector  = x / ||x||,  x = [ (D - l I)^{-1} z ; -1 ]     (Sec. 1, eq. (Aeigenvec))
  *
- *   DPR1 M = D + rho u u^T (rho > 0): eigenvalues are the n zeros of
+ *   DPR1 M = D + rho u u^T (rho > 0; rho < 0 by negation): eigenvalues are the n zeros of
  *       phi(l) = 1 + rho sum_j u_j^2 / (d_j - l)               (Remark 1, secular equation)
  *     one in each interval of eq. (lld) in Sec. 6.3; eigenvector q ~ (D - l I)^{-1} u.
  *
@@ -560,11 +560,18 @@ int oracle_arrow_eig(int64_t n, const double *d, const double *z, double alpha,
  * u_j != 0.  Same conventions as above; Q is n x nk with q = x/||x||,
  * x = (D - l I)^{-1} u (rows in caller order).
  */
+static int dpr1_negative(int64_t n, const double *d, const double *u, double rho,
+                         int64_t nk, const int64_t *ks,
+                         double *lam, double *lam_lo, double *tau, double *tau_lo,
+                         int64_t *pole, double *Q, double *relerr, int nthreads);
+
 int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
                     int64_t nk, const int64_t *ks,
                     double *lam, double *lam_lo, double *tau, double *tau_lo,
                     int64_t *pole, double *Q, double *relerr, int nthreads) {
-  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(rho) || !(rho > 0)) return -1;
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(rho) || rho == 0) return -1;
+  if (rho < 0)
+    return dpr1_negative(n, d, u, rho, nk, ks, lam, lam_lo, tau, tau_lo, pole, Q, relerr, nthreads);
   for (int64_t j = 0; j < n; ++j) {
     if (!finite_d(d[j]) || !finite_d(u[j])) return -1;
     if (u[j] == 0) return 1;
@@ -616,6 +623,58 @@ int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
   }
   free(order); free(dq); free(cq);
   return 0;
+}
+
+/*
+ * rho < 0: D + rho u u^T = -((-D) + |rho| u u^T), so the k-th largest
+ * eigenvalue is minus the (n-1-k)-th largest of (-D) + |rho| u u^T, measured
+ * from the same pole with tau negated.  The eigenvectors are then formed here
+ * from their definition q ~ (D - l I)^{-1} u, in the caller's frame.
+ */
+static int dpr1_negative(int64_t n, const double *d, const double *u, double rho,
+                         int64_t nk, const int64_t *ks,
+                         double *lam, double *lam_lo, double *tau, double *tau_lo,
+                         int64_t *pole, double *Q, double *relerr, int nthreads) {
+  double *nd = (double *)malloc((size_t)n * sizeof *nd);
+  int64_t *kr = (int64_t *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *kr);
+  double *th = (double *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *th);
+  double *tl = (double *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *tl);
+  double *lh = (double *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *lh);
+  double *ll = (double *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *ll);
+  int64_t *pl = (int64_t *)malloc((size_t)(nk > 0 ? nk : 1) * sizeof *pl);
+  int rc = -100;
+  if (!nd || !kr || !th || !tl || !lh || !ll || !pl) goto done;
+  for (int64_t j = 0; j < n; ++j) nd[j] = -d[j];
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) { rc = -1; goto done; }
+    kr[i] = n - 1 - k;
+  }
+  rc = oracle_dpr1_eig(n, nd, u, -rho, nk, kr, lh, ll, th, tl, pl, NULL, relerr, nthreads);
+  if (rc != 0) goto done;
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    if (lam) lam[i] = -lh[i];
+    if (lam_lo) lam_lo[i] = -ll[i];
+    if (tau) tau[i] = -th[i];
+    if (tau_lo) tau_lo[i] = -tl[i];
+    if (pole) pole[i] = pl[i];
+    if (Q) {
+      /* l = d_p + t, t = -(th + tl) */
+      R dp = (R)d[pl[i]], t = -((R)th[i] + (R)tl[i]), nrm2 = 0;
+      for (int64_t j = 0; j < n; ++j) {
+        R x = (R)u[j] / (((R)d[j] - dp) - t);
+        nrm2 += x * x;
+      }
+      R nrm = sqrtq(nrm2);
+      double *col = Q + i * n;
+      for (int64_t j = 0; j < n; ++j) col[j] = (double)(((R)u[j] / (((R)d[j] - dp) - t)) / nrm);
+    }
+  }
+done:
+  free(nd); free(kr); free(th); free(tl); free(lh); free(ll); free(pl);
+  return rc;
 }
 
 /*

@@ -359,6 +359,39 @@ def test_dpr1_exact_inertia(n, seed, oracle_lib):
         assert r.lam[k] > ds[k] if r.lam_lo[k] >= 0 or r.lam[k] != ds[k] else False
 
 
+def _dpr1_negative_failures(pr, r):
+    """D + rho u u^T with rho < 0: exact eigenvalues, interlacing from below
+    (d_{k+1} < lambda_k < d_k), exact null vectors and q ~ +(D - lambda I)^{-1} u."""
+    bad = []
+    n = pr.n
+    M = brute.dense_dpr1(pr.d, pr.z, pr.scalar)
+    lam_exact = brute.exact_eigvals(M, rel_bits=170)
+    ds = np.sort(pr.d)[::-1]
+    for k in range(n):
+        if abs(hilo(r.lam[k], r.lam_lo[k]) - lam_exact[k]) > abs(lam_exact[k]) * Fraction(1, 10 ** 25):
+            bad.append(f"lambda_{k}")
+        if not (lam_exact[k] < F(ds[k]) and (k == n - 1 or lam_exact[k] > F(ds[k + 1]))):
+            bad.append(f"interlacing {k}")
+        x = brute.exact_null_vector(M, lam_exact[k]) if n > 1 else [Fraction(-1)]
+        col = r.vec[:, k]
+        for j in range(n - 1):
+            if abs(F(col[j]) / F(col[-1]) - x[j] / x[-1]) > abs(x[j] / x[-1]) * Fraction(4, 10 ** 16):
+                bad.append(f"vector {k}")
+                break
+        # the row of the largest pole: lambda_k < d_max, so (d_max - lambda) u > 0 in sign
+        jmax = int(np.argmax(pr.d))
+        if np.sign(col[jmax]) != np.sign(pr.z[jmax]):
+            bad.append(f"sign {k}")
+    return bad
+
+
+@pytest.mark.parametrize("n,seed", [(1, 6), (3, 7), (6, 8)])
+def test_dpr1_negative_rho(n, seed, oracle_lib):
+    pr = W.dpr1(n, np.random.default_rng(seed))
+    pr.scalar = -pr.scalar
+    assert _dpr1_negative_failures(pr, oracle.dpr1_eig(pr.d, pr.z, pr.scalar)) == []
+
+
 @pytest.mark.parametrize("n,seed", [(12, 4), (20, 5)])
 def test_dpr1_mpmath_dense(n, seed, oracle_lib):
     pr = W.dpr1(n, np.random.default_rng(seed))
@@ -431,6 +464,8 @@ _MUTANTS = {
     "deflation_weight_dropped": ("c += (R)zq * (R)zq;", "c += 0;"),
     "deflation_unit_row_sorted": ("out[t->row] = 1.0;", "out[t->pos] = 1.0;"),
     "deflation_merge_count": ("if (g > err) c = P + 1;", "if (g < -err) c = P + 1;"),
+    "dpr1_negative_order": ("kr[i] = n - 1 - k;", "kr[i] = k;"),
+    "dpr1_negative_tau_sign": ("t = -((R)th[i] + (R)tl[i])", "t = ((R)th[i] + (R)tl[i])"),
     "vector_tau_sign": ("R x = (R)z[j] / (((R)d[j] - dp) - r.tau);\n        col[j]",
                         "R x = (R)z[j] / (((R)d[j] - dp) + r.tau);\n        col[j]"),
 }
@@ -482,12 +517,19 @@ def _quick_pins(lib):
 
 def _quick_deflation_pins(lib):
     failed = []
+    pr = W.dpr1(5, np.random.default_rng(9))
+    pr.scalar = -pr.scalar
+    try:
+        if _dpr1_negative_failures(pr, oracle.dpr1_eig(pr.d, pr.z, pr.scalar, lib=lib)):
+            failed.append("dpr1 rho < 0")
+    except (oracle.oracle.OracleError, ValueError, ZeroDivisionError):   # NaN or zero where a value belongs
+        failed.append("dpr1 rho < 0 error")
     for i in range(len(REDUCIBLE)):
         d, z, a = REDUCIBLE[i]
         try:
             if _deflation_failures(i, oracle.arrow_eig(d, z, a, lib=lib)):
                 failed.append(f"deflation {i}")
-        except oracle.oracle.OracleError:
+        except (oracle.oracle.OracleError, ValueError, ZeroDivisionError):
             failed.append(f"deflation {i} error")
     return failed
 
