@@ -115,11 +115,13 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
 
 /*
  * Eigen-decomposition of the real symmetric DPR1 matrix M = diag(d) + rho u u^T
- * (Sec. 6.3) of order n >= 1, rho > 0.  d, u: n entries, any order; d distinct,
- * u_j != 0 (else info reports REDUCIBLE).
+ * (Sec. 6.3) of order n >= 1, rho != 0.  d, u: n entries, any order; d distinct,
+ * u_j != 0 (else info reports REDUCIBLE).  rho < 0 is solved as the negation of
+ * (-D) + |rho| u u^T (the reduction of Sec. 6.3 needs rho > 0; the closing
+ * remark of Sec. 6 names D - u u^T as the case it does not cover).
  *   lambda: n eigenvalues, descending.
  *   Q:      n x n eigenvectors (ldq >= n) or null; q_k = x/||x||,
- *           x = (D - lambda_k I)^{-1} u.
+ *           x = (D - lambda_k I)^{-1} u, for either sign of rho.
  *   info:   optional.
  */
 int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, double rho,
@@ -147,7 +149,7 @@ int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
  * the same schedule).
  */
 #define ARROW_KIND_ARROW 0   /* arrowhead: d, z (n-1 each), scalar = alpha */
-#define ARROW_KIND_DPR1 1    /* diag(d) + rho u u^T: d, u (n each), scalar = rho > 0 */
+#define ARROW_KIND_DPR1 1    /* diag(d) + rho u u^T: d, u (n each), scalar = rho != 0 */
 #define ARROW_KIND_SVD 2     /* triangular arrowhead SVD: d, z (n-1 each), scalar = alpha */
 
 typedef struct {

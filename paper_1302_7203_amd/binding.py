@@ -215,7 +215,7 @@ def arrow_eig(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool =
 
 
 def dpr1_eig(d: torch.Tensor, u: torch.Tensor, rho: float, *, vectors: bool = True) -> EigOut:
-    """Eigenpairs of diag(d) + rho u u^T (rho > 0); d, u float64 CUDA tensors of length n."""
+    """Eigenpairs of diag(d) + rho u u^T (rho != 0); d, u float64 CUDA tensors of length n."""
     device = d.device
     n = d.numel()
     d = _dev_vec(d, n, device, "d")

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
   const int ms = sorted_count(D);
   int bad = 0;
   for (int j = threadIdx.x; j + 1 < ms; j += FRONT_BLOCK)
-    if (!(sort_key<KIND>(D.d[j]) > sort_key<KIND>(D.d[j + 1]))) bad = 1;
+    if (!(sort_key<KIND>(in_pole<KIND>(D, j)) > sort_key<KIND>(in_pole<KIND>(D, j + 1)))) bad = 1;
   bad = __syncthreads_or(bad);
   if (bad) {
     uint32_t* rank = rank_array(w, D.n);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
     return;
   }
   for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
-    w.ds[j] = D.d[j];
+    w.ds[j] = in_pole<KIND>(D, j);
     w.zs[j] = D.z[j];
     w.st[j] = input_status<KIND>(D, j, false);
     if (KIND == KIND_ARROW) w.iperm[j] = j;
@@ -98,14 +98,14 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   const int ms = sorted_count(D);
   uint32_t* rank = rank_array(w, D.n);
   const int j = blockIdx.x * BLOCK + threadIdx.x;
-  const double kj = (j < ms) ? sort_key<KIND>(D.d[j]) : NAN;
+  const double kj = (j < ms) ? sort_key<KIND>(in_pole<KIND>(D, j)) : NAN;
   const int l0 = blockIdx.y * SORT_CHUNK;
   const int l1 = min(ms, l0 + SORT_CHUNK);
   uint32_t cnt = 0;
   bool dup = false;
   for (int base = l0; base < l1; base += BLOCK) {
     const int l = base + threadIdx.x;
-    tile[threadIdx.x] = (l < l1) ? sort_key<KIND>(D.d[l]) : NAN;
+    tile[threadIdx.x] = (l < l1) ? sort_key<KIND>(in_pole<KIND>(D, l)) : NAN;
     __syncthreads();
     const int lim = min(BLOCK, l1 - base);
     for (int t = 0; t < lim; ++t) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   for (int q = threadIdx.x; q < ms; q += BLOCK) {
     const uint32_t raw = __hip_atomic_load(&rank[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int r = (int)(raw & 0x3fffffffu);
-    w.ds[r] = D.d[q];
+    w.ds[r] = in_pole<KIND>(D, q);
     w.zs[r] = D.z[q];
     w.st[q] = input_status<KIND>(D, q, (raw >> 30) & 1u);
     if (KIND == KIND_ARROW) w.iperm[q] = r;
@@ -493,7 +493,7 @@ int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, doub
   if (n < 1 || n > (int64_t)1 << 28) return -2;
   if (!d) return -3;
   if (!u) return -4;
-  if (!finite_h(rho) || !(rho > 0.0)) return -5;
+  if (!finite_h(rho) || rho == 0.0) return -5;
   if (!lambda) return -6;
   if (Q && ldq < n) return -8;
   DeviceGuard g(h->device);
@@ -502,9 +502,10 @@ int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, doub
   ProbDesc D{};
   D.kind = KIND_DPR1;
   D.n = (int32_t)n;
+  D.neg = rho < 0.0;
   D.d = d;
   D.z = u;
-  D.scalar = rho;
+  D.scalar = fabs(rho);
   D.lam = lambda;
   D.V = Q;
   D.ldv = ldq;

@@ -216,7 +216,7 @@ static int check_desc(const arrow_desc_t& a) {
   if (a.kind < ARROW_KIND_ARROW || a.kind > ARROW_KIND_SVD) return 1;
   if (a.n < 1 || a.n > 46340) return 1;
   if (!(a.scalar - a.scalar == 0.0)) return 1;
-  if (a.kind == ARROW_KIND_DPR1 && !(a.scalar > 0.0)) return 1;
+  if (a.kind == ARROW_KIND_DPR1 && a.scalar == 0.0) return 1;
   const int64_t ms = a.kind == ARROW_KIND_DPR1 ? a.n : a.n - 1;
   if (ms > 0 && (a.d_off < 0 || a.z_off < 0)) return 1;
   if (a.lam_off < 0) return 1;
@@ -309,7 +309,8 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     D.n = a.n;
     D.d = in_pool + a.d_off;
     D.z = in_pool + a.z_off;
-    D.scalar = a.scalar;
+    D.neg = a.kind == ARROW_KIND_DPR1 && a.scalar < 0.0;
+    D.scalar = D.neg ? -a.scalar : a.scalar;
     D.lam = out_pool + a.lam_off;
     D.V = a.vec_off >= 0 ? out_pool + a.vec_off : nullptr;
     D.ldv = a.n;
@@ -447,7 +448,8 @@ int arrow_solve_sequential(arrow_handle_t h, int64_t count, const arrow_desc_t* 
     D.n = a.n;
     D.d = in_pool + a.d_off;
     D.z = in_pool + a.z_off;
-    D.scalar = a.scalar;
+    D.neg = a.kind == ARROW_KIND_DPR1 && a.scalar < 0.0;
+    D.scalar = D.neg ? -a.scalar : a.scalar;
     D.lam = out_pool + a.lam_off;
     D.V = a.vec_off >= 0 ? out_pool + a.vec_off : nullptr;
     D.ldv = a.n;

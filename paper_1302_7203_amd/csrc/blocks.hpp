@@ -115,11 +115,11 @@ __device__ inline void sort_block(const ProbDesc& D) {
   const int ms = sorted_count(D);
   int bad = 0;
   for (int j = threadIdx.x; j + 1 < ms; j += BLOCK)
-    if (!(sort_key<KIND>(D.d[j]) > sort_key<KIND>(D.d[j + 1]))) bad = 1;
+    if (!(sort_key<KIND>(in_pole<KIND>(D, j)) > sort_key<KIND>(in_pole<KIND>(D, j + 1)))) bad = 1;
   bad = __syncthreads_or(bad);
   if (!bad) {
     for (int j = threadIdx.x; j < ms; j += BLOCK) {
-      w.ds[j] = D.d[j];
+      w.ds[j] = in_pole<KIND>(D, j);
       w.zs[j] = D.z[j];
       w.st[j] = input_status<KIND>(D, j, false);
       if (KIND == KIND_ARROW) w.iperm[j] = j;
@@ -129,12 +129,12 @@ __device__ inline void sort_block(const ProbDesc& D) {
   }
   for (int j0 = 0; j0 < ms; j0 += BLOCK) {
     const int j = j0 + threadIdx.x;
-    const double kj = (j < ms) ? sort_key<KIND>(D.d[j]) : NAN;
+    const double kj = (j < ms) ? sort_key<KIND>(in_pole<KIND>(D, j)) : NAN;
     int rank = 0;
     bool dup = false;
     for (int base = 0; base < ms; base += BLOCK) {
       const int l = base + threadIdx.x;
-      tile[threadIdx.x] = (l < ms) ? sort_key<KIND>(D.d[l]) : NAN;
+      tile[threadIdx.x] = (l < ms) ? sort_key<KIND>(in_pole<KIND>(D, l)) : NAN;
       __syncthreads();
       const int lim = min(BLOCK, ms - base);
       for (int t = 0; t < lim; ++t) {
@@ -146,7 +146,7 @@ __device__ inline void sort_block(const ProbDesc& D) {
       __syncthreads();
     }
     if (j < ms) {
-      w.ds[rank] = D.d[j];
+      w.ds[rank] = in_pole<KIND>(D, j);
       w.zs[rank] = D.z[j];
       w.st[j] = input_status<KIND>(D, j, dup);
       if (KIND == KIND_ARROW) w.iperm[j] = rank;
@@ -199,7 +199,7 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
     for (int e = 0; e < W; ++e) {
       const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W + e;
       const bool body = (KIND == KIND_DPR1) ? (r < n) : (r < n - 1);
-      dr[q * W + e] = body ? D.d[r] : 0.0;
+      dr[q * W + e] = body ? in_pole<KIND>(D, r) : 0.0;
       num[q * W + e] = body ? ((KIND == KIND_SVD) ? dr[q * W + e] * D.z[r] : D.z[r]) : 0.0;
     }
   }
@@ -272,7 +272,7 @@ __device__ inline void vec_flat(const ProbDesc& D, int t) {
   const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
   for (int step = 0; step < VEC_FLAT / BLOCK && e < nn; ++step, e += BLOCK) {
     const bool body = (KIND == KIND_DPR1) ? true : (row < n - 1);
-    const double dr = body ? D.d[row] : 0.0;
+    const double dr = body ? in_pole<KIND>(D, row) : 0.0;
     const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[row] : D.z[row]) : 0.0;
     const int it = (KIND == KIND_ARROW && nd > 0) ? w.cm[col] : -1;
     const double v = (it >= 0 && it < nd) ? (body ? deflated_entry(w, it, w.iperm[row], num) : 0.0)

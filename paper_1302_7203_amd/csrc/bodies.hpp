@@ -16,9 +16,10 @@ namespace ahd {
 struct ProbDesc {
   int32_t kind;        // KIND_ARROW / KIND_DPR1 / KIND_SVD
   int32_t n;           // matrix order
+  int32_t neg;         // DPR1 with rho < 0: solve (-D) + |rho| u u^T (scalar holds |rho|) and negate
   const double* d;     // ARROW, SVD: n-1 poles; DPR1: n diagonal entries (any order)
   const double* z;     // ARROW, SVD: n-1 shaft entries; DPR1: u (n)
-  double scalar;       // ARROW, SVD: alpha; DPR1: rho
+  double scalar;       // ARROW, SVD: alpha; DPR1: |rho|
   double* lam;         // n: eigenvalues (SVD: singular values), descending
   double* V;           // n x n column-major (ARROW: V, DPR1: Q, SVD: right vectors) or null
   int64_t ldv;
@@ -144,6 +145,15 @@ __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const 
 }
 
 __host__ __device__ inline bool finite_d(double x) { return x - x == 0.0; }
+
+// pole j of the problem the kernels solve, read from the caller's array: for
+// a DPR1 matrix with rho < 0 the spectrum of D + rho u u^T is the negated
+// spectrum of (-D) + |rho| u u^T (same eigenvectors), so its poles are -d_j
+template <int KIND>
+__host__ __device__ inline double in_pole(const ProbDesc& D, int j) {
+  if constexpr (KIND == KIND_DPR1) return D.neg ? -D.d[j] : D.d[j];
+  else return D.d[j];
+}
 
 // ---------------------------------------------------------------------------
 // normalisation (symmetric permutation to decreasing poles, Sec. 1 eq. (order)):
@@ -502,6 +512,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     const dd sh = dd_add_d(pval_dd<KIND>(pv), s);
     const double lam = dd_to_d(dd_add_d(sh, mu));
     int col = k;   // output column: k unless eigenpairs were deflated
+    double sg = 1.0;   // -1: DPR1 with rho < 0, whose eigenvalue order is reversed
     if constexpr (KIND == KIND_ARROW) {
       const int nd = deflated_count(w);
       if (nd > 0) {
@@ -510,14 +521,21 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
         w.cm[col] = -1;
       }
     }
+    if constexpr (KIND == KIND_DPR1) {
+      if (D.neg) {
+        col = D.n - 1 - k;
+        sg = -1.0;
+      }
+    }
     w.pv[col] = pv;
     w.sf[col] = s;
     w.mu[col] = mu;
-    w.inrm[col] = inrm;
+    // q = (D - lambda)^{-1} u for rho < 0 is minus the vector of (-D) + |rho| u u^T
+    w.inrm[col] = sg * inrm;
     if constexpr (KIND == KIND_SVD) D.lam[col] = sqrt(fmax(lam, 0.0));
-    else D.lam[col] = lam;
-    if (D.shift) D.shift[col] = dd_to_d(sh);
-    if (D.mu) D.mu[col] = mu;
+    else D.lam[col] = sg * lam;
+    if (D.shift) D.shift[col] = sg * dd_to_d(sh);
+    if (D.mu) D.mu[col] = sg * mu;
     if (D.info) D.info[col] = fl;
   }
 }
@@ -531,7 +549,7 @@ __host__ __device__ inline double vec_elem(const ProbDesc& D, double pv, double 
                                            int r) {
   const int n = D.n;
   if constexpr (KIND == KIND_DPR1) {
-    return (D.z[r] * inrm) * recip(((D.d[r] - pv) - s) - mu);
+    return (D.z[r] * inrm) * recip(((in_pole<KIND>(D, r) - pv) - s) - mu);
   } else {
     if (r == n - 1) return -inrm;
     if (KIND == KIND_ARROW && D.z[r] == 0.0) return 0.0;   // a deflated row

@@ -18,15 +18,15 @@ static void run(ProbDesc D, const Options& opt, double* U) {
   const int ms = sorted_count(D);
   Ws w = ws_view(D.ws, D.n);
   for (int j = 0; j < ms; ++j) {
-    const double kj = sort_key<KIND>(D.d[j]);
+    const double kj = sort_key<KIND>(in_pole<KIND>(D, j));
     int rank = 0;
     bool dup = false;
     for (int l = 0; l < ms; ++l) {
-      const double kl = sort_key<KIND>(D.d[l]);
+      const double kl = sort_key<KIND>(in_pole<KIND>(D, l));
       rank += (kl > kj) || (kl == kj && l < j);
       dup |= (kl == kj) && (l != j);
     }
-    w.ds[rank] = D.d[j];
+    w.ds[rank] = in_pole<KIND>(D, j);
     w.zs[rank] = D.z[j];
     w.st[j] = input_status<KIND>(D, j, dup);
     if (KIND == KIND_ARROW) w.iperm[j] = rank;
@@ -91,7 +91,8 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   D.n = (int32_t)n;
   D.d = d;
   D.z = z;
-  D.scalar = scalar;
+  D.neg = kind == KIND_DPR1 && scalar < 0.0;
+  D.scalar = D.neg ? -scalar : scalar;
   D.lam = lam;
   D.V = V;
   D.ldv = n;

@@ -89,6 +89,16 @@ def test_dpr1(n, oracle_lib):
     assert_close(r["V"], ref.vec, "Q")
 
 
+@pytest.mark.parametrize("n", [1, 2, 97, 600])
+def test_dpr1_negative_rho(n, oracle_lib):
+    """rho < 0: solved as the negation of (-D) + |rho| u u^T."""
+    pr = W.dpr1(n, np.random.default_rng(45 + n))
+    r = emu.solve(1, pr.d, pr.z, -pr.scalar)
+    ref = oracle.dpr1_eig(pr.d, pr.z, -pr.scalar)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "Q")
+
+
 @pytest.mark.parametrize("n", [2, 60, 300])
 def test_svd(n, oracle_lib):
     pr = W.svd_arrow(n, np.random.default_rng(50 + n))

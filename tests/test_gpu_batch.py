@@ -29,6 +29,9 @@ def _mixed(count, seed, nmin=16, nmax=300):
     out.append(W.graded_arrow(200, rng, clusters=4, cluster_size=8))
     out.append(W.reducible_arrow(40, rng))
     out.append(W.reducible_arrow(150, rng, zero_frac=0.3, repeat_every=4))
+    neg = W.dpr1(120, rng)          # rho < 0
+    neg.scalar = -neg.scalar
+    out.append(neg)
     out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
     return out
 
@@ -128,7 +131,8 @@ def test_reducible_row_tiles(env, oracle_lib):
     torch, batch, dev = env
     rng = np.random.default_rng(61)
     probs = [W.reducible_arrow(701, rng), W.uniform_arrow(600, rng), W.reducible_arrow(1024, rng, zero_frac=0.2),
-             W.dpr1(520, rng)]
+             W.dpr1(520, rng), W.dpr1(777, rng)]
+    probs[-1].scalar = -probs[-1].scalar     # rho < 0, odd n
     b = batch.Batch(probs, device=dev)
     b.run()
     _check(b, probs, torch)

@@ -288,6 +288,19 @@ def test_dpr1(gpu, n, oracle_lib):
     assert_close(_np(out.V), ref.vec, "Q")
 
 
+@pytest.mark.parametrize("n", [1, 2, 97, 1000, 4097])
+def test_dpr1_negative_rho(gpu, n, oracle_lib):
+    """rho < 0 (solved as the negation of (-D) + |rho| u u^T), every tile shape up to n = 4097."""
+    torch, binding, dev = gpu
+    pr = W.dpr1(n, np.random.default_rng(65 + n))
+    out = binding.dpr1_eig(torch.from_numpy(pr.d).to(dev), torch.from_numpy(pr.z).to(dev), -pr.scalar)
+    torch.cuda.synchronize(dev)
+    ks = np.arange(n) if n <= 1000 else np.arange(0, n, 41)
+    ref = oracle.dpr1_eig(pr.d, pr.z, -pr.scalar, ks=ks)
+    assert_close(_np(out.lam)[ks], ref.lam, "lambda")
+    assert_close(_np(out.V)[:, ks], ref.vec, "Q")
+
+
 @pytest.mark.parametrize("n", [1, 2, 97, 1000])
 def test_svd(gpu, n, oracle_lib):
     torch, binding, dev = gpu
