@@ -9,4 +9,5 @@ from .oracle import (  # noqa: F401
     arrow_eig,
     dpr1_eig,
     arrow_svd,
+    herm_eig,
 )

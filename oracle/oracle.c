@@ -21,6 +21,9 @@
  *       phi(l) = 1 + rho sum_j u_j^2 / (d_j - l)               (Remark 1, secular equation)
  *     one in each interval of eq. (lld) in Sec. 6.3; eigenvector q ~ (D - l I)^{-1} u.
  *
+ *   Hermitian C = [D z; z^* alpha] (Sec. 6.1): the same with |z_j|^2, eigenvector
+ *     [(D - l I)^{-1} z; -1] / norm with the complex z.
+ *
  *   SVD of B = [D z; 0 alpha]: sigma_k = sqrt(lambda_k(B^T B)), where
  *     B^T B is the arrowhead with poles d_j^2, shaft d_j zeta_j and corner
  *     alpha^2 + z^T z (Sec. 6.2); v_k its eigenvector, u_k = B v_k / sigma_k.
@@ -619,6 +622,91 @@ int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
         R x = (R)u[j] / (((R)d[j] - dp) - r.tau);
         col[j] = (double)(x / nrm);
       }
+    }
+  }
+  free(order); free(dq); free(cq);
+  return 0;
+}
+
+/*
+ * Hermitian arrowhead C = [diag(d) z; z^* alpha] (Sec. 6.1): d, alpha real,
+ * z complex given as zr + i zi (n-1 entries each, any order).  C is unitarily
+ * similar to the real arrowhead with shaft |z_j|, so its eigenvalues are the
+ * zeros of f(l) = alpha - l - sum_j |z_j|^2 / (d_j - l) (|z_j|^2 = zr^2 + zi^2
+ * formed in binary128), and its eigenvector is x / ||x||, x = [(D - l I)^{-1} z; -1]
+ * with the complex z (C x = l x row by row).  U: n x nk complex, column-major,
+ * (re, im) pairs.  Returns 0, -1 bad argument, 1 reducible.
+ */
+int oracle_herm_eig(int64_t n, const double *d, const double *zr, const double *zi, double alpha,
+                    int64_t nk, const int64_t *ks,
+                    double *lam, double *lam_lo, double *tau, double *tau_lo,
+                    int64_t *pole, double *U, double *relerr, int nthreads) {
+  if (n < 1 || nk < 0 || (!ks && nk != n) || !finite_d(alpha)) return -1;
+  const int64_t m = n - 1;
+  for (int64_t j = 0; j < m; ++j) {
+    if (!finite_d(d[j]) || !finite_d(zr[j]) || !finite_d(zi[j])) return -1;
+    if (zr[j] == 0 && zi[j] == 0) return 1;
+  }
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) return -1;
+  }
+  if (n == 1) {
+    for (int64_t i = 0; i < nk; ++i) {
+      if (lam) lam[i] = alpha;
+      if (lam_lo) lam_lo[i] = 0;
+      if (tau) tau[i] = alpha;
+      if (tau_lo) tau_lo[i] = 0;
+      if (pole) pole[i] = -1;
+      if (U) { U[2 * i] = -1.0; U[2 * i + 1] = 0.0; }
+      if (relerr) relerr[i] = 0;
+    }
+    return 0;
+  }
+  int64_t *order = (int64_t *)malloc((size_t)m * sizeof *order);
+  R *dq = (R *)malloc((size_t)m * sizeof *dq);
+  R *cq = (R *)malloc((size_t)m * sizeof *cq);
+  if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
+  int dup = sort_desc(m, d, order);
+  if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R zsum = 0, up = (R)alpha, lowb = (R)alpha;
+  for (int64_t j = 0; j < m; ++j) {
+    int64_t o = order[j];
+    dq[j] = (R)d[o];
+    cq[j] = (R)zr[o] * (R)zr[o] + (R)zi[o] * (R)zi[o];
+    R az = sqrtq(cq[j]);
+    zsum += az;
+    if (dq[j] + az > up) up = dq[j] + az;
+    if (dq[j] - az < lowb) lowb = dq[j] - az;
+  }
+  if ((R)alpha + zsum > up) up = (R)alpha + zsum;
+  if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
+  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha };
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    root_t r;
+    solve_root(&s, k, up, lowb, &r);
+    if (lam || lam_lo) split(r.lam, lam ? &lam[i] : NULL, lam_lo ? &lam_lo[i] : NULL);
+    if (tau || tau_lo) split(r.tau, tau ? &tau[i] : NULL, tau_lo ? &tau_lo[i] : NULL);
+    if (pole) pole[i] = order[r.p];
+    if (relerr) relerr[i] = r.relerr;
+    if (U) {
+      R dp = dq[r.p], nrm2 = 1;
+      for (int64_t j = 0; j < m; ++j) {
+        R den = ((R)d[j] - dp) - r.tau;
+        nrm2 += ((R)zr[j] * (R)zr[j] + (R)zi[j] * (R)zi[j]) / (den * den);
+      }
+      R nrm = sqrtq(nrm2);
+      double *col = U + 2 * i * n;
+      for (int64_t j = 0; j < m; ++j) {
+        R den = (((R)d[j] - dp) - r.tau) * nrm;
+        col[2 * j] = (double)((R)zr[j] / den);
+        col[2 * j + 1] = (double)((R)zi[j] / den);
+      }
+      col[2 * m] = (double)(-1 / nrm);
+      col[2 * m + 1] = 0.0;
     }
   }
   free(order); free(dq); free(cq);

@@ -45,7 +45,8 @@ def _load(path=None):
         lib.oracle_arrow_eig.argtypes = [I64, P, P, D, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_dpr1_eig.argtypes = [I64, P, P, D, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_arrow_svd.argtypes = [I64, P, P, D, I64, P, P, P, P, P, P, ctypes.c_int]
-        for f in (lib.oracle_arrow_eig, lib.oracle_dpr1_eig, lib.oracle_arrow_svd):
+        lib.oracle_herm_eig.argtypes = [I64, P, P, P, D, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
+        for f in (lib.oracle_arrow_eig, lib.oracle_dpr1_eig, lib.oracle_arrow_svd, lib.oracle_herm_eig):
             f.restype = ctypes.c_int
         _libs[key] = lib
     return _libs[key]
@@ -98,6 +99,27 @@ def arrow_eig(d, z, alpha, ks=None, vectors=True, threads=0, lib=None) -> EigRes
                                   _ptr(pole), _ptr(V), _ptr(rel), int(threads))
     _check(rc, "oracle_arrow_eig")
     return EigResult(out[0], out[1], out[2], out[3], pole, None if V is None else V.T, rel, k)
+
+
+def herm_eig(d, z, alpha, ks=None, vectors=True, threads=0, lib=None) -> EigResult:
+    """Eigenpairs of the Hermitian arrowhead [diag(d) z; z^* alpha] (d real, z complex, n-1 each);
+    ``vec`` is complex."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    z = np.asarray(z, dtype=np.complex128)
+    zr = np.ascontiguousarray(z.real)
+    zi = np.ascontiguousarray(z.imag)
+    n = d.size + 1
+    k = _ks(n, ks)
+    nk = k.size
+    out = [np.empty(nk) for _ in range(4)]
+    pole = np.empty(nk, dtype=np.int64)
+    rel = np.empty(nk)
+    U = np.empty((nk, n), dtype=np.complex128) if vectors else None
+    rc = _load(lib).oracle_herm_eig(n, _ptr(d), _ptr(zr), _ptr(zi), float(alpha), nk, _ptr(k),
+                                 _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(out[3]),
+                                 _ptr(pole), _ptr(U), _ptr(rel), int(threads))
+    _check(rc, "oracle_herm_eig")
+    return EigResult(out[0], out[1], out[2], out[3], pole, None if U is None else U.T, rel, k)
 
 
 def dpr1_eig(d, u, rho, ks=None, vectors=True, threads=0, lib=None) -> EigResult:

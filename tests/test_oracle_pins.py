@@ -447,6 +447,76 @@ def test_svd_mpmath_dense(n, seed, oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# Hermitian arrowhead (Sec. 6.1)
+
+def _herm_case(n, seed):
+    rng = np.random.default_rng(seed)
+    m = n - 1
+    d = W._sorted_with_gap(rng, m, -1.0, 1.0)[rng.permutation(m)]
+    z = rng.uniform(0.1, 1.0, m) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, m))
+    return d, z, float(rng.uniform(-1.0, 1.0))
+
+
+def _herm_failures(d, z, a, r, dps=40):
+    """Against mpmath's dense Hermitian solver: eigenvalues to 1e-25 relative,
+    eigenvectors (phase fixed by the real negative corner entry) to 2.3e-16."""
+    bad = []
+    n = d.size + 1
+    with mp.workdps(dps):
+        C = mp.matrix(n, n)
+        for j in range(n - 1):
+            C[j, j] = mp.mpf(float(d[j]))
+            C[j, n - 1] = mp.mpc(float(z[j].real), float(z[j].imag))
+            C[n - 1, j] = mp.mpc(float(z[j].real), -float(z[j].imag))
+        C[n - 1, n - 1] = mp.mpf(a)
+        E, Q = mp.eighe(C)
+        order = sorted(range(n), key=lambda i: -E[i])
+        for k, i in enumerate(order):
+            if abs(mpf2(r.lam[k], r.lam_lo[k]) - E[i]) > abs(E[i]) * mp.mpf("1e-25"):
+                bad.append(f"lambda_{k}")
+            c = Q[n - 1, i]
+            ph = -mp.conj(c) / abs(c)          # makes the corner entry real and negative
+            for j in range(n):
+                want = Q[j, i] * ph
+                got = mp.mpc(float(r.vec[j, k].real), float(r.vec[j, k].imag))
+                if abs(got - want) > abs(want) * mp.mpf("2.3e-16") + mp.mpf("1e-50"):
+                    bad.append(f"vector {k}")
+                    break
+    return bad
+
+
+@pytest.mark.parametrize("n,seed", [(1, 81), (2, 82), (7, 83), (16, 84)])
+def test_herm_mpmath_dense(n, seed, oracle_lib):
+    d, z, a = _herm_case(n, seed)
+    assert _herm_failures(d, z, a, oracle.herm_eig(d, z, a)) == []
+
+
+def test_herm_phase_invariance(oracle_lib):
+    """Phi^* C Phi only sees |z_j| (Sec. 6.1): z_j -> i z_j leaves every eigenvalue and
+    multiplies row j of U by i, exactly."""
+    d, z, a = _herm_case(30, 85)
+    base = oracle.herm_eig(d, z, a)
+    z2 = z.copy()
+    z2[[3, 11]] *= 1j
+    r = oracle.herm_eig(d, z2, a)
+    assert np.array_equal(r.lam, base.lam) and np.array_equal(r.lam_lo, base.lam_lo)
+    assert np.array_equal(r.vec[[3, 11]], 1j * base.vec[[3, 11]])
+    keep = np.setdiff1d(np.arange(30), [3, 11])
+    assert np.array_equal(r.vec[keep], base.vec[keep])
+
+
+def test_herm_real_case(oracle_lib):
+    """Real z: the symmetric arrowhead's decomposition (values to the last bit, vectors to an ulp)."""
+    pr = W.uniform_arrow(200, np.random.default_rng(86))
+    pr.z[::3] *= -1
+    h = oracle.herm_eig(pr.d, pr.z.astype(np.complex128), pr.scalar)
+    r = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert np.array_equal(h.lam, r.lam)
+    assert np.all(h.vec.imag == 0)
+    assert np.max(np.abs(h.vec.real - r.vec) / np.abs(r.vec)) <= 2.3e-16
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: every one must be caught by the pins above
 
 _MUTANTS = {
@@ -466,6 +536,8 @@ _MUTANTS = {
     "deflation_merge_count": ("if (g > err) c = P + 1;", "if (g < -err) c = P + 1;"),
     "dpr1_negative_order": ("kr[i] = n - 1 - k;", "kr[i] = k;"),
     "dpr1_negative_tau_sign": ("t = -((R)th[i] + (R)tl[i])", "t = ((R)th[i] + (R)tl[i])"),
+    "herm_conjugated_vector": ("col[2 * j + 1] = (double)((R)zi[j] / den);", "col[2 * j + 1] = (double)(-(R)zi[j] / den);"),
+    "herm_modulus_real_part_only": ("cq[j] = (R)zr[o] * (R)zr[o] + (R)zi[o] * (R)zi[o];", "cq[j] = (R)zr[o] * (R)zr[o];"),
     "vector_tau_sign": ("R x = (R)z[j] / (((R)d[j] - dp) - r.tau);\n        col[j]",
                         "R x = (R)z[j] / (((R)d[j] - dp) + r.tau);\n        col[j]"),
 }
@@ -515,8 +587,14 @@ def _quick_pins(lib):
     return failed
 
 
-def _quick_deflation_pins(lib):
+def _quick_extension_pins(lib):
     failed = []
+    d, z, a = _herm_case(5, 87)
+    try:
+        if _herm_failures(d, z, a, oracle.herm_eig(d, z, a, lib=lib), dps=30):
+            failed.append("hermitian")
+    except (oracle.oracle.OracleError, ValueError, ZeroDivisionError):
+        failed.append("hermitian error")
     pr = W.dpr1(5, np.random.default_rng(9))
     pr.scalar = -pr.scalar
     try:
@@ -535,7 +613,7 @@ def _quick_deflation_pins(lib):
 
 
 def test_pins_catch_planted_mistakes(oracle_lib):
-    assert _quick_pins(None) == [] and _quick_deflation_pins(None) == []
+    assert _quick_pins(None) == [] and _quick_extension_pins(None) == []
     src = open(os.path.join(os.path.dirname(oracle.oracle.__file__), "oracle.c")).read()
     tmp = tempfile.mkdtemp(prefix="oracle_mut_")
     try:
@@ -546,6 +624,6 @@ def test_pins_catch_planted_mistakes(oracle_lib):
                 f.write(src.replace(old, new))
             so = os.path.join(tmp, f"lib_{name}.so")
             subprocess.run(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-o", so, path, "-lquadmath"], check=True)
-            assert _quick_pins(so) + _quick_deflation_pins(so) != [], f"planted mistake '{name}' not caught"
+            assert _quick_pins(so) + _quick_extension_pins(so) != [], f"planted mistake '{name}' not caught"
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
