@@ -48,8 +48,8 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_INFO_REMEDY_A 2u    /* shifted to the other neighbouring pole (Remark 2(a)) */
 #define ARROW_INFO_REMEDY_B 4u    /* DPR1 inverse at a shift near lambda (Remark 2(b)) */
 #define ARROW_INFO_NEAR_ZERO 8u   /* eigenvalue closest to 0 taken from A^{-1} (Remark 1) */
-#define ARROW_INFO_REDUCIBLE 16u  /* dpr1_eig / arrow_svd: some z_j = 0 or d_i = d_j (Sec. 1):
-                                     not solved, outputs NaN (arrow_eig deflates instead) */
+#define ARROW_INFO_REDUCIBLE 16u  /* dpr1_eig / arrow_svd / arrow_eig_herm: some z_j = 0 or d_i = d_j
+                                     (Sec. 1): not solved, outputs NaN (arrow_eig deflates instead) */
 #define ARROW_INFO_NONFINITE 32u  /* non-finite input: not solved, outputs NaN */
 #define ARROW_INFO_KB_LARGE 64u   /* K_b (eq. K2) beyond what double-double resolves */
 #define ARROW_INFO_KNU_LARGE 128u /* reserved */
@@ -112,6 +112,23 @@ size_t arrow_workspace_size(int64_t n);
  */
 int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
               double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info);
+
+/*
+ * Eigen-decomposition of the Hermitian arrowhead C = [ diag(d)  z ; z^*  alpha ]
+ * (Sec. 6.1) of order n >= 1: d real (n-1), z complex (n-1 (re, im) pairs of
+ * doubles, any order; 8-byte aligned), alpha real.  Solved as the real
+ * arrowhead Phi^* C Phi = [D |z|; |z|^T alpha], Phi = diag(z_j/|z_j|, 1), with
+ * |z_j|^2 formed in double-double; u = Phi v.
+ *   lambda: n eigenvalues, descending.
+ *   U:      n x n complex eigenvectors as (re, im) pairs, column-major with
+ *           leading dimension ldu >= n counted in complex entries, 16-byte
+ *           aligned (a complex128 array), or null.  u_k = x/||x||,
+ *           x = [(D - lambda_k I)^{-1} z; -1], so U[n-1, k] is real and < 0.
+ *   shift, mu, info: as for arrow_eig.  Reducible input (some z_j = 0 or
+ *           d_i = d_j) is reported (ARROW_INFO_REDUCIBLE, outputs NaN), not deflated.
+ */
+int arrow_eig_herm(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+                   double* lambda, double* U, int64_t ldu, double* shift, double* mu, uint32_t* info);
 
 /*
  * Eigen-decomposition of the real symmetric DPR1 matrix M = diag(d) + rho u u^T

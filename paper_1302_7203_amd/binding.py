@@ -71,6 +71,7 @@ def lib():
                 L.arrow_workspace_size.argtypes = [I64]
                 L.arrow_workspace_size.restype = ctypes.c_size_t
                 L.arrow_eig.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
+                L.arrow_eig_herm.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
                 L.dpr1_eig.argtypes = [P, I64, P, P, D, P, P, I64, P]
                 L.arrow_svd.argtypes = [P, I64, P, P, D, P, P, I64, P, I64, P]
                 L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
@@ -81,7 +82,8 @@ def lib():
                 L.arrow_probe_copy.argtypes = [P, P, I64, P]
                 for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
-                          "arrow_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing", "arrow_last_counters",
+                          "arrow_eig", "arrow_eig_herm", "dpr1_eig", "arrow_svd", "arrow_last_timing",
+                          "arrow_last_counters",
                           "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
                 _lib = L
@@ -211,6 +213,31 @@ def arrow_eig(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool =
         rc = lib().arrow_eig(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(lam), _ptr(buf), n,
                              _ptr(shift), _ptr(mu), _ptr(info))
     _check(rc, "arrow_eig")
+    return EigOut(lam, None if buf is None else buf.t(), None, shift, mu, info)
+
+
+def arrow_eig_herm(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool = True,
+                   pairs: bool = False) -> EigOut:
+    """Eigenpairs of the Hermitian arrowhead [diag(d) z; z^* alpha]; d float64 and z complex128
+    CUDA tensors of length n-1.  V is complex128."""
+    device = d.device
+    n = d.numel() + 1
+    d = _dev_vec(d, n - 1, device, "d")
+    if not isinstance(z, torch.Tensor) or z.device.type != "cuda" or z.dtype != torch.complex128 \
+            or z.dim() != 1 or z.numel() != n - 1:
+        raise ValueError(f"z must be a 1-D complex128 CUDA tensor of length {n - 1}")
+    z = z.contiguous()
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        lam = torch.empty(n, dtype=torch.float64, device=device)
+        buf = torch.empty((n, n), dtype=torch.complex128, device=device) if vectors else None
+        shift = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
+        mu = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
+        info = torch.empty(n, dtype=torch.int32, device=device)
+        rc = lib().arrow_eig_herm(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(lam), _ptr(buf), n,
+                                  _ptr(shift), _ptr(mu), _ptr(info))
+    _check(rc, "arrow_eig_herm")
     return EigOut(lam, None if buf is None else buf.t(), None, shift, mu, info)
 
 

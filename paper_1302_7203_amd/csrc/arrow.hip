@@ -11,7 +11,8 @@
 //   k_check     per eigenvalue: K_nu test (Algorithm 5), norm; repairs are deferred
 //   k_repair    the deferred repairs (Remarks 1-2, DPR1 re-measure), a block per eigenvalue;
 //               then the eigenpairs a reducible arrowhead deflated (Sec. 1) are placed
-//   k_vec       eigenvector entries, streamed to HBM (eq. eigenvecAi, Algorithm 4)
+//   k_vec       eigenvector entries, streamed to HBM (eq. eigenvecAi, Algorithm 4);
+//               k_vec_c the complex ones of a Hermitian arrowhead (Sec. 6.1)
 // k_root / k_check give G lanes of a wavefront to each eigenvalue (G = 64: one
 // wavefront per eigenvalue); k_vec is bound by the n^2 FP64 stores.
 
@@ -75,10 +76,8 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
     return;
   }
   for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
-    w.ds[j] = in_pole<KIND>(D, j);
-    w.zs[j] = D.z[j];
+    put_sorted<KIND>(D, w, j, j);
     w.st[j] = input_status<KIND>(D, j, false);
-    if (KIND == KIND_ARROW) w.iperm[j] = j;
   }
   __syncthreads();
   prologue_block<KIND, FRONT_BLOCK>(D);
@@ -129,10 +128,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   for (int q = threadIdx.x; q < ms; q += BLOCK) {
     const uint32_t raw = __hip_atomic_load(&rank[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int r = (int)(raw & 0x3fffffffu);
-    w.ds[r] = in_pole<KIND>(D, q);
-    w.zs[r] = D.z[q];
+    put_sorted<KIND>(D, w, r, q);
     w.st[q] = input_status<KIND>(D, q, (raw >> 30) & 1u);
-    if (KIND == KIND_ARROW) w.iperm[q] = r;
   }
   __threadfence();
   __syncthreads();
@@ -229,6 +226,12 @@ __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles, int co
   vec_tile<KIND, W, RPT>(D, blockIdx.x - ct * row_tiles, ct, cols);
 }
 
+template <int RPT>
+__global__ __launch_bounds__(BLOCK) void k_vec_c(ProbDesc D, int row_tiles, int cols) {
+  const int ct = blockIdx.x / row_tiles;
+  vec_tile_c<RPT>(D, blockIdx.x - ct * row_tiles, ct, cols);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -267,12 +270,16 @@ int launch_single(arrow_handle_t h, const ProbDesc& D) {
   switch (D.kind) {
     case KIND_ARROW: return launch_problem<KIND_ARROW>(h, D);
     case KIND_DPR1: return launch_problem<KIND_DPR1>(h, D);
+    case KIND_HERM: return launch_problem<KIND_HERM>(h, D);
     default: return launch_problem<KIND_SVD>(h, D);
   }
 }
 
+// A Hermitian problem is sorted and its weights formed as KIND_HERM, then
+// solved by the real arrowhead's root, check and repair kernels.
 template <int KIND>
 static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
+  constexpr int SK = (KIND == KIND_HERM) ? KIND_ARROW : KIND;
   hipStream_t st = h->stream;
   (void)hipGetLastError();
   const bool tm = h->timing && h->ev_made;
@@ -292,19 +299,27 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   const int G = single_lanes(h, D.n);
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
   const size_t lds = (hot <= h->lds_max) ? hot : 0;
-  launch_rc_any<KIND>(G, D, h->opt, st, false, lds);
+  launch_rc_any<SK>(G, D, h->opt, st, false, lds);
   mark(3);
-  launch_rc_any<KIND>(G, D, h->opt, st, true, lds);
+  launch_rc_any<SK>(G, D, h->opt, st, true, lds);
   {
     // deferred repairs; the block reductions add a little static LDS
     const size_t lds_r = (hot + 4096 <= h->lds_max) ? hot : 0;
     constexpr int GR = REPAIR_BLOCK;   // a block per repair (measured faster than a wavefront for n >= 4096)
     const dim3 grid((unsigned)std::min<int64_t>((D.n + REPAIR_BLOCK / GR - 1) / (REPAIR_BLOCK / GR), h->cus));
-    if (lds_r > 0) hipLaunchKernelGGL((k_repair<KIND, true, GR>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
-    else hipLaunchKernelGGL((k_repair<KIND, false, GR>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
+    if (lds_r > 0) hipLaunchKernelGGL((k_repair<SK, true, GR>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
+    else hipLaunchKernelGGL((k_repair<SK, false, GR>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
   }
   mark(4);
-  if (D.V) {
+  if (KIND == KIND_HERM && D.V) {
+    const VecShape sh = vec_shape(D.n);
+    const int row_tiles = (int)((D.n + (int64_t)BLOCK * sh.rpt - 1) / ((int64_t)BLOCK * sh.rpt));
+    const int col_chunks = (D.n + sh.cols - 1) / sh.cols;
+    const dim3 grid((unsigned)((int64_t)row_tiles * col_chunks));
+    if (sh.rpt == 8) hipLaunchKernelGGL((k_vec_c<8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    else if (sh.rpt == 2) hipLaunchKernelGGL((k_vec_c<2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    else hipLaunchKernelGGL((k_vec_c<4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+  } else if (D.V) {
     const VecShape sh = vec_shape(D.n);
     const int row_tiles = (int)((D.n + (int64_t)BLOCK * sh.rpt - 1) / ((int64_t)BLOCK * sh.rpt));
     const int col_chunks = (D.n + sh.cols - 1) / sh.cols;
@@ -485,6 +500,35 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
   D.info = info;
   D.ws = h->ws;
   return launch_problem<KIND_ARROW>(h, D);
+}
+
+int arrow_eig_herm(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
+                   double* U, int64_t ldu, double* shift, double* mu, uint32_t* info) {
+  if (!valid(h)) return -1;
+  if (n < 1 || n > (int64_t)1 << 28) return -2;
+  if (n > 1 && !d) return -3;
+  if (n > 1 && (!z || ((uintptr_t)z & 7))) return -4;
+  if (!finite_h(alpha)) return -5;
+  if (!lambda) return -6;
+  if (U && ((uintptr_t)U & 15)) return -7;
+  if (U && ldu < n) return -8;
+  DeviceGuard g(h->device);
+  const int rc = ensure_ws(h, ws_doubles(n));
+  if (rc) return rc;
+  ProbDesc D{};
+  D.kind = KIND_HERM;
+  D.n = (int32_t)n;
+  D.d = d;
+  D.z = z;
+  D.scalar = alpha;
+  D.lam = lambda;
+  D.V = U;
+  D.ldv = ldu;
+  D.shift = shift;
+  D.mu = mu;
+  D.info = info;
+  D.ws = h->ws;
+  return launch_problem<KIND_HERM>(h, D);
 }
 
 int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, double rho, double* lambda,

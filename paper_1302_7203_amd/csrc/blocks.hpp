@@ -119,10 +119,8 @@ __device__ inline void sort_block(const ProbDesc& D) {
   bad = __syncthreads_or(bad);
   if (!bad) {
     for (int j = threadIdx.x; j < ms; j += BLOCK) {
-      w.ds[j] = in_pole<KIND>(D, j);
-      w.zs[j] = D.z[j];
+      put_sorted<KIND>(D, w, j, j);
       w.st[j] = input_status<KIND>(D, j, false);
-      if (KIND == KIND_ARROW) w.iperm[j] = j;
     }
     __syncthreads();
     return;
@@ -146,10 +144,8 @@ __device__ inline void sort_block(const ProbDesc& D) {
       __syncthreads();
     }
     if (j < ms) {
-      w.ds[rank] = in_pole<KIND>(D, j);
-      w.zs[rank] = D.z[j];
+      put_sorted<KIND>(D, w, rank, j);
       w.st[j] = input_status<KIND>(D, j, dup);
-      if (KIND == KIND_ARROW) w.iperm[j] = rank;
     }
   }
   __syncthreads();
@@ -248,6 +244,40 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
             __builtin_nontemporal_store(uu, (v2d*)(uc + r));
           }
         }
+      }
+    }
+  }
+}
+
+// Complex eigenvector entries of a Hermitian arrowhead (vec_entry_c), one
+// 16-byte (re, im) store each; rows and columns are tiled as in vec_tile.
+template <int RPT>
+__device__ inline void vec_tile_c(const ProbDesc& D, int rt, int ct, int cols) {
+  constexpr int TILE = BLOCK * RPT;
+  const int n = D.n;
+  const Ws w = ws_view(D.ws, n);
+  double dr[RPT], zr[RPT], zi[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = rt * TILE + q * BLOCK + threadIdx.x;
+    const bool body = r < n - 1;
+    dr[q] = body ? D.d[r] : 0.0;
+    zr[q] = body ? D.z[2 * r] : 0.0;
+    zi[q] = body ? D.z[2 * r + 1] : 0.0;
+  }
+  const int c0 = ct * cols;
+  const int c1 = min(n, c0 + cols);
+  for (int col = c0; col < c1; ++col) {
+    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
+    v2d* uc = (v2d*)D.V + (size_t)col * (size_t)D.ldv;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = rt * TILE + q * BLOCK + threadIdx.x;
+      if (r < n) {
+        double ur, ui;
+        vec_entry_c(dr[q], zr[q], zi[q], r == n - 1, pv, s, mu, inrm, &ur, &ui);
+        const v2d u = {ur, ui};
+        __builtin_nontemporal_store(u, uc + r);
       }
     }
   }

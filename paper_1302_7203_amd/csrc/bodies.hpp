@@ -18,11 +18,12 @@ struct ProbDesc {
   int32_t n;           // matrix order
   int32_t neg;         // DPR1 with rho < 0: solve (-D) + |rho| u u^T (scalar holds |rho|) and negate
   const double* d;     // ARROW, SVD: n-1 poles; DPR1: n diagonal entries (any order)
-  const double* z;     // ARROW, SVD: n-1 shaft entries; DPR1: u (n)
+  const double* z;     // ARROW, SVD: n-1 shaft entries; DPR1: u (n); HERM: n-1 complex (re, im) pairs
   double scalar;       // ARROW, SVD: alpha; DPR1: |rho|
   double* lam;         // n: eigenvalues (SVD: singular values), descending
-  double* V;           // n x n column-major (ARROW: V, DPR1: Q, SVD: right vectors) or null
-  int64_t ldv;
+  double* V;           // n x n column-major (ARROW: V, DPR1: Q, SVD: right vectors, HERM: complex U
+                       // as (re, im) pairs) or null
+  int64_t ldv;         // leading dimension (HERM: in complex entries)
   double* U;           // SVD left vectors or null
   int64_t ldu;
   double* shift;       // n or null: lambda_k = shift_k + mu_k (Remark 3 pairs)
@@ -146,6 +147,12 @@ __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const 
 
 __host__ __device__ inline bool finite_d(double x) { return x - x == 0.0; }
 
+// sqrt of a double-double, to about one ulp
+__host__ __device__ inline double dd_sqrt_d(dd x) {
+  const double s = sqrt(x.hi);
+  return s == 0.0 ? 0.0 : s + (fma(-s, s, x.hi) + x.lo) * (0.5 / s);
+}
+
 // pole j of the problem the kernels solve, read from the caller's array: for
 // a DPR1 matrix with rho < 0 the spectrum of D + rho u u^T is the negated
 // spectrum of (-D) + |rho| u u^T (same eigenvectors), so its poles are -d_j
@@ -169,11 +176,36 @@ __host__ __device__ inline double sort_key(double d) {
 template <int KIND>
 __host__ __device__ inline uint32_t input_status(const ProbDesc& D, int j, bool dup) {
   uint32_t st = 0;
-  const double dj = D.d[j], zj = D.z[j];
-  if (!finite_d(dj) || !finite_d(zj)) st |= INFO_NONFINITE;
-  if (zj == 0.0 || dup) st |= INFO_REDUCIBLE;
+  const double dj = D.d[j];
+  if constexpr (KIND == KIND_HERM) {
+    const double re = D.z[2 * j], im = D.z[2 * j + 1];
+    if (!finite_d(dj) || !finite_d(re) || !finite_d(im)) st |= INFO_NONFINITE;
+    if ((re == 0.0 && im == 0.0) || dup) st |= INFO_REDUCIBLE;
+  } else {
+    const double zj = D.z[j];
+    if (!finite_d(dj) || !finite_d(zj)) st |= INFO_NONFINITE;
+    if (zj == 0.0 || dup) st |= INFO_REDUCIBLE;
+  }
   if (KIND == KIND_SVD && dj == 0.0) st |= INFO_BAD_INPUT;
   return st;
+}
+
+// sorted entry r from the caller's entry q: the pole, the shaft entry (HERM:
+// the weight |z_q|^2 = re^2 + im^2 as an exact-product double-double, which
+// Sec. 6.1 asks for in doubled precision), and for ARROW the row's sorted index
+template <int KIND>
+__host__ __device__ inline void put_sorted(const ProbDesc& D, const Ws& w, int r, int q) {
+  w.ds[r] = in_pole<KIND>(D, q);
+  if constexpr (KIND == KIND_HERM) {
+    const double re = D.z[2 * q], im = D.z[2 * q + 1];
+    const dd c = dd_add(two_prod(re, re), two_prod(im, im));
+    w.ch[r] = c.hi;
+    w.cl[r] = c.lo;
+    w.zs[r] = hypot(re, im);   // |z_q| rounded (only the bounds use it); exact when im = 0
+  } else {
+    w.zs[r] = D.z[q];
+  }
+  if constexpr (KIND == KIND_ARROW) w.iperm[q] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -182,7 +214,9 @@ __host__ __device__ inline uint32_t input_status(const ProbDesc& D, int j, bool 
 template <int KIND>
 __host__ __device__ inline void prologue_elem(const ProbDesc& D, const Ws& w, int j) {
   dd c;
-  if constexpr (KIND == KIND_ARROW) {
+  if constexpr (KIND == KIND_HERM) {
+    c = dd{w.ch[j], w.cl[j]};                             // |zeta_j|^2, formed by the sort
+  } else if constexpr (KIND == KIND_ARROW) {
     c = two_prod(w.zs[j], w.zs[j]);                       // zeta_j^2
   } else if constexpr (KIND == KIND_SVD) {
     const dd p = two_prod(w.ds[j], w.zs[j]);              // d_j zeta_j (Sec. 6.2)
@@ -194,20 +228,20 @@ __host__ __device__ inline void prologue_elem(const ProbDesc& D, const Ws& w, in
   }
   w.ch[j] = c.hi;
   w.cl[j] = c.lo;
-  w.dz[j] = (KIND == KIND_ARROW) ? fabs(w.zs[j]) : sqrt(c.hi);
+  w.dz[j] = (KIND == KIND_ARROW || KIND == KIND_HERM) ? fabs(w.zs[j]) : sqrt(c.hi);
 }
 
 // contribution of sorted entry j to the corner
 template <int KIND>
 __host__ __device__ inline dd corner_term(const ProbDesc& D, const Ws& w, int j) {
-  if constexpr (KIND == KIND_ARROW) return dd_from(0.0);
+  if constexpr (KIND == KIND_ARROW || KIND == KIND_HERM) return dd_from(0.0);
   else if constexpr (KIND == KIND_SVD) return two_prod(w.zs[j], w.zs[j]);           // z^T z
   else return dd_mul_d(two_prod(w.zs[j], w.zs[j]), D.scalar);                          // rho u^T u
 }
 
 template <int KIND>
 __host__ __device__ inline dd corner_base(const ProbDesc& D, const Ws& w) {
-  if constexpr (KIND == KIND_ARROW) return dd_from(D.scalar);                          // alpha
+  if constexpr (KIND == KIND_ARROW || KIND == KIND_HERM) return dd_from(D.scalar);   // alpha
   else if constexpr (KIND == KIND_SVD) return two_prod(D.scalar, D.scalar);            // alpha^2
   else return dd_from(w.ds[D.n - 1]);                                                  // d_n
 }
@@ -247,12 +281,6 @@ __host__ __device__ inline DeflCount deflate_count(const Ws& w, int m, int j) {
   for (; e < m && w.ds[e] == dj; ++e) nz |= w.zs[e] != 0.0;
   const int keep = nz ? 1 : 0;
   return DeflCount{keep, (e - j) - keep};
-}
-
-// sqrt of a double-double, to about one ulp
-__host__ __device__ inline double dd_sqrt_d(dd x) {
-  const double s = sqrt(x.hi);
-  return s == 0.0 ? 0.0 : s + (fma(-s, s, x.hi) + x.lo) * (0.5 / s);
 }
 
 // the run starting at sorted index j: its pole goes to reduced index r (poles
@@ -570,6 +598,22 @@ __host__ __device__ inline double vec_entry(double dr, double num, bool last, do
     if (KIND == KIND_ARROW && num == 0.0) return 0.0;   // a deflated row
     return (num * inrm) * recip((pdiff<KIND>(dr, pv) - s) - mu);
   }
+}
+
+// Hermitian arrowhead (Sec. 6.1): u = Phi v with Phi = diag(z_j/|z_j|, 1), so
+// u_r = z_r / ((d_r - pole) - s - mu) / ||x|| with the complex z_r = zr + i zi,
+// and the corner entry is -1/||x||.  Each part is rounded as vec_entry rounds
+// the real case, so zi = 0 gives vec_entry's value.
+__host__ __device__ inline void vec_entry_c(double dr, double zr, double zi, bool last, double pv, double s,
+                                            double mu, double inrm, double* ur, double* ui) {
+  if (last) {
+    *ur = -inrm;
+    *ui = 0.0;
+    return;
+  }
+  const double f = recip(((dr - pv) - s) - mu);
+  *ur = (zr * inrm) * f;
+  *ui = (zi * inrm) * f;
 }
 
 // SVD left vector entry from the right vector entry v_r: u_j = sigma v_j / d_j,

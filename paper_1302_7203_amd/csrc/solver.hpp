@@ -25,7 +25,9 @@
 
 namespace ahd {
 
-enum Kind { KIND_ARROW = 0, KIND_DPR1 = 1, KIND_SVD = 2 };
+// KIND_HERM: a Hermitian arrowhead, solved as the real arrowhead with shaft
+// |z| (Sec. 6.1); the root and check stages treat it as KIND_ARROW.
+enum Kind { KIND_ARROW = 0, KIND_DPR1 = 1, KIND_SVD = 2, KIND_HERM = 3 };
 
 // per-eigenvalue info bits (the public header repeats them)
 constexpr uint32_t INFO_DD_B = 1u;        // b evaluated in double-double (Theorem 6)

@@ -43,12 +43,13 @@ def _p(a):
 
 
 def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1):
-    """kind 0 arrowhead, 1 DPR1, 2 SVD.  Returns dict of numpy arrays (V[:, k] = k-th vector)."""
+    """kind 0 arrowhead, 1 DPR1, 2 SVD, 3 Hermitian arrowhead (complex z; complex V).
+    Returns dict of numpy arrays (V[:, k] = k-th vector)."""
     d = np.ascontiguousarray(d, dtype=np.float64)
-    z = np.ascontiguousarray(z, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.complex128 if kind == 3 else np.float64)
     n = d.size + (0 if kind == 1 else 1)
     lam = np.empty(n)
-    Vb = np.empty((n, n)) if vectors else None
+    Vb = np.empty((n, n), dtype=np.complex128 if kind == 3 else np.float64) if vectors else None
     Ub = np.empty((n, n)) if (vectors and kind == 2) else None
     sh, mu, kb = np.empty(n), np.empty(n), np.empty(n)
     info = np.empty(n, dtype=np.uint32)

@@ -26,10 +26,8 @@ static void run(ProbDesc D, const Options& opt, double* U) {
       rank += (kl > kj) || (kl == kj && l < j);
       dup |= (kl == kj) && (l != j);
     }
-    w.ds[rank] = in_pole<KIND>(D, j);
-    w.zs[rank] = D.z[j];
+    put_sorted<KIND>(D, w, rank, j);
     w.st[j] = input_status<KIND>(D, j, dup);
-    if (KIND == KIND_ARROW) w.iperm[j] = rank;
   }
   uint32_t st = 0;
   int zp = 0;
@@ -62,13 +60,24 @@ static void run(ProbDesc D, const Options& opt, double* U) {
     w.hdr[2] = zr ? 1.0 : 0.0;
     *prob_flags(w) = 0u;
   }
+  // a Hermitian arrowhead is solved as the real one with shaft |z|
+  constexpr int SK = KIND == KIND_HERM ? KIND_ARROW : KIND;
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int k = 0; k < D.n; ++k) root_body<KIND, 1>(D, opt, k, 0);
+  for (int k = 0; k < D.n; ++k) root_body<SK, 1>(D, opt, k, 0);
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int k = 0; k < D.n; ++k) check_body<KIND, 1>(D, opt, k, 0);
+  for (int k = 0; k < D.n; ++k) check_body<SK, 1>(D, opt, k, 0);
   const int nd = deflated_count(w);
   for (int s = 0; s < nd; ++s) place_deflated(D, w, s);
-  if (D.V) {
+  if (KIND == KIND_HERM && D.V) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < D.n; ++k)
+      for (int r = 0; r < D.n; ++r) {
+        const bool body = r < D.n - 1;
+        double* u = D.V + 2 * ((size_t)k * D.ldv + r);
+        vec_entry_c(body ? D.d[r] : 0.0, body ? D.z[2 * r] : 0.0, body ? D.z[2 * r + 1] : 0.0, !body, w.pv[k],
+                    w.sf[k], w.mu[k], w.inrm[k], u, u + 1);
+      }
+  } else if (D.V) {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < D.n; ++k) {
       const int it = (nd > 0 && w.cm[k] < nd) ? w.cm[k] : -1;
@@ -105,6 +114,7 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   Options opt{tau_nu, tau_zero, fp64_b, remedies, root};
   if (kind == KIND_ARROW) run<KIND_ARROW>(D, opt, U);
   else if (kind == KIND_DPR1) run<KIND_DPR1>(D, opt, U);
+  else if (kind == KIND_HERM) run<KIND_HERM>(D, opt, U);
   else run<KIND_SVD>(D, opt, U);
   if (kb) {
     const Ws w = ws_view(D.ws, D.n);

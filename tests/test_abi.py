@@ -28,7 +28,7 @@ def libarrow():
 def test_header_declares_the_documented_entry_points():
     names = set(declared_functions())
     for f in ("arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
-              "arrow_workspace_size", "arrow_eig", "dpr1_eig", "arrow_svd"):
+              "arrow_workspace_size", "arrow_eig", "arrow_eig_herm", "dpr1_eig", "arrow_svd"):
         assert f in names
 
 

@@ -99,6 +99,37 @@ def test_dpr1_negative_rho(n, oracle_lib):
     assert_close(r["V"], ref.vec, "Q")
 
 
+def _herm_case(n, seed):
+    rng = np.random.default_rng(seed)
+    m = n - 1
+    d = W._sorted_with_gap(rng, m, -1.0, 1.0)[rng.permutation(m)]
+    z = rng.uniform(0.1, 1.0, m) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, m))
+    return d, z, float(rng.uniform(-1.0, 1.0))
+
+
+def assert_close_c(got, ref, what, tol=TOL):
+    """Complex entries: |got - ref| / |ref| componentwise."""
+    den = np.abs(ref)
+    e = np.where(den == 0, np.abs(got - ref), np.abs(got - ref) / np.where(den == 0, 1, den))
+    worst = float(e.max()) if e.size else 0.0
+    assert worst <= tol, f"{what}: max relative error {worst:.3e}"
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 400])
+def test_hermitian(n, oracle_lib):
+    """Hermitian arrowhead (Sec. 6.1): the real solver on |z|, vectors with the complex z."""
+    d, z, a = _herm_case(n, 90 + n)
+    r = emu.solve(3, d, z, a)
+    ref = oracle.herm_eig(d, z, a)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close_c(r["V"], ref.vec, "U")
+
+
+def test_hermitian_reducible_reported(oracle_lib):
+    r = emu.solve(3, np.array([1.0, 0.5]), np.array([0.0, 1.0 + 1.0j]), 0.0)
+    assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))
+
+
 @pytest.mark.parametrize("n", [2, 60, 300])
 def test_svd(n, oracle_lib):
     pr = W.svd_arrow(n, np.random.default_rng(50 + n))

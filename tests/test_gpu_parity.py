@@ -301,6 +301,58 @@ def test_dpr1_negative_rho(gpu, n, oracle_lib):
     assert_close(_np(out.V)[:, ks], ref.vec, "Q")
 
 
+def _herm_case(n, seed):
+    rng = np.random.default_rng(seed)
+    m = n - 1
+    d = W._sorted_with_gap(rng, m, -1.0, 1.0)[rng.permutation(m)]
+    z = rng.uniform(0.1, 1.0, m) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, m))
+    return d, z, float(rng.uniform(-1.0, 1.0))
+
+
+def _herm(gpu, d, z, a, pairs=False):
+    torch, binding, dev = gpu
+    out = binding.arrow_eig_herm(torch.from_numpy(np.ascontiguousarray(d)).to(dev),
+                                 torch.from_numpy(np.ascontiguousarray(z, dtype=np.complex128)).to(dev), a,
+                                 pairs=pairs)
+    torch.cuda.synchronize(dev)
+    return out
+
+
+def _assert_close_c(got, ref, what, tol=1e-13):
+    den = np.abs(ref)
+    e = np.abs(got - ref) / np.where(den == 0, 1.0, den)
+    worst = float(e.max()) if e.size else 0.0
+    assert np.all(np.isfinite(e)) and worst <= tol, f"{what}: max relative error {worst:.3e}"
+
+
+@pytest.mark.parametrize("n", [1, 2, 97, 1000, 4097])
+def test_hermitian(gpu, n, oracle_lib):
+    """Hermitian arrowhead (Sec. 6.1), every complex vector tile shape; sampled above n = 1000."""
+    d, z, a = _herm_case(n, 95 + n)
+    out = _herm(gpu, d, z, a, pairs=True)
+    ks = np.arange(n) if n <= 1000 else np.arange(0, n, 41)
+    ref = oracle.herm_eig(d, z, a, ks=ks)
+    assert_close(_np(out.lam)[ks], ref.lam, "lambda")
+    assert_close(_np(out.shift)[ks] + _np(out.mu)[ks], ref.lam, "shift+mu")
+    _assert_close_c(_np(out.V)[:, ks], ref.vec, "U")
+
+
+def test_hermitian_real_case_bitwise(gpu):
+    """Real z: the Hermitian path gives the symmetric path's results bit for bit."""
+    pr = W.uniform_arrow(600, np.random.default_rng(96))
+    pr.z[::3] *= -1
+    h = _herm(gpu, pr.d, pr.z.astype(np.complex128), pr.scalar)
+    r = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    assert np.array_equal(_np(h.lam), _np(r.lam))
+    U = _np(h.V)
+    assert np.array_equal(U.real, _np(r.V)) and np.all(U.imag == 0)
+
+
+def test_hermitian_reducible_reported(gpu):
+    out = _herm(gpu, np.array([1.0, 0.5, 0.2]), np.array([1.0 + 1j, 0.0, 2.0]), 0.0)
+    assert np.all(_np(out.info) & 16) and np.all(np.isnan(_np(out.lam)))
+
+
 @pytest.mark.parametrize("n", [1, 2, 97, 1000])
 def test_svd(gpu, n, oracle_lib):
     torch, binding, dev = gpu
