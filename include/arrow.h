@@ -168,6 +168,9 @@ int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
 #define ARROW_KIND_ARROW 0   /* arrowhead: d, z (n-1 each), scalar = alpha */
 #define ARROW_KIND_DPR1 1    /* diag(d) + rho u u^T: d, u (n each), scalar = rho != 0 */
 #define ARROW_KIND_SVD 2     /* triangular arrowhead SVD: d, z (n-1 each), scalar = alpha */
+#define ARROW_KIND_HERM 3    /* Hermitian arrowhead: d (n-1), z (n-1 complex = 2(n-1) doubles as
+                                (re, im) pairs), scalar = alpha; vectors complex (2n^2 doubles,
+                                vec_off must leave them 16-byte aligned) */
 
 typedef struct {
   int32_t kind;       /* ARROW_KIND_* */

@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import binding
-from .workloads import KIND_ARROW, KIND_DPR1, KIND_SVD, Problem
+from .workloads import KIND_ARROW, KIND_DPR1, KIND_HERM, KIND_SVD, Problem
 
 BATCH_GRAPH = 1
 
@@ -78,12 +78,20 @@ def pack(problems: list[Problem], vectors: bool = True, left: bool = True, info:
         D = descs[p]
         D.kind, D.n, D.scalar = pr.kind, pr.n, float(pr.scalar)
         D.d_off, D.z_off = ioff, ioff + ms
-        ins += [np.asarray(pr.d, dtype=np.float64), np.asarray(pr.z, dtype=np.float64)]
-        ioff += 2 * ms
+        if pr.kind == KIND_HERM:   # z as (re, im) pairs
+            ins += [np.asarray(pr.d, dtype=np.float64), np.asarray(pr.z, dtype=np.complex128).view(np.float64)]
+            ioff += 3 * ms
+        else:
+            ins += [np.asarray(pr.d, dtype=np.float64), np.asarray(pr.z, dtype=np.float64)]
+            ioff += 2 * ms
         D.lam_off = ooff
         ooff += pr.n
         D.vec_off, D.left_off = -1, -1
-        if vectors:
+        if vectors and pr.kind == KIND_HERM:
+            ooff += ooff & 1               # complex entries start on 16 bytes
+            D.vec_off = ooff
+            ooff += 2 * pr.n * pr.n
+        elif vectors:
             D.vec_off = ooff
             ooff += pr.n * pr.n
             if pr.kind == KIND_SVD and left:
@@ -147,7 +155,10 @@ class Batch:
         D = self.packed.descs[p]
         n = D.n
         lam = self.out_pool[D.lam_off:D.lam_off + n]
-        V = self.out_pool[D.vec_off:D.vec_off + n * n].view(n, n).t() if D.vec_off >= 0 else None
+        if D.vec_off >= 0 and D.kind == KIND_HERM:
+            V = torch.view_as_complex(self.out_pool[D.vec_off:D.vec_off + 2 * n * n].view(n * n, 2)).view(n, n).t()
+        else:
+            V = self.out_pool[D.vec_off:D.vec_off + n * n].view(n, n).t() if D.vec_off >= 0 else None
         U = self.out_pool[D.left_off:D.left_off + n * n].view(n, n).t() if D.left_off >= 0 else None
         info = self.info_pool[D.info_off:D.info_off + n] if D.info_off >= 0 else None
         return lam, V, U, info

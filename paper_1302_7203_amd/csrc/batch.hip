@@ -1,5 +1,5 @@
-// Batched solves: many independent ARROW / DPR1 / SVD problems of uneven
-// order in one plan of four launches.
+// Batched solves: many independent ARROW / DPR1 / SVD / Hermitian problems of
+// uneven order in one plan of five launches.
 //
 //   k_b_prep    one block per problem: sort (Sec. 1 ordering) and prologue
 //   k_b_stage   persistent: every wavefront takes (problem, eigenvalue-group)
@@ -64,12 +64,14 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
     switch (D.kind) {
       case KIND_ARROW: sort_block<KIND_ARROW>(D); break;
       case KIND_DPR1: sort_block<KIND_DPR1>(D); break;
+      case KIND_HERM: sort_block<KIND_HERM>(D); break;
       default: sort_block<KIND_SVD>(D); break;
     }
   }
   switch (D.kind) {
     case KIND_ARROW: prologue_block<KIND_ARROW>(D); break;
     case KIND_DPR1: prologue_block<KIND_DPR1>(D); break;
+    case KIND_HERM: prologue_block<KIND_HERM>(D); break;
     default: prologue_block<KIND_SVD>(D); break;
   }
 }
@@ -108,7 +110,8 @@ __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))
     const int ln = lane & (G - 1);
     if (k < D.n) {
       switch (D.kind) {
-        case KIND_ARROW: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;
+        case KIND_ARROW:
+        case KIND_HERM: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
         case KIND_DPR1: run_kind<CHECK, KIND_DPR1>(D, opt, G, k, ln); break;
         default: run_kind<CHECK, KIND_SVD>(D, opt, G, k, ln); break;
       }
@@ -133,7 +136,8 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options 
     const int k = (int)list[q];
     if (k < 0 || k >= D.n) continue;
     switch (D.kind) {
-      case KIND_ARROW: check_body<KIND_ARROW, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
+      case KIND_ARROW:
+      case KIND_HERM: check_body<KIND_ARROW, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
       case KIND_DPR1: check_body<KIND_DPR1, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
       default: check_body<KIND_SVD, REPAIR_BLOCK>(D, opt, k, threadIdx.x); break;
     }
@@ -163,6 +167,12 @@ __global__ __launch_bounds__(BLOCK) void k_b_vec(BatchArgs B) {
   switch (D.kind) {
     case KIND_ARROW: vec_one<KIND_ARROW>(D, t, mode); break;
     case KIND_DPR1: vec_one<KIND_DPR1>(D, t, mode); break;
+    case KIND_HERM: {   // complex row tiles at every n
+      const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
+      const int ct = t / row_tiles;
+      vec_tile_c<VEC_RPT>(D, t - ct * row_tiles, ct, VEC_COLS);
+      break;
+    }
     default: vec_one<KIND_SVD>(D, t, mode); break;
   }
 }
@@ -213,7 +223,7 @@ static Layout plan_layout(int64_t count, const arrow_desc_t* descs) {
 }
 
 static int check_desc(const arrow_desc_t& a) {
-  if (a.kind < ARROW_KIND_ARROW || a.kind > ARROW_KIND_SVD) return 1;
+  if (a.kind < ARROW_KIND_ARROW || a.kind > ARROW_KIND_HERM) return 1;
   if (a.n < 1 || a.n > 46340) return 1;
   if (!(a.scalar - a.scalar == 0.0)) return 1;
   if (a.kind == ARROW_KIND_DPR1 && a.scalar == 0.0) return 1;
@@ -268,6 +278,9 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   for (int64_t p = 0; p < count; ++p) {
     if (check_desc(descs[p])) return -3;
     if (descs[p].info_off >= 0 && !info_pool) return -6;
+    // Hermitian vectors are complex: 16-byte aligned
+    if (descs[p].kind == ARROW_KIND_HERM && descs[p].vec_off >= 0 && ((uintptr_t)(out_pool + descs[p].vec_off) & 15))
+      return -3;
   }
   DeviceGuard g(h->device);
   const Layout L = plan_layout(count, descs);
@@ -325,7 +338,11 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     item_start[q] = (int32_t)items;
     items += (a.n + (WAVE / G) - 1) / (WAVE / G);
     vec_start[q] = (int32_t)vchunks;
-    if (D.V) {
+    if (D.V && a.kind == ARROW_KIND_HERM) {
+      const int64_t n = a.n;
+      vec_mode[q] = 1;
+      vchunks += ((n + VEC_TILE - 1) / VEC_TILE) * ((n + VEC_COLS - 1) / VEC_COLS);
+    } else if (D.V) {
       const int64_t n = a.n;
       if (n < VEC_TALL_MIN) {
         vec_mode[q] = 0;

@@ -28,7 +28,7 @@ import numpy as np
 import torch
 
 from . import batch, binding
-from .workloads import KIND_DPR1, KIND_SVD, Problem
+from .workloads import KIND_DPR1, KIND_HERM, KIND_SVD, Problem
 
 ALIGN = 256
 
@@ -73,9 +73,19 @@ def _ms(pr: Problem):
     return pr.n if pr.kind == KIND_DPR1 else pr.n - 1
 
 
+def _vec_at(pr: Problem):
+    """Offset (doubles) of a request's vectors after its n values: Hermitian vectors are
+    complex and start on 16 bytes."""
+    return pr.n + (pr.n & 1 if pr.kind == KIND_HERM else 0)
+
+
+def _in_doubles(pr: Problem):
+    return _ms(pr) * (3 if pr.kind == KIND_HERM else 2)   # Hermitian z: (re, im) pairs
+
+
 def out_doubles(pr: Problem, vectors=True):
-    k = (2 if pr.kind == KIND_SVD else 1) if vectors else 0
-    return pr.n + k * pr.n * pr.n
+    k = (2 if pr.kind in (KIND_SVD, KIND_HERM) else 1) if vectors else 0
+    return _vec_at(pr) + k * pr.n * pr.n
 
 
 def _up(nbytes: int) -> int:
@@ -93,7 +103,7 @@ def request_parts(pr: Problem, vectors=True):
     104-byte descriptor and four table words)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 16 * _ms(pr) + _up(8 * (16 + 24 * pr.n)) + 128
+    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 24 * pr.n)) + 128
     return out, info, rest
 
 
@@ -219,7 +229,10 @@ class Server:
         # inputs of the batch: one contiguous arena chunk, one H2D copy
         ins = []
         for r in reqs:
-            ins += [np.asarray(r.problem.d, dtype=np.float64), np.asarray(r.problem.z, dtype=np.float64)]
+            z = r.problem.z
+            z = np.asarray(z, dtype=np.complex128).view(np.float64) if r.problem.kind == KIND_HERM \
+                else np.asarray(z, dtype=np.float64)
+            ins += [np.asarray(r.problem.d, dtype=np.float64), z]
         in_host = np.concatenate(ins) if ins else np.zeros(1)
         if in_host.size > self.slot_doubles:
             raise ValueError("batch inputs exceed the staging slot")
@@ -230,10 +243,10 @@ class Server:
             ms = _ms(pr)
             D.kind, D.n, D.scalar = pr.kind, pr.n, float(pr.scalar)
             D.d_off, D.z_off = ioff, ioff + ms     # relative; shifted below
-            ioff += 2 * ms
+            ioff += _in_doubles(pr)
             o = r.out[0] // 8
             D.lam_off = o
-            D.vec_off = o + pr.n if self.vectors else -1
+            D.vec_off = o + _vec_at(pr) if self.vectors else -1
             D.left_off = o + pr.n + pr.n * pr.n if (self.vectors and pr.kind == KIND_SVD) else -1
             D.info_off = r.info[0] // 4
         in_chunk = self.arena.alloc(8 * max(1, in_host.size))
@@ -299,7 +312,11 @@ class Server:
         pr, n = req.problem, req.problem.n
         o = req.out[0] // 8
         lam = self.buf[o:o + n]
-        V = self.buf[o + n:o + n + n * n].view(n, n).t() if self.vectors else None
+        v = o + _vec_at(pr)
+        if self.vectors and pr.kind == KIND_HERM:
+            V = torch.view_as_complex(self.buf[v:v + 2 * n * n].view(n * n, 2)).view(n, n).t()
+        else:
+            V = self.buf[v:v + n * n].view(n, n).t() if self.vectors else None
         U = (self.buf[o + n + n * n:o + n + 2 * n * n].view(n, n).t()
              if (self.vectors and pr.kind == KIND_SVD) else None)
         info = self.buf.view(torch.int32)[req.info[0] // 4: req.info[0] // 4 + n]

@@ -17,6 +17,7 @@ only by ranges), so these laws stand in for its workloads:
   dpr1      d as ``uniform``, u = g/||g|| with g ~ N(0, I), rho ~ U(0.1, 10)
   svd       d ~ U(0, 1) sorted with min gap >= 1e-6, z ~ U(0.1, 1), alpha ~ U(0, 1)
   reducible ``uniform`` with some z_j = 0, repeated poles and signed z, shuffled
+  herm      ``uniform`` poles shuffled, z = r e^{i theta}, r ~ U(0.1, 1), theta ~ U(0, 2 pi)
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ import numpy as np
 KIND_ARROW = 0
 KIND_DPR1 = 1
 KIND_SVD = 2
+KIND_HERM = 3
 
 SEED_BASE = 72030
 
@@ -36,7 +38,7 @@ class Problem:
     kind: int                 # KIND_ARROW / KIND_DPR1 / KIND_SVD
     n: int                    # matrix order
     d: np.ndarray             # arrow/svd: n-1 poles; dpr1: n diagonal entries
-    z: np.ndarray             # arrow/svd: n-1 shaft entries; dpr1: u (n entries)
+    z: np.ndarray             # arrow/svd: n-1 shaft entries; dpr1: u (n entries); herm: complex
     scalar: float             # arrow/svd: alpha; dpr1: rho
     meta: dict = field(default_factory=dict)
 
@@ -151,6 +153,15 @@ def serving_requests(count=2200, nmin=32, nmax=8192, rate=1.0, seed=SEED_BASE + 
             pr = svd_arrow(n, rng)
         out.append((t, pr))
     return out
+
+
+def herm_arrow(n, rng):
+    """Hermitian arrowhead (Sec. 6.1): ``uniform`` poles in random order, z = r e^{i theta}
+    with r ~ U(0.1, 1), theta ~ U(0, 2 pi)."""
+    m = n - 1
+    d = _sorted_with_gap(rng, m, -1.0, 1.0)[rng.permutation(m)]
+    z = rng.uniform(0.1, 1.0, m) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, m))
+    return Problem(KIND_HERM, n, d.copy(), z, float(rng.uniform(-1.0, 1.0)))
 
 
 def reducible_arrow(n, rng, zero_frac=0.1, repeat_every=97, triple=True):

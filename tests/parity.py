@@ -7,8 +7,10 @@ TOL = 1e-13   # relative, componentwise, for every eigenvalue and every vector e
 
 
 def relerr(got, ref):
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    """|got - ref| / |ref| entrywise (complex entries by modulus)."""
+    dt = np.complex128 if (np.iscomplexobj(got) or np.iscomplexobj(ref)) else np.float64
+    got = np.asarray(got, dtype=dt)
+    ref = np.asarray(ref, dtype=dt)
     den = np.abs(ref)
     with np.errstate(divide="ignore", invalid="ignore"):
         e = np.abs(got - ref) / den

@@ -32,6 +32,7 @@ def _mixed(count, seed, nmin=16, nmax=300):
     neg = W.dpr1(120, rng)          # rho < 0
     neg.scalar = -neg.scalar
     out.append(neg)
+    out += [W.herm_arrow(33, rng), W.herm_arrow(90, rng)]   # Hermitian (Sec. 6.1)
     out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
     return out
 
@@ -42,6 +43,9 @@ def _oracle(pr):
         return r.lam, r.vec, None
     if pr.kind == W.KIND_DPR1:
         r = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+        return r.lam, r.vec, None
+    if pr.kind == W.KIND_HERM:
+        r = oracle.herm_eig(pr.d, pr.z, pr.scalar)
         return r.lam, r.vec, None
     r = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
     return r.sigma, r.V, r.U
@@ -99,14 +103,16 @@ def test_graph_replays_equal_eager(env):
     eager = batch.Batch(probs, device=dev)
     eager.run()
     torch.cuda.synchronize()
-    ref = eager.out_pool.clone()
+    ref = [[None if t is None else t.clone() for t in eager.result(p)] for p in range(len(probs))]
     g = batch.Batch(probs, device=dev, graph=True)
     for rep in range(3):
         g.out_pool.fill_(float("nan"))          # eager work between replays
         torch.cuda.synchronize()
         g.run()
         torch.cuda.synchronize()
-        assert torch.equal(g.out_pool, ref), f"replay {rep}"
+        for p in range(len(probs)):             # every output of every problem (the pools' padding aside)
+            for a, b in zip(g.result(p), ref[p]):
+                assert (a is None) == (b is None) and (a is None or torch.equal(a, b)), f"replay {rep} problem {p}"
     g.close()
     eager.close()
 
@@ -131,8 +137,8 @@ def test_reducible_row_tiles(env, oracle_lib):
     torch, batch, dev = env
     rng = np.random.default_rng(61)
     probs = [W.reducible_arrow(701, rng), W.uniform_arrow(600, rng), W.reducible_arrow(1024, rng, zero_frac=0.2),
-             W.dpr1(520, rng), W.dpr1(777, rng)]
-    probs[-1].scalar = -probs[-1].scalar     # rho < 0, odd n
+             W.dpr1(520, rng), W.dpr1(777, rng), W.herm_arrow(701, rng)]
+    probs[-2].scalar = -probs[-2].scalar     # rho < 0, odd n
     b = batch.Batch(probs, device=dev)
     b.run()
     _check(b, probs, torch)

@@ -12,7 +12,10 @@ pytestmark = pytest.mark.gpu
 
 def _stream(count, seed, nmax=400, rate=2000.0):
     reqs = W.serving_requests(count=count, nmin=32, nmax=nmax, rate=rate, seed=seed)
-    return [(t, p) for t, p in reqs]
+    out = [(t, p) for t, p in reqs]
+    # every 6th request becomes a Hermitian arrowhead of the same order (odd and even n)
+    rng = np.random.default_rng(seed + 100)
+    return [(t, W.herm_arrow(p.n, rng) if i % 6 == 5 else p) for i, (t, p) in enumerate(out)]
 
 
 def test_served_results_equal_alone_and_oracle(oracle_lib):
@@ -26,7 +29,7 @@ def test_served_results_equal_alone_and_oracle(oracle_lib):
     torch.cuda.synchronize()
     assert all(r.done >= r.arrival for r in reqs)
     assert srv.peak_used <= srv.arena.capacity
-    for r in reqs[:: 7]:
+    for r in reqs[:: 7] + [r for r in reqs if r.problem.kind == W.KIND_HERM][:3]:
         lam, V, U, info = srv.result(r)
         one = batch.Batch([r.problem], device=dev)
         one.run()
@@ -42,6 +45,9 @@ def test_served_results_equal_alone_and_oracle(oracle_lib):
             rl, rV = ref.lam, ref.vec
         elif pr.kind == W.KIND_DPR1:
             ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+            rl, rV = ref.lam, ref.vec
+        elif pr.kind == W.KIND_HERM:
+            ref = oracle.herm_eig(pr.d, pr.z, pr.scalar)
             rl, rV = ref.lam, ref.vec
         else:
             ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)

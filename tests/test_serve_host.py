@@ -87,10 +87,25 @@ def test_request_bytes_cover_the_plan_workspace():
     rng = np.random.default_rng(2)
     for trial in range(6):
         k = 1 if trial < 2 else 20
-        probs = [W.uniform_arrow(int(n), rng) if c == 0 else W.dpr1(int(n), rng) if c == 1 else W.svd_arrow(int(n), rng)
-                 for n, c in zip(rng.integers(1, 300, k), rng.integers(0, 3, k))]
+        gen = (W.uniform_arrow, W.dpr1, W.svd_arrow, W.herm_arrow)
+        probs = [gen[c](int(n), rng) for n, c in zip(rng.integers(1, 300, k), rng.integers(0, 4, k))]
         pk = batch.pack(probs)
         ws = int(L.arrow_batch_workspace_size(len(probs), ctypes.cast(pk.descs, ctypes.c_void_p)))
         up = lambda x: (x + ALIGN - 1) // ALIGN * ALIGN   # noqa: E731
         reserved = sum(request_parts(p)[2] for p in probs) + BATCH_OVERHEAD
         assert up(ws) + up(8 * pk.in_host.size) <= reserved
+
+
+def test_hermitian_packing_aligns_complex_vectors():
+    """Hermitian z goes in as (re, im) pairs and its complex vectors start on 16 bytes."""
+    from paper_1302_7203_amd import batch
+    rng = np.random.default_rng(3)
+    probs = [W.uniform_arrow(4, rng), W.herm_arrow(5, rng), W.dpr1(3, rng), W.herm_arrow(4, rng)]
+    pk = batch.pack(probs)
+    for p, pr in enumerate(probs):
+        D = pk.descs[p]
+        if pr.kind == W.KIND_HERM:
+            assert D.vec_off % 2 == 0
+            z = pk.in_host[D.z_off:D.z_off + 2 * (pr.n - 1)].view(np.complex128)
+            assert np.array_equal(z, pr.z)
+    assert pk.descs[2].d_off == pk.descs[1].z_off + 2 * (probs[1].n - 1)
