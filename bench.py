@@ -251,6 +251,56 @@ def serving_leg(args, dev):
     return res
 
 
+def extensions_leg(args, binding, workloads, dev):
+    """The solver's extensions at n = 4096, each timed like the main workload (inputs resident,
+    HIP-event stage times): a Hermitian arrowhead (Sec. 6.1; complex vectors, 16 bytes per entry),
+    a reducible arrowhead deflated on the device (Sec. 1), and a DPR1 matrix with rho < 0.
+    Throughput and the vector phase's HBM rate only; their parity is checked by the GPU tests
+    on the same generators."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(workloads.SEED_BASE + 7)
+    n = 4096
+    herm = workloads.herm_arrow(n, rng)
+    red = workloads.reducible_arrow(n, rng, zero_frac=0.1, repeat_every=13)
+    neg = workloads.dpr1(n, rng)
+    cases = {
+        "hermitian_4096": (lambda d, z: binding.arrow_eig_herm(d, z, herm.scalar), herm, 16.0,
+                           "Hermitian arrowhead, uniform poles shuffled, z = r e^{i theta}, r~U(0.1,1); complex U"),
+        "reducible_4096": (lambda d, z: binding.arrow_eig(d, z, red.scalar), red, 8.0,
+                           "uniform arrowhead shuffled with 10% z_j = 0 and every 13th pole repeated, deflated"),
+        "dpr1_negative_4096": (lambda d, z: binding.dpr1_eig(d, z, -neg.scalar), neg, 8.0,
+                               "D + rho u u^T with rho = -U(0.1,10), u = g/||g||"),
+    }
+    out = {}
+    steps = max(5, args.steps // 2)
+    for name, (solve, pr, entry_bytes, desc) in cases.items():
+        d = torch.from_numpy(pr.d).to(dev)
+        z = torch.from_numpy(np.ascontiguousarray(pr.z)).to(dev)
+        for _ in range(2):
+            res = solve(d, z)
+        binding.set_option(binding.OPT_TIMING, 1)
+        stages = np.zeros(5)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = solve(d, z)
+            stages += np.array(binding.last_timing())
+        torch.cuda.synchronize(dev)
+        el = time.perf_counter() - t0
+        binding.set_option(binding.OPT_TIMING, 0)
+        st = stages / steps
+        info = res.info.cpu().numpy().astype(np.uint32)
+        out[name] = {"workload": desc, "n": n, "steps": steps, "value": n * steps / el, "unit": "eigenpairs/s",
+                     "ms_per_step": el / steps * 1e3,
+                     "stages_ms": {k: float(v) for k, v in zip(("front", "sort", "root", "check", "vectors"), st)},
+                     "vector_hbm_gbs": entry_bytes * n * n / (st[4] * 1e-3) / 1e9,
+                     "vector_hbm_frac": entry_bytes * n * n / (st[4] * 1e-3) / PEAK_HBM,
+                     "deflated": int(np.sum((info & 1024) != 0)),
+                     "not_solved": int(np.sum((info & 304) != 0))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +318,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-batch", type=int, default=4096, help="most requests one launch may take")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the Hermitian / reducible / rho < 0 legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -357,6 +409,8 @@ def main():
         result["batched"] = batched_leg(args, binding, workloads, dev)
     if not args.no_serve:
         result["serving"] = serving_leg(args, dev)
+    if not args.no_extensions:
+        result["extensions"] = extensions_leg(args, binding, workloads, dev)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -42,11 +42,12 @@ static_assert(ARROW_INFO_DD_B == INFO_DD_B && ARROW_INFO_REMEDY_A == INFO_REMEDY
 // kernels
 
 // Sorting (symmetric permutation to decreasing poles, Sec. 1): a one-block
-// check whether the input already is in that order (the usual case), then,
-// only if not, a rank count over a 2-D grid of (pole tile, comparison chunk)
-// blocks, then the scatter.  rank[] holds the count in its low 30 bits and a
-// duplicate marker in bit 30.
-constexpr int SORT_CHUNK = 2048;
+// check whether the input already is in that order, or in the reverse one
+// (the usual cases), then, only if not, a rank count over a 2-D grid of (pole
+// tile, comparison chunk) blocks, then the scatter.  rank[] holds the count
+// in its low 30 bits and a duplicate marker in bit 30.
+constexpr int SORT_CHUNK = 256;   // keys of one comparison chunk
+constexpr int SORT_BLOCK = 1024;  // the last block also scatters and runs the prologue: a wide one
 
 __host__ __device__ inline uint32_t* rank_array(const Ws& w, int64_t n) { return w.st + n; }
 
@@ -62,10 +63,16 @@ template <int KIND>
 __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
   const Ws w = ws_view(D.ws, D.n);
   const int ms = sorted_count(D);
-  int bad = 0;
-  for (int j = threadIdx.x; j + 1 < ms; j += FRONT_BLOCK)
-    if (!(sort_key<KIND>(in_pole<KIND>(D, j)) > sort_key<KIND>(in_pole<KIND>(D, j + 1)))) bad = 1;
-  bad = __syncthreads_or(bad);
+  int down = 0, up = 0;   // some pair not strictly decreasing / not strictly increasing
+  for (int j = threadIdx.x; j + 1 < ms; j += FRONT_BLOCK) {
+    const double a = sort_key<KIND>(in_pole<KIND>(D, j)), b = sort_key<KIND>(in_pole<KIND>(D, j + 1));
+    if (!(a > b)) down = 1;
+    if (!(a < b)) up = 1;
+  }
+  down = __syncthreads_or(down);
+  up = __syncthreads_or(up);
+  const bool rev = down && !up;   // strictly increasing: sorted index ms-1-j
+  const int bad = down && up;
   if (bad) {
     uint32_t* rank = rank_array(w, D.n);
     for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) rank[j] = 0;
@@ -76,7 +83,7 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
     return;
   }
   for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
-    put_sorted<KIND>(D, w, j, j);
+    put_sorted<KIND>(D, w, rev ? ms - 1 - j : j, j);
     w.st[j] = input_status<KIND>(D, j, false);
   }
   __syncthreads();
@@ -89,31 +96,33 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
 // (a completion count) then holds every rank, scatters the poles into
 // decreasing order and runs the prologue.
 template <int KIND>
-__global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
-  __shared__ double tile[BLOCK];
+__global__ __launch_bounds__(SORT_BLOCK) void k_sort(ProbDesc D, int chunk, int nchunks) {
+  __shared__ double tile[SORT_BLOCK];
   __shared__ int last;
   const Ws w = ws_view(D.ws, D.n);
   if (w.hdr[5] == 0.0) return;  // already sorted: k_front did everything
   const int ms = sorted_count(D);
   uint32_t* rank = rank_array(w, D.n);
-  const int j = blockIdx.x * BLOCK + threadIdx.x;
+  const int j = blockIdx.x * SORT_BLOCK + threadIdx.x;
   const double kj = (j < ms) ? sort_key<KIND>(in_pole<KIND>(D, j)) : NAN;
-  const int l0 = blockIdx.y * SORT_CHUNK;
-  const int l1 = min(ms, l0 + SORT_CHUNK);
   uint32_t cnt = 0;
   bool dup = false;
-  for (int base = l0; base < l1; base += BLOCK) {
-    const int l = base + threadIdx.x;
-    tile[threadIdx.x] = (l < l1) ? sort_key<KIND>(in_pole<KIND>(D, l)) : NAN;
-    __syncthreads();
-    const int lim = min(BLOCK, l1 - base);
-    for (int t = 0; t < lim; ++t) {
-      const double kl = tile[t];
-      const int idx = base + t;
-      cnt += (kl > kj) || (kl == kj && idx < j);
-      dup |= (kl == kj) && (idx != j);
+  for (int cy = blockIdx.y; cy < nchunks; cy += gridDim.y) {   // this block's comparison chunks
+    const int l0 = cy * chunk;
+    const int l1 = min(ms, l0 + chunk);
+    for (int base = l0; base < l1; base += SORT_BLOCK) {
+      const int l = base + threadIdx.x;
+      tile[threadIdx.x] = (l < l1) ? sort_key<KIND>(in_pole<KIND>(D, l)) : NAN;
+      __syncthreads();
+      const int lim = min(SORT_BLOCK, l1 - base);
+      for (int t = 0; t < lim; ++t) {
+        const double kl = tile[t];
+        const int idx = base + t;
+        cnt += (kl > kj) || (kl == kj && idx < j);
+        dup |= (kl == kj) && (idx != j);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   if (j < ms) {
     if (cnt) atomicAdd(&rank[j], cnt);
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   __syncthreads();
   if (!last) return;
   __threadfence();
-  for (int q = threadIdx.x; q < ms; q += BLOCK) {
+  for (int q = threadIdx.x; q < ms; q += SORT_BLOCK) {
     const uint32_t raw = __hip_atomic_load(&rank[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int r = (int)(raw & 0x3fffffffu);
     put_sorted<KIND>(D, w, r, q);
@@ -133,7 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort(ProbDesc D) {
   }
   __threadfence();
   __syncthreads();
-  prologue_block<KIND, BLOCK>(D);
+  prologue_block<KIND, SORT_BLOCK>(D);
 }
 
 // Root and check stages: ROOT_BLOCK threads per block, G lanes per
@@ -291,9 +300,14 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   hipLaunchKernelGGL(k_front<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
   mark(1);
   if (ms > 0) {
-    const unsigned jt = (unsigned)((ms + BLOCK - 1) / BLOCK);
-    const unsigned lc = (unsigned)((ms + SORT_CHUNK - 1) / SORT_CHUNK);
-    hipLaunchKernelGGL(k_sort<KIND>, dim3(jt, lc), dim3(BLOCK), 0, st, D);
+    // about SORT_GRID blocks in all (they return at once when k_front found the
+    // order), each comparing its key tile against one or more chunks
+    constexpr int64_t SORT_GRID = 256;
+    const int64_t jt = (ms + SORT_BLOCK - 1) / SORT_BLOCK;
+    const int64_t nchunks = (ms + SORT_CHUNK - 1) / SORT_CHUNK;
+    const int64_t lc = std::max<int64_t>(1, std::min<int64_t>({nchunks, SORT_GRID / jt, 65535}));
+    hipLaunchKernelGGL(k_sort<KIND>, dim3((unsigned)jt, (unsigned)lc), dim3(SORT_BLOCK), 0, st, D, SORT_CHUNK,
+                       (int)nchunks);
   }
   mark(2);
   const int G = single_lanes(h, D.n);

@@ -107,19 +107,25 @@ __device__ inline void prologue_block(const ProbDesc& D) {
 }
 
 // Sort of one problem by one block: a copy when the input already has
-// strictly decreasing keys, else the rank of every key (ties by index).
+// strictly decreasing (or strictly increasing) keys, else the rank of every
+// key (ties by index).
 template <int KIND>
 __device__ inline void sort_block(const ProbDesc& D) {
   __shared__ double tile[BLOCK];
   const Ws w = ws_view(D.ws, D.n);
   const int ms = sorted_count(D);
-  int bad = 0;
-  for (int j = threadIdx.x; j + 1 < ms; j += BLOCK)
-    if (!(sort_key<KIND>(in_pole<KIND>(D, j)) > sort_key<KIND>(in_pole<KIND>(D, j + 1)))) bad = 1;
-  bad = __syncthreads_or(bad);
-  if (!bad) {
+  int down = 0, up = 0;
+  for (int j = threadIdx.x; j + 1 < ms; j += BLOCK) {
+    const double a = sort_key<KIND>(in_pole<KIND>(D, j)), b = sort_key<KIND>(in_pole<KIND>(D, j + 1));
+    if (!(a > b)) down = 1;
+    if (!(a < b)) up = 1;
+  }
+  down = __syncthreads_or(down);
+  up = __syncthreads_or(up);
+  if (!(down && up)) {
+    const bool rev = down != 0;
     for (int j = threadIdx.x; j < ms; j += BLOCK) {
-      put_sorted<KIND>(D, w, j, j);
+      put_sorted<KIND>(D, w, rev ? ms - 1 - j : j, j);
       w.st[j] = input_status<KIND>(D, j, false);
     }
     __syncthreads();

@@ -18,7 +18,7 @@ def build():
     deps = [SRC] + [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
     if os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(p) for p in deps):
         return LIB
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"   # concurrent test workers may build at once
     subprocess.run(["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-host-only", "-O2", "-std=c++17", "-fPIC",
                     "-shared", "-ffp-contract=off", "-fopenmp", "-o", tmp, SRC], check=True,
                    capture_output=True)

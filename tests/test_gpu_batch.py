@@ -33,6 +33,9 @@ def _mixed(count, seed, nmin=16, nmax=300):
     neg.scalar = -neg.scalar
     out.append(neg)
     out += [W.herm_arrow(33, rng), W.herm_arrow(90, rng)]   # Hermitian (Sec. 6.1)
+    inc = W.uniform_arrow(77, rng)                          # poles in increasing order
+    inc.d, inc.z = inc.d[::-1].copy(), inc.z[::-1].copy()
+    out.append(inc)
     out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
     return out
 

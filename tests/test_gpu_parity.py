@@ -180,6 +180,18 @@ def test_order_and_sign_invariance_bitwise(gpu):
     assert np.array_equal(_np(fl.V)[7], -_np(base.V)[7])
 
 
+@pytest.mark.parametrize("n", [3, 700, 5000])
+def test_increasing_input_equals_decreasing_bitwise(gpu, n):
+    """Poles given in increasing order take the front end's reversed copy: the same
+    eigenvalues bit for bit, and the vectors with their rows reversed."""
+    pr = W.uniform_arrow(n, np.random.default_rng(300 + n))
+    a = _arrow(gpu, pr.d, pr.z, pr.scalar)
+    b = _arrow(gpu, pr.d[::-1].copy(), pr.z[::-1].copy(), pr.scalar)
+    assert np.array_equal(_np(a.lam), _np(b.lam))
+    Va, Vb = _np(a.V), _np(b.V)
+    assert np.array_equal(Va[:-1][::-1], Vb[:-1]) and np.array_equal(Va[-1], Vb[-1])
+
+
 def test_repeat_is_bitwise_deterministic(gpu):
     pr = W.single_graded_4096()
     a = _arrow(gpu, pr.d, pr.z, pr.scalar)
