@@ -33,13 +33,17 @@ METRIC = "eigenpairs/s (FP64, rel err≤1e-13) batched vs per-solve launch; p99 
 PEAK_FP64_VECTOR = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 PEAK_HBM = 8.0e12               # bytes/s
 
-# Algorithmic FP64 operations per pole term of each O(n) pass (an FMA counts
-# 2, a divide or square root 1), read off the kernel bodies:
-F_BISECT = 6      # bisection step: e = d_j - d_i, fma(-nu, e, 1), e*(.), c_j/(.), sum
-F_RATIONAL = 11   # rational step: e, fma(nu, e, -1), e*(.), 1/(.), c_j*q, sum, t*e, e*q, *, sum
-F_SELECT = 4      # shift selection: (d_j - d_k) - mid, c_j/(.), sum
-F_DD = 44         # b in double-double: TwoSum (6), two-digit dd quotient (17), TwoSum accumulate (9), FP64 part (12)
-F_NORM = 6        # eigenvector norm: ((e_j - s) - mu)^2, c_j/(.), sum
+# Algorithmic FP64 operations per pole term of each O(n) pass, read off the
+# kernel bodies (solver.hpp): +, -, * and a reciprocal count 1, an FMA 2;
+# max and abs are not counted.
+F_BISECT = 7      # bisection step: e = d_j - d_i (1), fma(-nu, e, 1) (2), e*(.) (1), 1/(.) (1), fma(c_j, ., S) (2)
+F_RATIONAL = 14   # rational step: e (1), fma(nu, e, -1) (2), e*(.) (1), 1/(.) (1), v = e q (1), fma(c_j, q, .) (2),
+                  # (c_j v) v (2), sum (1), e v (1), fma(d1, e v, .) (2)
+F_SELECT = 5      # shift selection: (d_j - d_k) - mid (2), 1/(.) (1), fma(c_j, ., s) (2)
+F_DD = 30         # b in double-double: e (1), 1/e (1), the rest of TwoSum(d_j, -d_i) (5), two-digit quotient
+                  # (q1 1, TwoProd 3, remainder 5, second digit 1), TwoSum accumulate (8), Gershgorin
+                  # terms |w_j| (1), sum (1), side*delta_j (1), fma (2)
+F_NORM = 7        # eigenvector norm: (e_j - s) - mu (3), 1/(.) (1), c_j r (1), fma(., r, acc) (2)
 
 WORKLOADS = {
     "graded_4096": ("single graded arrowhead n=4096: |d| log-uniform [1e-10,1e10] with random signs "

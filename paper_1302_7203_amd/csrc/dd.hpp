@@ -88,12 +88,18 @@ __host__ __device__ inline double dd_to_d(dd a) { return a.hi + a.lo; }
 // exact through TwoProd) times r once more.  q1 need not be the rounded
 // quotient: the remainder carries its error exactly, so the pair is good to a
 // few units of 2^-104 -- enough where quotients of one sign are summed, which
-// is the only use.
-__host__ __device__ inline dd dd_div2(dd c, dd e, double r) {
+// is the only use.  dd_div2_raw leaves the pair unnormalised (|q.lo| is a few
+// ulps of q.hi), which is all dd_acc needs; dd_div2 renormalises it.
+__host__ __device__ inline dd dd_div2_raw(dd c, dd e, double r) {
   const double q1 = c.hi * r;
   const dd p = two_prod(q1, e.hi);
   const double rem = (((c.hi - p.hi) - p.lo) + c.lo) - q1 * e.lo;
-  return fast_two_sum(q1, rem * r);
+  return {q1, rem * r};
+}
+
+__host__ __device__ inline dd dd_div2(dd c, dd e, double r) {
+  const dd q = dd_div2_raw(c, e, r);
+  return fast_two_sum(q.hi, q.lo);
 }
 
 // s += q for a running sum of terms of one sign: the error of every leading

@@ -272,29 +272,25 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   const double di = P.ds[i];
   const double sg = (double)side;
   dd p1 = {0.0, 0.0}, p2 = {0.0, 0.0};  // sum over j < i (>= 0), j > i (<= 0)
-  double f1 = 0.0, f2 = 0.0;            // the same sums in FP64
+  double f1 = 0.0, f2 = 0.0;            // the same sums in FP64 (Algorithm 2 only)
   double wsum = 0.0;                    // sum_{j != i} |shaft_j| / |e_j|
-  double dx = -INFINITY, gx = -INFINITY;  // max over j != i of side*delta_j and side*delta_j + |w_j|
+  double gx = -INFINITY;                // max over j != i of side*delta_j + |w_j|
   const double rzi = 1.0 / P.dz[i];
   for_terms<G>(ln, m, i, [&](int j, bool above) {
     const double ej = pdiff<KIND>(P.ds[j], di);
     const double rj = recip(ej);                    // delta_j, the diagonal of A_i^{-1}
-    const double t = P.ch[j] * rj;
-    if (above) f2 += t; else f1 += t;
-    if constexpr (!FP64_B) {
-      const dd q = dd_div2(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
+    if constexpr (FP64_B) {
+      const double t = P.ch[j] * rj;
+      if (above) f2 += t; else f1 += t;
+    } else {
+      const dd q = dd_div2_raw(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
     const double wj = P.dz[j] * fabs(rj);           // |w_j| |zeta_i|
     wsum += wj;
-    const double srj = sg * rj;
-    dx = fmax(dx, srj);
-    gx = fmax(gx, fma(wj, rzi, srj));
+    gx = fmax(gx, fma(wj, rzi, sg * rj));
   });
-  f1 = gsum<G>(f1);
-  f2 = gsum<G>(f2);
   wsum = gsum<G>(wsum);
-  dx = gmax<G>(dx);
   gx = gmax<G>(gx);
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
   const double ci = P.ch[i];
@@ -302,11 +298,15 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   double num_abs;
   if constexpr (FP64_B) {
     // Algorithm 2: b = (-a + sum_{j<i} + sum_{j>i}) / zeta_i^2, all in FP64
+    f1 = gsum<G>(f1);
+    f2 = gsum<G>(f2);
     r.b = ((-a.hi + f1) + f2) / ci;
     num_abs = fabs(r.b) * ci;
   } else {
     p1 = gsum_dd<G>(dd_norm(p1));
     p2 = gsum_dd<G>(dd_norm(p2));
+    f1 = p1.hi;
+    f2 = p2.hi;
     dd pp, qq;
     if (-a.hi > 0) { pp = dd_add(dd_neg(a), p1); qq = dd_neg(p2); }
     else { pp = p1; qq = dd_sub(a, p2); }
@@ -318,9 +318,12 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   // Gershgorin discs of A_i^{-1}: rows j != i (centre delta_j, radius |w_j|),
   // row i (centre 0, radius 1/|zeta_i|), last row (centre b, radius ||w||_1).
   // On the requested side, in the variable side*nu: the extreme eigenvalue
-  // lies right of every centre and left of every disc's far end.
+  // lies right of every centre and left of every disc's far end.  The
+  // rightmost centre side*delta_j > 0 belongs to the pole next to d_i on
+  // that side (the smallest |e_j| of that sign); with none, the row-i centre 0.
   const double w1 = (wsum + 1.0) * rzi;
-  const double xl = fmax(dx, 0.0);
+  const int jn = i - side;
+  const double xl = (jn >= 0 && jn < m) ? fmax(sg * recip(pdiff<KIND>(P.ds[jn], di)), 0.0) : 0.0;
   const double xh = fmax(fmax(gx, rzi), sg * r.b + w1);
   if (side > 0) { r.lo = xl; r.hi = xh; }
   else { r.lo = -xh; r.hi = -xl; }
