@@ -128,19 +128,21 @@ __global__ __launch_bounds__(SORT_BLOCK) void k_sort(ProbDesc D, int chunk, int 
     if (cnt) atomicAdd(&rank[j], cnt);
     if (dup) atomicOr(&rank[j], 1u << 30);
   }
-  __threadfence();
+  // Every thread releases its counts at device scope (a write-back, no
+  // invalidation of the L2), then one thread counts the block in; only the
+  // last block acquires before it reads the ranks.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(sort_done(w), 1u) == gridDim.x * gridDim.y - 1;
   __syncthreads();
   if (!last) return;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   for (int q = threadIdx.x; q < ms; q += SORT_BLOCK) {
     const uint32_t raw = __hip_atomic_load(&rank[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int r = (int)(raw & 0x3fffffffu);
-    put_sorted<KIND>(D, w, r, q);
+    if (r < ms) put_sorted<KIND>(D, w, r, q);   // a rank is < ms by construction
     w.st[q] = input_status<KIND>(D, q, (raw >> 30) & 1u);
   }
-  __threadfence();
   __syncthreads();
   prologue_block<KIND, SORT_BLOCK>(D);
 }

@@ -330,12 +330,12 @@ __device__ inline void vec_flat(const ProbDesc& D, int t) {
 // one of the `blocks` blocks must call this.
 __device__ inline void place_deflated_last(const ProbDesc& D, const Ws& w, uint32_t blocks) {
   __shared__ int last;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this thread's results, device-wide
   __syncthreads();
   if (threadIdx.x == 0) last = atomicAdd(place_done(w), 1u) == blocks - 1;
   __syncthreads();
   if (!last) return;
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every block's results, in the last block
   const int nd = deflated_count(w);
   for (int s = threadIdx.x; s < nd; s += blockDim.x) place_deflated(D, w, s);
 }
