@@ -10,4 +10,5 @@ from .oracle import (  # noqa: F401
     dpr1_eig,
     arrow_svd,
     herm_eig,
+    tridiag_eig,
 )

@@ -858,3 +858,137 @@ int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
   free(key); free(order); free(dq); free(cq);
   return 0;
 }
+
+/*
+ * Symmetric tridiagonal T = tridiag(b, a, b): a diagonal (n), b off-diagonal
+ * (n-1).  Plain definition, in binary128:
+ *   eigenvalues: the k-th largest is located by bisection on the number of
+ *     eigenvalues below x, which is the number of negative pivots of the LDL^T
+ *     factorisation of T - xI (Sylvester's law of inertia), started from the
+ *     Gershgorin interval and run to a width of 2^-110 relative;
+ *   eigenvectors: two steps of inverse iteration with that eigenvalue
+ *     (Gaussian elimination with partial pivoting of the banded T - lI),
+ *     normalised, with the sign that makes the largest-magnitude entry
+ *     positive.
+ * Q: n x nk column-major.  Returns 0, -1 bad argument, -100 no memory.
+ */
+static int64_t sturm_below(int64_t n, const R *a, const R *b2, R x, R pivmin) {
+  int64_t neg = 0;
+  R q = a[0] - x;
+  for (int64_t i = 0;;) {
+    if (fabsq(q) < pivmin) q = -pivmin;
+    if (q < 0) ++neg;
+    if (++i == n) break;
+    q = (a[i] - x) - b2[i - 1] / q;
+  }
+  return neg;
+}
+
+static void inverse_iteration(int64_t n, const R *a, const R *b, R lam, R *x, R *w) {
+  /* rows of the banded factor: (T - lam I) with partial pivoting keeps up to two
+     superdiagonals: u0 (diagonal), u1, u2; l (multiplier); p (swap) */
+  R *u0 = w, *u1 = w + n, *u2 = w + 2 * n, *l = w + 3 * n;
+  char *p = (char *)(w + 4 * n);
+  R scale = 0;
+  for (int64_t i = 0; i < n; ++i) scale = fmaxq(scale, fabsq(a[i]) + (i ? fabsq(b[i - 1]) : 0) + (i < n - 1 ? fabsq(b[i]) : 0));
+  R tiny = scale * 1e-40Q + 1e-4000Q;
+  /* elimination */
+  R d0 = a[0] - lam, e0 = n > 1 ? b[0] : 0, f0 = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (i == n - 1) { u0[i] = fabsq(d0) < tiny ? tiny : d0; u1[i] = 0; u2[i] = 0; p[i] = 0; l[i] = 0; break; }
+    R sub = b[i], dn = a[i + 1] - lam, en = i + 2 < n ? b[i + 1] : 0;
+    if (fabsq(sub) > fabsq(d0)) {     /* swap rows i and i+1 */
+      p[i] = 1;
+      u0[i] = sub; u1[i] = dn; u2[i] = en;
+      R m = d0 / sub;
+      l[i] = m;
+      d0 = e0 - m * dn;
+      e0 = f0 - m * en;
+    } else {
+      p[i] = 0;
+      if (fabsq(d0) < tiny) d0 = tiny;
+      u0[i] = d0; u1[i] = e0; u2[i] = f0;
+      R m = sub / d0;
+      l[i] = m;
+      d0 = dn - m * e0;
+      e0 = en - m * f0;
+    }
+    f0 = 0;
+  }
+  for (int it = 0; it < 2; ++it) {
+    /* forward: apply the row operations to x */
+    for (int64_t i = 0; i + 1 < n; ++i) {
+      if (p[i]) { R t = x[i]; x[i] = x[i + 1]; x[i + 1] = t; }
+      x[i + 1] -= l[i] * x[i];
+    }
+    /* back substitution */
+    for (int64_t i = n - 1; i >= 0; --i) {
+      R s = x[i];
+      if (i + 1 < n) s -= u1[i] * x[i + 1];
+      if (i + 2 < n) s -= u2[i] * x[i + 2];
+      x[i] = s / u0[i];
+    }
+    R nrm = 0, big = 0;
+    for (int64_t i = 0; i < n; ++i) { nrm += x[i] * x[i]; }
+    nrm = sqrtq(nrm);
+    for (int64_t i = 0; i < n; ++i) { x[i] /= nrm; if (fabsq(x[i]) > fabsq(big)) big = x[i]; }
+    if (it == 1 && big < 0)
+      for (int64_t i = 0; i < n; ++i) x[i] = -x[i];
+  }
+}
+
+int oracle_tridiag_eig(int64_t n, const double *a, const double *b, int64_t nk, const int64_t *ks,
+                       double *lam, double *Q, int nthreads) {
+  if (n < 1 || nk < 0 || (!ks && nk != n)) return -1;
+  for (int64_t i = 0; i < n; ++i) if (!finite_d(a[i]) || (i < n - 1 && !finite_d(b[i]))) return -1;
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    if (k < 0 || k >= n) return -1;
+  }
+  R *aq = (R *)malloc((size_t)n * sizeof *aq);
+  R *bq = (R *)malloc((size_t)(n > 1 ? n - 1 : 1) * sizeof *bq);
+  R *b2 = (R *)malloc((size_t)(n > 1 ? n - 1 : 1) * sizeof *b2);
+  if (!aq || !bq || !b2) { free(aq); free(bq); free(b2); return -100; }
+  R lo = 1e4000Q, hi = -1e4000Q, tmax = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    aq[i] = (R)a[i];
+    R r = (i ? fabsq((R)b[i - 1]) : 0) + (i < n - 1 ? fabsq((R)b[i]) : 0);
+    if (aq[i] - r < lo) lo = aq[i] - r;
+    if (aq[i] + r > hi) hi = aq[i] + r;
+    if (fabsq(aq[i]) + r > tmax) tmax = fabsq(aq[i]) + r;
+  }
+  for (int64_t i = 0; i + 1 < n; ++i) { bq[i] = (R)b[i]; b2[i] = bq[i] * bq[i]; }
+  R pivmin = (tmax > 0 ? tmax : 1) * 1e-4000Q;
+  if (pivmin == 0) pivmin = 1e-4900Q;
+  set_threads(nthreads);
+  int fail = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < nk; ++i) {
+    int64_t k = ks ? ks[i] : i;
+    /* the k-th largest: n-1-k eigenvalues lie below it */
+    R l = lo - 1, h = hi + 1;
+    for (int it = 0; it < 20000; ++it) {
+      R mid = l / 2 + h / 2;
+      if (h - l <= fmaxq(fabsq(l), fabsq(h)) * 7.7e-34Q || mid <= l || mid >= h) break;
+      if (sturm_below(n, aq, b2, mid, pivmin) <= n - 1 - k) l = mid; else h = mid;
+    }
+    R ev = l / 2 + h / 2;
+    if (lam) lam[i] = (double)ev;
+    if (Q) {
+      R *x = (R *)malloc((size_t)n * sizeof *x);
+      R *w = (R *)malloc((size_t)n * (4 * sizeof(R) + 1) + 16);
+      if (!x || !w) {
+        free(x); free(w);
+#pragma omp atomic write
+        fail = 1;
+        continue;
+      }
+      for (int64_t j = 0; j < n; ++j) x[j] = 1 + (R)((j * 7919) % 97) / 97;   /* a fixed start */
+      inverse_iteration(n, aq, bq, ev, x, w);
+      for (int64_t j = 0; j < n; ++j) Q[i * n + j] = (double)x[j];
+      free(x); free(w);
+    }
+  }
+  free(aq); free(bq); free(b2);
+  return fail ? -100 : 0;
+}

@@ -46,7 +46,9 @@ def _load(path=None):
         lib.oracle_dpr1_eig.argtypes = [I64, P, P, D, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_arrow_svd.argtypes = [I64, P, P, D, I64, P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_herm_eig.argtypes = [I64, P, P, P, D, I64, P, P, P, P, P, P, P, P, ctypes.c_int]
-        for f in (lib.oracle_arrow_eig, lib.oracle_dpr1_eig, lib.oracle_arrow_svd, lib.oracle_herm_eig):
+        lib.oracle_tridiag_eig.argtypes = [I64, P, P, I64, P, P, P, ctypes.c_int]
+        for f in (lib.oracle_arrow_eig, lib.oracle_dpr1_eig, lib.oracle_arrow_svd, lib.oracle_herm_eig,
+                  lib.oracle_tridiag_eig):
             f.restype = ctypes.c_int
         _libs[key] = lib
     return _libs[key]
@@ -166,3 +168,17 @@ def arrow_svd(d, z, alpha, ks=None, vectors=True, threads=0, lib=None) -> SvdRes
                                   _ptr(s), _ptr(slo), _ptr(U), _ptr(V), _ptr(rel), int(threads))
     _check(rc, "oracle_arrow_svd")
     return SvdResult(s, slo, None if U is None else U.T, None if V is None else V.T, rel, k)
+
+
+def tridiag_eig(a, b, ks=None, vectors=True, threads=0, lib=None):
+    """Eigenpairs of the symmetric tridiagonal matrix with diagonal a (n) and off-diagonal b (n-1):
+    (lam, Q) with lam descending over ks and Q[:, i] the i-th vector, largest-magnitude entry > 0."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = a.size
+    k = _ks(n, ks)
+    lam = np.empty(k.size)
+    Q = np.empty((k.size, n)) if vectors else None
+    rc = _load(lib).oracle_tridiag_eig(n, _ptr(a), _ptr(b), k.size, _ptr(k), _ptr(lam), _ptr(Q), int(threads))
+    _check(rc, "oracle_tridiag_eig")
+    return lam, (None if Q is None else Q.T)

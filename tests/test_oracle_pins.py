@@ -517,6 +517,64 @@ def test_herm_real_case(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# symmetric tridiagonal (the divide-and-conquer application of Sec. 1)
+
+def _dense_tridiag(a, b):
+    n = len(a)
+    T = [[Fraction(0)] * n for _ in range(n)]
+    for i in range(n):
+        T[i][i] = F(a[i])
+        if i + 1 < n:
+            T[i][i + 1] = T[i + 1][i] = F(b[i])
+    return T
+
+
+def _tridiag_failures(a, b, lam, Q):
+    """Exact eigenvalues (rounded once: half an ulp, or the bisection floor), the null
+    vector of T - lambda I, and the sign rule (largest entry positive)."""
+    bad = []
+    n = len(a)
+    T = _dense_tridiag(a, b)
+    ex = brute.exact_eigvals(T)
+    for k in range(n):
+        if abs(F(lam[k]) - ex[k]) > abs(ex[k]) * Fraction(1, 2 ** 53) + Fraction(1, 2 ** 399):
+            bad.append(f"lambda_{k}")
+        q = Q[:, k]
+        j = int(np.argmax(np.abs(q)))
+        if not q[j] > 0:
+            bad.append(f"sign {k}")
+        # T q = lambda q to the rounding of q: the exact residual of the rounded vector
+        res = max(abs(sum(T[i][l] * F(q[l]) for l in range(n)) - ex[k] * F(q[i])) for i in range(n))
+        if res > Fraction(8 * n, 2 ** 53) * (1 + max(abs(x) for x in ex)):
+            bad.append(f"vector {k}")
+    return bad
+
+
+@pytest.mark.parametrize("n,seed", [(1, 41), (2, 42), (5, 43), (6, 44)])
+def test_tridiag_exact(n, seed, oracle_lib):
+    rng = np.random.default_rng(seed)
+    a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    lam, Q = oracle.tridiag_eig(a, b)
+    assert _tridiag_failures(a, b, lam, Q) == []
+
+
+@pytest.mark.parametrize("n,seed", [(40, 45), (200, 46)])
+def test_tridiag_against_lapack(n, seed, oracle_lib):
+    """LAPACK's dsyevd (numpy) is normwise accurate: eigenvalues agree to a few n eps ||T||;
+    the oracle's vectors are orthonormal with residual at its own rounding."""
+    rng = np.random.default_rng(seed)
+    a, b = rng.standard_normal(n), rng.standard_normal(n - 1)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    lam, Q = oracle.tridiag_eig(a, b)
+    ev = np.linalg.eigvalsh(T)[::-1]
+    tn = np.abs(T).sum(axis=1).max()
+    assert np.max(np.abs(lam - ev)) <= 4 * n * 2.0 ** -53 * tn
+    Tl, Ql = T.astype(np.longdouble), Q.astype(np.longdouble)
+    assert np.max(np.abs(Tl @ Ql - Ql * lam.astype(np.longdouble))) <= 4 * 2.0 ** -53 * tn
+    assert np.max(np.abs(Ql.T @ Ql - np.eye(n))) <= 4 * n * 2.0 ** -53
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: every one must be caught by the pins above
 
 _MUTANTS = {
@@ -538,6 +596,8 @@ _MUTANTS = {
     "dpr1_negative_tau_sign": ("t = -((R)th[i] + (R)tl[i])", "t = ((R)th[i] + (R)tl[i])"),
     "herm_conjugated_vector": ("col[2 * j + 1] = (double)((R)zi[j] / den);", "col[2 * j + 1] = (double)(-(R)zi[j] / den);"),
     "herm_modulus_real_part_only": ("cq[j] = (R)zr[o] * (R)zr[o] + (R)zi[o] * (R)zi[o];", "cq[j] = (R)zr[o] * (R)zr[o];"),
+    "tridiag_sturm_b_not_squared": ("b2[i] = bq[i] * bq[i];", "b2[i] = fabsq(bq[i]);"),
+    "tridiag_back_substitution_sign": ("s -= u1[i] * x[i + 1];", "s += u1[i] * x[i + 1];"),
     "vector_tau_sign": ("R x = (R)z[j] / (((R)d[j] - dp) - r.tau);\n        col[j]",
                         "R x = (R)z[j] / (((R)d[j] - dp) + r.tau);\n        col[j]"),
 }
@@ -589,6 +649,14 @@ def _quick_pins(lib):
 
 def _quick_extension_pins(lib):
     failed = []
+    rng = np.random.default_rng(47)
+    a, b = rng.standard_normal(5), rng.standard_normal(4)
+    try:
+        lam, Q = oracle.tridiag_eig(a, b, lib=lib)
+        if _tridiag_failures(a, b, lam, Q):
+            failed.append("tridiagonal")
+    except (oracle.oracle.OracleError, ValueError, ZeroDivisionError):
+        failed.append("tridiagonal error")
     d, z, a = _herm_case(5, 87)
     try:
         if _herm_failures(d, z, a, oracle.herm_eig(d, z, a, lib=lib), dps=30):
