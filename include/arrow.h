@@ -156,6 +156,29 @@ int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, doub
 int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
               double* sigma, double* U, int64_t ldu, double* V, int64_t ldv, uint32_t* info);
 
+/*
+ * Eigen-decomposition of the symmetric tridiagonal T = tridiag(b, a, b) of
+ * order 1 <= n <= 46340 by divide and conquer, each merge a DPR1 eigenproblem
+ * solved by the accurate method (Sec. 1 names the arrowhead/DPR1 problem as
+ * the merge step of divide-and-conquer solvers).  T is torn at every
+ * off-diagonal (T = diag(T1', T2') + b_k v v^T, the tearing of Cuppen's
+ * method) down to 1x1 blocks; a level's merges
+ * diag(L1, L2) + b_k u u^T, u = [last row of Q1; first row of Q2], run as one
+ * batched DPR1 plan (either sign of b_k; b_k = 0 merges two sorted lists), and
+ * Q = diag(Q1, Q2) Qh as FP64 GEMMs (rocBLAS).
+ *   a: n diagonal entries, b: n-1 off-diagonal entries (device).
+ *   lambda: n eigenvalues, descending.  Q: n x n (ldq >= n), column k the
+ *   eigenvector of lambda_k (sign as produced by the merges).
+ *   info: optional, n words: the top merge's ARROW_INFO_* bits (a merge that
+ *   is reducible, e.g. exactly equal eigenvalues of two halves, is reported
+ *   there and its outputs are NaN).
+ * Synchronous: it reads b to the host to plan the tree, allocates its
+ * buffers (about 3 n^2 doubles) and waits for the handle's stream before
+ * returning.
+ */
+int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, double* lambda, double* Q,
+                int64_t ldq, uint32_t* info);
+
 /* ------------------------------------------------------------------------
  * Batched solves: many independent problems of uneven order in one plan.
  *

@@ -72,6 +72,7 @@ def lib():
                 L.arrow_workspace_size.restype = ctypes.c_size_t
                 L.arrow_eig.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
                 L.arrow_eig_herm.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
+                L.tridiag_eig.argtypes = [P, I64, P, P, P, P, I64, P]
                 L.dpr1_eig.argtypes = [P, I64, P, P, D, P, P, I64, P]
                 L.arrow_svd.argtypes = [P, I64, P, P, D, P, P, I64, P, I64, P]
                 L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
@@ -82,7 +83,7 @@ def lib():
                 L.arrow_probe_copy.argtypes = [P, P, I64, P]
                 for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
-                          "arrow_eig", "arrow_eig_herm", "dpr1_eig", "arrow_svd", "arrow_last_timing",
+                          "arrow_eig", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing",
                           "arrow_last_counters",
                           "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
@@ -239,6 +240,24 @@ def arrow_eig_herm(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: b
                                   _ptr(shift), _ptr(mu), _ptr(info))
     _check(rc, "arrow_eig_herm")
     return EigOut(lam, None if buf is None else buf.t(), None, shift, mu, info)
+
+
+def tridiag_eig(a: torch.Tensor, b: torch.Tensor) -> EigOut:
+    """Eigenpairs of the symmetric tridiagonal matrix with diagonal a (n) and off-diagonal b (n-1),
+    float64 CUDA tensors, by divide and conquer with DPR1 merges.  Synchronous."""
+    device = a.device
+    n = a.numel()
+    a = _dev_vec(a, n, device, "a")
+    b = _dev_vec(b, n - 1, device, "b") if n > 1 else torch.zeros(1, dtype=torch.float64, device=device)
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        lam = torch.empty(n, dtype=torch.float64, device=device)
+        buf = _colmajor(n, device)
+        info = torch.empty(n, dtype=torch.int32, device=device)
+        rc = lib().tridiag_eig(h, n, _ptr(a), _ptr(b), _ptr(lam), _ptr(buf), n, _ptr(info))
+    _check(rc, "tridiag_eig")
+    return EigOut(lam, buf.t(), None, None, None, info)
 
 
 def dpr1_eig(d: torch.Tensor, u: torch.Tensor, rho: float, *, vectors: bool = True) -> EigOut:

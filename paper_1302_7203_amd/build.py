@@ -21,6 +21,8 @@ FLAGS = [
     # the double-double transformations need every + and * rounded on its own
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # tridiag_eig's eigenvector updates are plain FP64 GEMMs
+    "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

@@ -397,6 +397,7 @@ int arrow_destroy(arrow_handle_t h) {
   if (!valid(h)) return ARROW_ERR_STATE;
   DeviceGuard g(h->device);
   (void)hipStreamSynchronize(h->stream);
+  tridiag_release(h);
   if (h->ws) (void)hipFree(h->ws);
   if (h->ev_made)
     for (int e = 0; e < 6; ++e) (void)hipEventDestroy(h->ev[e]);

@@ -29,6 +29,7 @@ struct arrow_handle_s {
   int ntab[2];
   int32_t tab_n[2][LANE_TABLE_MAX];
   int32_t tab_g[2][LANE_TABLE_MAX];
+  void* blas;         // rocBLAS handle of tridiag_eig's GEMMs, made on first use
   uint32_t magic;
 };
 
@@ -80,6 +81,9 @@ static inline int single_lanes(const arrow_handle_s* h, int64_t n) {
 
 // all launches of one single-problem solve (defined with the single-problem kernels)
 int launch_single(arrow_handle_t h, const ahd::ProbDesc& D);
+
+// frees what tridiag_eig keeps in the handle
+void tridiag_release(arrow_handle_t h);
 
 // lanes per eigenvalue for a problem of order n inside a batch
 static inline int batch_lanes(const arrow_handle_s* h, int64_t n) {
