@@ -258,9 +258,9 @@ def serving_leg(args, dev):
 def extensions_leg(args, binding, workloads, dev):
     """The solver's extensions at n = 4096, each timed like the main workload (inputs resident,
     HIP-event stage times): a Hermitian arrowhead (Sec. 6.1; complex vectors, 16 bytes per entry),
-    a reducible arrowhead deflated on the device (Sec. 1), and a DPR1 matrix with rho < 0.
-    Throughput and the vector phase's HBM rate only; their parity is checked by the GPU tests
-    on the same generators."""
+    a reducible arrowhead deflated on the device (Sec. 1), a DPR1 matrix with rho < 0, and the
+    divide-and-conquer tridiagonal solver built on the DPR1 merge.  Throughput (and the vector
+    phase's HBM rate) only; their parity is checked by the GPU tests on the same generators."""
     import numpy as np
     import torch
     rng = np.random.default_rng(workloads.SEED_BASE + 7)
@@ -302,6 +302,31 @@ def extensions_leg(args, binding, workloads, dev):
                      "vector_hbm_frac": entry_bytes * n * n / (st[4] * 1e-3) / PEAK_HBM,
                      "deflated": int(np.sum((info & 1024) != 0)),
                      "not_solved": int(np.sum((info & 304) != 0))}
+    # divide-and-conquer tridiagonal solve (synchronous: its allocations, the host
+    # planning of every tree level and the rocBLAS GEMMs are inside the time)
+    a = torch.from_numpy(rng.uniform(-1.0, 1.0, n)).to(dev)
+    b = torch.from_numpy(rng.uniform(-1.0, 1.0, n - 1)).to(dev)
+    res = binding.tridiag_eig(a, b)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        res = binding.tridiag_eig(a, b)
+    torch.cuda.synchronize(dev)
+    el = (time.perf_counter() - t0) / 3
+
+    def gemm_flops(lo, hi):   # Q = diag(Q1, Q2) Qh at every merge, 2 m n k each
+        if hi - lo < 2:
+            return 0.0
+        mid = lo + (hi - lo) // 2
+        s, sl, sr = hi - lo, mid - lo, hi - mid
+        return 2.0 * s * (sl * sl + sr * sr) + gemm_flops(lo, mid) + gemm_flops(mid, hi)
+    gf = gemm_flops(0, n)
+    info = res.info.cpu().numpy().astype(np.uint32)
+    out["tridiag_4096"] = {"workload": "symmetric tridiagonal, a, b ~ U(-1,1), divide and conquer with batched DPR1 "
+                                       "merges and FP64 GEMM updates", "n": n, "steps": 3,
+                           "value": n / el, "unit": "eigenpairs/s", "ms_per_step": el * 1e3,
+                           "gemm_flops": gf, "gemm_tflops_over_whole_solve": gf / el / 1e12,
+                           "deflated_at_top": int(np.sum((info & 1024) != 0))}
     return out
 
 

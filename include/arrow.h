@@ -172,9 +172,9 @@ int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
  *   info: optional, n words: the top merge's ARROW_INFO_* bits (a merge that
  *   is reducible, e.g. exactly equal eigenvalues of two halves, is reported
  *   there and its outputs are NaN).
- * Synchronous: it reads b to the host to plan the tree, allocates its
- * buffers (about 3 n^2 doubles) and waits for the handle's stream before
- * returning.
+ * Synchronous: it reads b to the host to plan the tree, keeps its device
+ * buffers (about 4 n^2 doubles) in the handle, grown on demand, and waits for
+ * the handle's stream before returning.
  */
 int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, double* lambda, double* Q,
                 int64_t ldq, uint32_t* info);
