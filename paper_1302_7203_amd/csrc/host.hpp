@@ -30,6 +30,8 @@ struct arrow_handle_s {
   int32_t tab_n[2][LANE_TABLE_MAX];
   int32_t tab_g[2][LANE_TABLE_MAX];
   void* blas;         // rocBLAS handle of tridiag_eig's GEMMs, made on first use
+  void* td_ws;        // tridiag_eig's device buffers (grown on demand, kept)
+  size_t td_cap;      // bytes
   uint32_t magic;
 };
 

@@ -48,8 +48,10 @@ struct Node {
 struct MergeDev {
   int lo, mid, hi;
   int nk;            // entries kept for the DPR1 solve (the others are deflated)
-  int64_t out;       // offset of the merge's eigenvalues in the output pool; Qh follows (ld hi-lo)
+  int big;           // its product goes to rocBLAS (else to k_td_update)
+  int64_t out;       // offset of the merge's eigenvalues in the output pool; Qh follows (s x nk, ld s)
   int64_t dout;      // offset of the DPR1 solve's eigenvalues in its pool; its vectors follow (ld nk)
+  int64_t cout;      // big merges: offset of diag(Q1, Q2) Qh (s x nk, ld s) in the scratch pool
 };
 
 int build(std::vector<Node>& nodes, const std::vector<double>& b, int lo, int hi) {
@@ -105,14 +107,17 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_gather_u(const MergeDev* mg, in
   }
 }
 
-// One merge's eigenvalues and Qh from the DPR1 solve of its kept entries
-// (map[lo .. lo+nk): their rows, in the order given to the solve) and its
-// deflated entries (map[lo+nk .. hi): their rows, by decreasing eigenvalue;
-// eigenpair (d_f, e_f)).  Both lists descend; they are merged with a solved
-// eigenvalue first on ties.  info: the solve's bits, or ARROW_INFO_DEFLATED.
+// One merge's eigenvalues, the column each eigenpair goes to, and Qh over
+// the solved ones.  The DPR1 solve had the kept entries (map[lo .. lo+nk):
+// their rows, ascending); the deflated ones (map[lo+nk .. hi): their rows, by
+// decreasing eigenvalue) keep (d_f, e_f).  Both lists descend and are merged
+// with a solved eigenvalue first on ties; pos[lo + j] is the column of source
+// j (the same numbering as map).  Qh (s x nk, ld s) holds the solved vectors
+// on the kept rows and zeros elsewhere.  info: the solve's bits, or
+// ARROW_INFO_DEFLATED.
 __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(const MergeDev* mg, const int* map, const double* lam,
                                                         const double* dpool, const uint32_t* dinfo, double* out,
-                                                        uint32_t* info) {
+                                                        uint32_t* info, int* pos) {
   const MergeDev m = mg[blockIdx.y];
   const int s = m.hi - m.lo, nk = m.nk, nf = s - nk;
   const int* kept = map + m.lo;
@@ -122,28 +127,64 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(const MergeDev* mg, cons
   double* lo_out = out + m.out;
   double* qh = lo_out + s;
   for (int c = (int)(blockIdx.x * TD_BLOCK + threadIdx.x); c < s; c += (int)gridDim.x * TD_BLOCK) {
-    int pos;
     if (c < nk) {
       const double v = dl[c];
       int lo = 0, hi = nf;                 // deflated values > v
       while (lo < hi) { const int md = (lo + hi) >> 1; if (lam[m.lo + defl[md]] > v) lo = md + 1; else hi = md; }
-      pos = c + lo;
-      lo_out[pos] = v;
-      double* col = qh + (size_t)pos * s;
+      lo_out[c + lo] = v;
+      pos[m.lo + c] = c + lo;
+      info[m.lo + c + lo] = dinfo[m.lo + c];
+      double* col = qh + (size_t)c * s;
       for (int r = 0; r < s; ++r) col[r] = 0.0;
       for (int r = 0; r < nk; ++r) col[kept[r]] = dq[(size_t)c * nk + r];
-      info[m.lo + pos] = dinfo[m.lo + c];
     } else {
       const int f = c - nk;
       const double v = lam[m.lo + defl[f]];
       int lo = 0, hi = nk;                 // solved values >= v
       while (lo < hi) { const int md = (lo + hi) >> 1; if (dl[md] >= v) lo = md + 1; else hi = md; }
-      pos = f + lo;
-      lo_out[pos] = v;
-      double* col = qh + (size_t)pos * s;
-      for (int r = 0; r < s; ++r) col[r] = (r == defl[f]) ? 1.0 : 0.0;
-      info[m.lo + pos] = ARROW_INFO_DEFLATED;
+      lo_out[f + lo] = v;
+      pos[m.lo + c] = f + lo;
+      info[m.lo + f + lo] = ARROW_INFO_DEFLATED;
     }
+  }
+}
+
+// The merged block's columns in the output buffer: a deflated pair's vector
+// is column f of diag(Q1, Q2); a solved one is diag(Q1, Q2) times its Qh
+// column, summed here over the kept rows (small merges) or scattered from the
+// rocBLAS product (k_td_scatter, big merges).
+__global__ __launch_bounds__(TD_BLOCK) void k_td_update(const MergeDev* mg, const int* map, const int* pos,
+                                                        const double* out, int n, const double* Qold, double* Qnew) {
+  const MergeDev m = mg[blockIdx.y];
+  const int s = m.hi - m.lo, sl = m.mid - m.lo, nk = m.nk;
+  const int* kept = map + m.lo;
+  const double* qh = out + m.out + s;
+  for (int64_t e = (int64_t)blockIdx.x * TD_BLOCK + threadIdx.x; e < (int64_t)s * s; e += (int64_t)gridDim.x * TD_BLOCK) {
+    const int j = (int)(e / s), i = (int)(e - (int64_t)j * s);   // source j, row i
+    if (j < nk && m.big) continue;
+    double v = 0.0;
+    if (j < nk) {
+      const bool top = i < sl;
+      for (int r = 0; r < nk; ++r) {
+        const int kr = kept[r];
+        if ((kr < sl) == top) v = fma(Qold[(size_t)(m.lo + kr) * n + (m.lo + i)], qh[(size_t)j * s + kr], v);
+      }
+    } else {
+      const int d = kept[j];                                    // deflated row (map continues past nk)
+      if ((i < sl) == (d < sl)) v = Qold[(size_t)(m.lo + d) * n + (m.lo + i)];
+    }
+    Qnew[(size_t)(m.lo + pos[m.lo + j]) * n + (m.lo + i)] = v;
+  }
+}
+
+__global__ __launch_bounds__(TD_BLOCK) void k_td_scatter(const MergeDev* mg, const int* pos, const double* C, int n,
+                                                         double* Qnew) {
+  const MergeDev m = mg[blockIdx.y];
+  if (!m.big) return;
+  const int s = m.hi - m.lo, nk = m.nk;
+  for (int64_t e = (int64_t)blockIdx.x * TD_BLOCK + threadIdx.x; e < (int64_t)s * nk; e += (int64_t)gridDim.x * TD_BLOCK) {
+    const int c = (int)(e / s), i = (int)(e - (int64_t)c * s);
+    Qnew[(size_t)(m.lo + pos[m.lo + c]) * n + (m.lo + i)] = C[m.cout + e];
   }
 }
 
@@ -176,6 +217,11 @@ void tridiag_release(arrow_handle_t h) {
     (void)rocblas_destroy_handle((rocblas_handle)h->blas);
     h->blas = nullptr;
   }
+  if (h->td_ws) {
+    (void)hipFree(h->td_ws);
+    h->td_ws = nullptr;
+    h->td_cap = 0;
+  }
 }
 
 extern "C" {
@@ -206,17 +252,46 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
   const int H = nodes[(size_t)root].height;
 
   // device memory: eigenvalues and u, the compacted DPR1 inputs, two Q
-  // buffers, the merges' output pool, the DPR1 solves' pool, info words, the
-  // row maps, merge records and GEMM pointer arrays
+  // buffers, the merges' output pool, the DPR1 solves' pool (then the GEMM
+  // scratch), info words, the row and column maps and the merge records
   const size_t nn = (size_t)n * (size_t)n;
-  DevBuf lamu, cpool, qbuf, outp, dpool, infop, infod, mapb, recs, ptrs;
+  // one buffer, kept in the handle, holds them all (256-byte aligned parts)
+  struct Part {
+    void** p;
+    size_t bytes;
+  };
+  void *p_lamu, *p_cpool, *p_qbuf, *p_outp, *p_dpool, *p_infop, *p_infod, *p_map, *p_pos, *p_recs;
+  const Part parts[] = {{&p_lamu, 2 * (size_t)n * sizeof(double)},  {&p_cpool, 2 * (size_t)n * sizeof(double)},
+                        {&p_qbuf, 2 * nn * sizeof(double)},          {&p_outp, ((size_t)n + nn) * sizeof(double)},
+                        {&p_dpool, ((size_t)n + nn) * sizeof(double)}, {&p_infop, (size_t)n * sizeof(uint32_t)},
+                        {&p_infod, (size_t)n * sizeof(uint32_t)},    {&p_map, (size_t)n * sizeof(int)},
+                        {&p_pos, (size_t)n * sizeof(int)},           {&p_recs, (size_t)n * sizeof(MergeDev) + 16}};
+  size_t total = 0;
+  for (const Part& q : parts) total += (q.bytes + 255) / 256 * 256;
+  if (total > h->td_cap) {
+    if (h->td_ws) (void)hipFree(h->td_ws);
+    h->td_ws = nullptr;
+    h->td_cap = 0;
+    if (hipMalloc(&h->td_ws, total) != hipSuccess) {
+      h->td_ws = nullptr;
+      return ARROW_ERR_NOMEM;
+    }
+    h->td_cap = total;
+  }
+  {
+    char* at = (char*)h->td_ws;
+    for (const Part& q : parts) {
+      *q.p = at;
+      at += (q.bytes + 255) / 256 * 256;
+    }
+  }
+  struct View {
+    void* p;
+  } lamu{p_lamu}, cpool{p_cpool}, qbuf{p_qbuf}, outp{p_outp}, dpool{p_dpool}, infop{p_infop}, infod{p_infod},
+      mapb{p_map}, posb{p_pos}, recs{p_recs};
+  DevBuf bws;
+  size_t bws_bytes = 0;
   int rc;
-  if ((rc = lamu.alloc(2 * (size_t)n * sizeof(double))) || (rc = cpool.alloc(2 * (size_t)n * sizeof(double))) ||
-      (rc = qbuf.alloc(2 * nn * sizeof(double))) || (rc = outp.alloc(((size_t)n + nn) * sizeof(double))) ||
-      (rc = dpool.alloc(((size_t)n + nn) * sizeof(double))) || (rc = infop.alloc((size_t)n * sizeof(uint32_t))) ||
-      (rc = infod.alloc((size_t)n * sizeof(uint32_t))) || (rc = mapb.alloc((size_t)n * sizeof(int))) ||
-      (rc = recs.alloc((size_t)n * sizeof(MergeDev) + 16)) || (rc = ptrs.alloc(6 * (size_t)n * sizeof(double*) + 16)))
-    return rc;
   double* lam = (double*)lamu.p;
   double* u = lam + n;
   double* qb[2] = {(double*)qbuf.p, (double*)qbuf.p + nn};
@@ -257,9 +332,10 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
     // the merges of this level; u of every one, then eigenvalues and u to the host
     all.clear();
     for (const Node& p : nodes)
-      if (p.height == lev && p.left >= 0) all.push_back(MergeDev{p.lo, p.mid, p.hi, 0, 0, 0});
+      if (p.height == lev && p.left >= 0) all.push_back(MergeDev{p.lo, p.mid, p.hi, 0, 0, 0, 0, 0});
     MergeDev* drec = (MergeDev*)recs.p;
-    const int64_t widest = (int64_t)n;   // grid-stride loops cover any block
+    int64_t widest = 1;   // the largest merge of the level sizes the grids (they stride over the rest)
+    for (const MergeDev& m : all) widest = std::max<int64_t>(widest, m.hi - m.lo);
     if (hipMemcpyAsync(drec, all.data(), all.size() * sizeof(MergeDev), hipMemcpyHostToDevice, st) != hipSuccess)
       return ARROW_ERR_HIP;
     hipLaunchKernelGGL(k_td_gather_u, dim3(grid_x(widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec, (int)n,
@@ -272,7 +348,7 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
     // sqrt2 -- a perturbation of T of that size; it leaves (d_j, e_j).  The
     // rest is solved as a DPR1 problem; beta = 0 drops every entry.
     descs.clear();
-    int64_t off = 0, doff = 0;
+    int64_t off = 0, doff = 0, coff = 0;
     size_t mi = 0;
     for (const Node& p : nodes) {
       if (p.height != lev || p.left < 0) continue;
@@ -302,7 +378,11 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
       m.nk = nk;
       m.out = off;
       m.dout = doff;
-      off += (int64_t)s + (int64_t)s * s;
+      // products of more than 2^22 multiply-adds go to rocBLAS
+      m.big = (int64_t)s * nk * (s / 2) > ((int64_t)1 << 22);
+      m.cout = coff;
+      if (m.big) coff += (int64_t)s * nk;
+      off += (int64_t)s + (int64_t)s * nk;
       if (nk > 0) {
         arrow_desc_t d{};
         d.kind = ARROW_KIND_DPR1;
@@ -323,9 +403,19 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
         hipMemcpyAsync(cpool.p, hc.data(), 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
       return ARROW_ERR_HIP;
     if (!descs.empty()) {
+      // the plan's device block comes from one buffer, grown when a level needs more
+      const size_t need = arrow_batch_workspace_size((int64_t)descs.size(), descs.data());
+      if (need > bws_bytes) {
+        (void)hipStreamSynchronize(st);
+        if (bws.p) (void)hipFree(bws.p);
+        bws.p = nullptr;
+        bws_bytes = 0;
+        if ((rc = bws.alloc(need))) return rc;
+        bws_bytes = need;
+      }
       arrow_batch_t plan = nullptr;
       rc = arrow_batch_create(h, (int64_t)descs.size(), descs.data(), (double*)cpool.p, (double*)dpool.p,
-                              (uint32_t*)infod.p, nullptr, 0, 0, &plan);
+                              (uint32_t*)infod.p, bws.p, bws_bytes, 0, &plan);
       if (rc != ARROW_OK) return rc > 0 ? rc : ARROW_ERR_STATE;
       rc = arrow_batch_run(plan);
       const int rc2 = arrow_batch_destroy(plan);   // synchronises the stream: the host arrays may be reused
@@ -334,46 +424,32 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
     }
     hipLaunchKernelGGL(k_td_expand, dim3(grid_x(widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec,
                        (const int*)mapb.p, lam, (const double*)dpool.p, (const uint32_t*)infod.p, (double*)outp.p,
-                       (uint32_t*)infop.p);
+                       (uint32_t*)infop.p, (int*)posb.p);
     hipLaunchKernelGGL(k_td_put_lam, dim3(grid_x(widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec,
                        (const double*)outp.p, lam);
-    // Q of each merge = diag(Q1, Q2) Qh: the top rows from Q1, the bottom rows
-    // from Q2; merges of equal shape go to one batched call
-    std::vector<const MergeDev*> order;
-    for (const MergeDev& m : all) order.push_back(&m);
-    std::sort(order.begin(), order.end(), [](const MergeDev* x, const MergeDev* y) {
-      const int ax = x->mid - x->lo, bx = x->hi - x->mid, ay = y->mid - y->lo, by = y->hi - y->mid;
-      return ax != ay ? ax < ay : bx < by;
-    });
+    // big merges: diag(Q1, Q2) Qh by rocBLAS into the scratch pool (the DPR1
+    // pool, read by k_td_expand before), Q1 against Qh's top rows, Q2 against
+    // its bottom rows
     const double one = 1.0, zero = 0.0;
-    double** dptr = (double**)ptrs.p;
-    std::vector<double*> hp;
-    for (size_t g0 = 0; g0 < order.size();) {
-      size_t g1 = g0 + 1;
-      const int sl = order[g0]->mid - order[g0]->lo, sr = order[g0]->hi - order[g0]->mid;
-      while (g1 < order.size() && order[g1]->mid - order[g1]->lo == sl && order[g1]->hi - order[g1]->mid == sr) ++g1;
-      const int cnt = (int)(g1 - g0), s = sl + sr;
-      hp.assign((size_t)6 * cnt, nullptr);
-      for (int q = 0; q < cnt; ++q) {
-        const MergeDev& m = *order[g0 + q];
-        double* qh = (double*)outp.p + m.out + s;
-        hp[(size_t)q] = qb[in] + (size_t)m.lo * n + m.lo;                    // Q1
-        hp[(size_t)cnt + q] = qh;                                            // Qh rows [0, sl)
-        hp[(size_t)2 * cnt + q] = qb[outb] + (size_t)m.lo * n + m.lo;        // rows [lo, mid) of the result
-        hp[(size_t)3 * cnt + q] = qb[in] + (size_t)m.mid * n + m.mid;        // Q2
-        hp[(size_t)4 * cnt + q] = qh + sl;                                   // Qh rows [sl, s)
-        hp[(size_t)5 * cnt + q] = qb[outb] + (size_t)m.lo * n + m.mid;       // rows [mid, hi)
-      }
-      if (hipMemcpyAsync(dptr, hp.data(), hp.size() * sizeof(double*), hipMemcpyHostToDevice, st) != hipSuccess)
+    double* scratch = (double*)dpool.p;
+    for (const MergeDev& m : all) {
+      if (!m.big) continue;
+      const int s = m.hi - m.lo, sl = m.mid - m.lo, sr = m.hi - m.mid;
+      const double* qh = (const double*)outp.p + m.out + s;
+      if (rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, sl, m.nk, sl, &one,
+                        qb[in] + (size_t)m.lo * n + m.lo, (int)n, qh, s, &zero, scratch + m.cout, s) !=
+              rocblas_status_success ||
+          rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, sr, m.nk, sr, &one,
+                        qb[in] + (size_t)m.mid * n + m.mid, (int)n, qh + sl, s, &zero, scratch + m.cout + sl, s) !=
+              rocblas_status_success)
         return ARROW_ERR_HIP;
-      if (rocblas_dgemm_batched(bh, rocblas_operation_none, rocblas_operation_none, sl, s, sl, &one, dptr, (int)n,
-                                dptr + cnt, s, &zero, dptr + 2 * cnt, (int)n, cnt) != rocblas_status_success ||
-          rocblas_dgemm_batched(bh, rocblas_operation_none, rocblas_operation_none, sr, s, sr, &one, dptr + 3 * cnt,
-                                (int)n, dptr + 4 * cnt, s, &zero, dptr + 5 * cnt, (int)n, cnt) != rocblas_status_success)
-        return ARROW_ERR_HIP;
-      if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // the pointer array is reused
-      g0 = g1;
     }
+    hipLaunchKernelGGL(k_td_update, dim3(grid_x(widest * widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec,
+                       (const int*)mapb.p, (const int*)posb.p, (const double*)outp.p, (int)n, (const double*)qb[in],
+                       qb[outb]);
+    hipLaunchKernelGGL(k_td_scatter, dim3(grid_x(widest * widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec,
+                       (const int*)posb.p, (const double*)scratch, (int)n, qb[outb]);
+    if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // host arrays are refilled next level
   }
   // results: eigenvalues (descending) and the root's block
   const int fin = H & 1;
@@ -388,7 +464,7 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
       return ARROW_ERR_HIP;
     }
   }
-  if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // before the buffers are freed
+  if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // results complete; the buffers are reused
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
 
