@@ -176,3 +176,21 @@ def test_other_kinds_reducible_reported(oracle_lib):
     assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))
     r = emu.solve(2, np.array([1.0, 0.7, 0.5]), np.array([1.0, 0.0, 3.0]), 0.5)
     assert np.all(r["info"] & 16) and np.all(np.isnan(r["lam"]))
+
+
+@pytest.mark.parametrize("k", [-100, 20, 100])
+def test_power_of_two_scaling_is_exact(k, oracle_lib):
+    """Scaling every input by 2^k scales every eigenvalue (singular value) by 2^k and leaves
+    the vectors unchanged, bit for bit: no step of the method uses an absolute threshold.
+    (k stays where no intermediate square or product leaves the normal range; at 2^-300 the
+    graded and SVD cases reach subnormals.)"""
+    s = 2.0 ** k
+    rng = np.random.default_rng(60)
+    cases = [(0, W.graded_arrow(300, rng, clusters=4, cluster_size=8)), (1, W.dpr1(200, rng)),
+             (2, W.svd_arrow(150, rng))]
+    for kind, pr in cases:
+        a = emu.solve(kind, pr.d, pr.z, pr.scalar)
+        zs = pr.z if kind == 1 else pr.z * s          # DPR1: D and rho scale, u does not
+        b = emu.solve(kind, pr.d * s, zs, pr.scalar * s)
+        assert np.array_equal(b["lam"], a["lam"] * s), kind
+        assert np.array_equal(b["V"], a["V"]), kind

@@ -408,3 +408,29 @@ def test_unsorted_large_input_matches_sorted(gpu):
     perm = sh.meta["perm"]
     Vb, Vo = _np(base.V), _np(out.V)
     assert np.array_equal(Vo[:-1], Vb[perm]) and np.array_equal(Vo[-1], Vb[-1])
+
+
+@pytest.mark.parametrize("k", [-100, 20, 100])
+def test_power_of_two_scaling_is_exact(gpu, k):
+    """2^k times every input: eigenvalues (singular values) times 2^k and the same vectors,
+    bit for bit, for every kind (no absolute threshold anywhere)."""
+    torch, binding, dev = gpu
+    s = 2.0 ** k
+    rng = np.random.default_rng(61)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)   # noqa: E731
+    pr = W.graded_arrow(1000, rng, clusters=8, cluster_size=8)
+    a, b = _arrow(gpu, pr.d, pr.z, pr.scalar), _arrow(gpu, pr.d * s, pr.z * s, pr.scalar * s)
+    assert np.array_equal(_np(b.lam), _np(a.lam) * s) and np.array_equal(_np(b.V), _np(a.V))
+    pr = W.dpr1(700, rng)
+    a, b = binding.dpr1_eig(t(pr.d), t(pr.z), pr.scalar), binding.dpr1_eig(t(pr.d * s), t(pr.z), pr.scalar * s)
+    torch.cuda.synchronize(dev)
+    assert np.array_equal(_np(b.lam), _np(a.lam) * s) and np.array_equal(_np(b.V), _np(a.V))
+    pr = W.svd_arrow(500, rng)
+    a = binding.arrow_svd(t(pr.d), t(pr.z), pr.scalar)
+    b = binding.arrow_svd(t(pr.d * s), t(pr.z * s), pr.scalar * s)
+    torch.cuda.synchronize(dev)
+    assert np.array_equal(_np(b.lam), _np(a.lam) * s)
+    assert np.array_equal(_np(b.V), _np(a.V)) and np.array_equal(_np(b.U), _np(a.U))
+    d, z, al = _herm_case(600, 62)
+    a, b = _herm(gpu, d, z, al), _herm(gpu, d * s, z * s, al * s)
+    assert np.array_equal(_np(b.lam), _np(a.lam) * s) and np.array_equal(_np(b.V), _np(a.V))
