@@ -485,6 +485,78 @@ __host__ __device__ inline double rational_next(double x, double h, double hnois
   return (lo > 0.0 && hi > 16.0 * lo) ? bits_mid(lo, hi) : 0.5 * (lo + hi);
 }
 
+// Lower bound on the zero from the model that keeps the nearest pole exact
+// and replaces the rest of psi_x by its tangent at x:
+//   c0 - t + ry/(t - y) + rest(x) + rest'(x) (t - x),  rest = psi_x - ry/(x - y).
+// Every other pole lies left of y with a positive residue, so the rest is
+// convex right of y, its tangent lies below it and the model's zero lies left
+// of the true one.  In u = t - y the model is beta - gamma u + ry/u with
+//   beta = h + u_x (1 - psi_x') - 2 ry/u_x,  gamma = 1 - psi_x' - ry/u_x^2 >= 1,
+// whose positive zero is taken in the form that avoids cancellation.  NaN or
+// a value outside the bracket (overflow, rounding) is ignored by the caller.
+__host__ __device__ inline double tangent_rest_bound(double x, double h, double dpsi_x, double y, double ry) {
+  const double ux = x - y;
+  const double rux = ry / ux;
+  const double beta = h + ux * (1.0 - dpsi_x) - 2.0 * rux;
+  const double gamma = fmax(1.0 - dpsi_x - rux / ux, 1.0);
+  const double disc = sqrt(beta * beta + 4.0 * gamma * ry);
+  const double u = (beta >= 0.0) ? (beta + disc) / (2.0 * gamma) : 2.0 * ry / (disc - beta);
+  return y + u;
+}
+
+// The step of rational_inverse, which also knows the residue ry of psi_x at
+// its nearest pole y.  Two closed-form models bound the zero before rounding:
+// the nearest-pole fit A/(t - y) + B lies above psi_x everywhere right of y
+// (for each pole p < y the difference times (t - y)(t - p) is a quadratic
+// with a double zero at x and a positive leading coefficient), so its zero is
+// an upper bound; tangent_rest_bound gives a lower one.  The tightest bounds
+// met so far, [slo, shi] inside the bracket kept from the signs of h, confine
+// the step: the second-order candidate clipped into them, or else a split of
+// them -- the bit-pattern midpoint across decades, the geometric mean across
+// more than a factor 2, the arithmetic mean otherwise.  Far from the zero the
+// nearest-pole candidate alone advances by a nearly constant factor when the
+// mass of psi_x sits on poles far left of y; the lower bound is what lets the
+// split close in from both sides.  The stopping rules are rational_next's.
+__host__ __device__ inline double bounded_next(double x, double h, double hnoise, double psi_x, double dpsi_x,
+                                               double d2psi_x, double y, double ry, double c0, double lo,
+                                               double hi, int it, int hi_open, double& slo, double& shi,
+                                               int* done) {
+  *done = 0;
+  if ((hi - lo) <= 4.0 * EPS * fabs(x)) { *done = 1; return x; }
+  if (it < RATIONAL_TO_BISECT) {
+    double cand = NAN;
+    if (d2psi_x > 0) {
+      const double pe = x + 2.0 * dpsi_x / d2psi_x;
+      if (pe <= y && pe < x) cand = rational_candidate(x, psi_x, dpsi_x, pe, c0, 1);
+    }
+    const double up = rational_candidate(x, psi_x, dpsi_x, y, c0, 1);
+    const bool second = cand > lo && cand < hi;
+    if (!second) cand = up;
+    if (cand == cand && (fabs(cand - x) <= 2.0 * EPS * fabs(cand) || fabs(h) <= hnoise)) {
+      *done = 1;
+      return (cand > lo && cand < hi) ? cand : x;
+    }
+    if (hi_open && cand >= hi) return hi;
+    slo = fmax(slo, lo);
+    shi = fmin(shi, hi);
+    if (!(slo < shi)) { slo = lo; shi = hi; }
+    const double down = tangent_rest_bound(x, h, dpsi_x, y, ry);
+    // the models agree when the lower bound meets the upper one to within the
+    // zero's uncertainty from the rounding of h; then slo == shi
+    const double tol = hnoise / (1.0 - dpsi_x);
+    if (up > slo && up < shi) shi = up;
+    if (down > slo && down < shi + tol) slo = fmin(down, shi);
+    double xn;
+    if (cand > slo && cand < shi) xn = cand;
+    else if (slo > 0.0 && shi > 16.0 * slo) xn = bits_mid(slo, shi);
+    else if (second) xn = fmin(fmax(cand, slo), shi);
+    else xn = (slo > 0.0 && shi > 2.0 * slo) ? sqrt(slo * shi) : 0.5 * (slo + shi);
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (slo + shi);
+    if (xn > lo && xn < hi) return xn;
+  }
+  return (lo > 0.0 && hi > 16.0 * lo) ? bits_mid(lo, hi) : 0.5 * (lo + hi);
+}
+
 // extreme eigenvalue of A_i^{-1} on the given side, by the rational iteration
 template <int KIND, int G>
 __host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
@@ -518,8 +590,15 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
   // inside the bracket is the better start
   const double x_est = sg * nu_est;
   if (x_est > xlo && x_est < xhi) x = x_est;
+  // residue of psi_x at y: c_jn / (zeta_i^2 e_jn^2) for the neighbouring pole
+  // jn, or 1/zeta_i^2 for the pole at 0 when no pole lies right of it
+  double ry = rci;
+  if (y > 0.0) {
+    const double e = pdiff<KIND>(P.ds[i - side], di);
+    ry = P.ch[i - side] * rci / (e * e);
+  }
+  double slo = xlo, shi = xhi;
   int it = 0;
-  double prev_step = INFINITY;
   for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
     if (x >= xhi) hi_open = 0;
     const double nu = sg * x;
@@ -535,10 +614,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     if (h == 0) break;
     const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi_x));
     int done = 0;
-    const double xn =
-        rational_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, c0, 1, xlo, xhi, it, prev_step, hi_open, &done);
-    prev_step = fabs(xn - x);
-    x = xn;
+    x = bounded_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, ry, c0, xlo, xhi, it, hi_open, slo, shi, &done);
     if (done) { ++it; break; }
   }
   if (iters) *iters = it;
