@@ -275,8 +275,18 @@ int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const in
  *   for input already in decreasing order also the copy and the shaft weights
  *   and corner), sort (input not in that order: rank sort, copy, weights and
  *   corner), root (shift, b, root of the inverse), check (K_nu, repairs, norm)
- *   and vectors.  Needs ARROW_OPT_TIMING set before that call; waits for it to
- *   finish.  Returns ARROW_ERR_STATE when no timed call exists.
+ *   and vectors.  The events are stamped by the kernels' own dispatches (no
+ *   marker packets between launches): root and vectors are their kernels'
+ *   durations, front and sort run from one kernel's start to the next one's,
+ *   check from the end of the root kernel to the start of the vector kernel,
+ *   so the five sum to the whole call.  Needs ARROW_OPT_TIMING set before that
+ *   call; waits for it to finish.  Returns ARROW_ERR_STATE when no timed call
+ *   exists.
+ * arrow_timing_of: the same for the most recent timed call (age 0) or the one
+ *   before it (age 1): the handle keeps the stage events of two timed calls, so
+ *   a caller can read a call's stages after queuing the next one without
+ *   draining the stream.  -3 for another age; ARROW_ERR_STATE when fewer than
+ *   age + 1 timed calls were made.
  * arrow_last_counters: out[0..6] receive, summed over all eigenvalues, the
  *   bisection steps, double-double O(n) passes and plain O(n) passes executed
  *   by the root stage (out[0..2]) and by the check stage (out[3..5]), and the
@@ -284,6 +294,7 @@ int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const in
  *   Synchronises the stream and copies 24 n bytes to the host.
  */
 int arrow_last_timing(arrow_handle_t h, double* ms);
+int arrow_timing_of(arrow_handle_t h, int age, double* ms);
 int arrow_last_counters(arrow_handle_t h, int64_t* out);
 
 /*

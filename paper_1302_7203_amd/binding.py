@@ -76,6 +76,7 @@ def lib():
                 L.dpr1_eig.argtypes = [P, I64, P, P, D, P, P, I64, P]
                 L.arrow_svd.argtypes = [P, I64, P, P, D, P, P, I64, P, I64, P]
                 L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+                L.arrow_timing_of.argtypes = [P, I, ctypes.POINTER(ctypes.c_double)]
                 L.arrow_last_counters.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
                 L.arrow_set_lanes_table.argtypes = [P, I, ctypes.c_int32, P, P]
                 L.arrow_probe_fma.argtypes = [P, I64, I, P]
@@ -84,7 +85,7 @@ def lib():
                 for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
                           "arrow_eig", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing",
-                          "arrow_last_counters",
+                          "arrow_timing_of", "arrow_last_counters",
                           "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
                 _lib = L
@@ -153,6 +154,13 @@ def last_timing(device=None) -> list[float]:
     """Stage times (ms) of the last timed call: front, sort, root, check, vectors."""
     ms = (ctypes.c_double * 5)()
     _check(lib().arrow_last_timing(handle(device), ms), "arrow_last_timing")
+    return list(ms)
+
+
+def timing_of(age: int, device=None) -> list[float]:
+    """Stage times (ms) of the most recent timed call (age 0) or the one before it (age 1)."""
+    ms = (ctypes.c_double * 5)()
+    _check(lib().arrow_timing_of(handle(device), int(age), ms), "arrow_timing_of")
     return list(ms)
 
 

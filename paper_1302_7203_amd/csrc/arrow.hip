@@ -16,6 +16,7 @@
 // k_root / k_check give G lanes of a wavefront to each eigenvalue (G = 64: one
 // wavefront per eigenvalue); k_vec is bound by the n^2 FP64 stores.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -246,29 +247,41 @@ __global__ __launch_bounds__(BLOCK) void k_vec_c(ProbDesc D, int row_tiles, int 
 // ---------------------------------------------------------------------------
 // host side
 
+// A launch whose timing events, when given, are stamped by the dispatch itself
+// at the kernel's start and end: no marker packets between the launches, which
+// would add a dispatch gap of their own at every stage boundary.
+template <typename F, typename... A>
+static void launch_timed(F kern, dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                         A... args) {
+  if (e0 || e1) hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)lds, st, e0, e1, 0u, args...);
+  else hipLaunchKernelGGL(kern, grid, block, lds, st, args...);
+}
+
 template <int KIND, int G>
-static void launch_rc(const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds) {
+static void launch_rc(const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds,
+                      hipEvent_t e0, hipEvent_t e1) {
   const int64_t threads = (int64_t)D.n * G;
   const dim3 grid((unsigned)((threads + ROOT_BLOCK - 1) / ROOT_BLOCK));
   if (lds > 0) {
-    if (!check) hipLaunchKernelGGL((k_root<KIND, G, true>), grid, dim3(ROOT_BLOCK), lds, st, D, opt);
-    else hipLaunchKernelGGL((k_check<KIND, G, true>), grid, dim3(ROOT_BLOCK), lds, st, D, opt);
+    if (!check) launch_timed(k_root<KIND, G, true>, grid, dim3(ROOT_BLOCK), lds, st, e0, e1, D, opt);
+    else launch_timed(k_check<KIND, G, true>, grid, dim3(ROOT_BLOCK), lds, st, e0, e1, D, opt);
   } else {
-    if (!check) hipLaunchKernelGGL((k_root<KIND, G, false>), grid, dim3(ROOT_BLOCK), 0, st, D, opt);
-    else hipLaunchKernelGGL((k_check<KIND, G, false>), grid, dim3(ROOT_BLOCK), 0, st, D, opt);
+    if (!check) launch_timed(k_root<KIND, G, false>, grid, dim3(ROOT_BLOCK), 0, st, e0, e1, D, opt);
+    else launch_timed(k_check<KIND, G, false>, grid, dim3(ROOT_BLOCK), 0, st, e0, e1, D, opt);
   }
 }
 
 template <int KIND>
-static void launch_rc_any(int G, const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds) {
+static void launch_rc_any(int G, const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   switch (G) {
-    case 1: launch_rc<KIND, 1>(D, opt, st, check, lds); break;
-    case 2: launch_rc<KIND, 2>(D, opt, st, check, lds); break;
-    case 4: launch_rc<KIND, 4>(D, opt, st, check, lds); break;
-    case 8: launch_rc<KIND, 8>(D, opt, st, check, lds); break;
-    case 16: launch_rc<KIND, 16>(D, opt, st, check, lds); break;
-    case 32: launch_rc<KIND, 32>(D, opt, st, check, lds); break;
-    default: launch_rc<KIND, 64>(D, opt, st, check, lds); break;
+    case 1: launch_rc<KIND, 1>(D, opt, st, check, lds, e0, e1); break;
+    case 2: launch_rc<KIND, 2>(D, opt, st, check, lds, e0, e1); break;
+    case 4: launch_rc<KIND, 4>(D, opt, st, check, lds, e0, e1); break;
+    case 8: launch_rc<KIND, 8>(D, opt, st, check, lds, e0, e1); break;
+    case 16: launch_rc<KIND, 16>(D, opt, st, check, lds, e0, e1); break;
+    case 32: launch_rc<KIND, 32>(D, opt, st, check, lds, e0, e1); break;
+    default: launch_rc<KIND, 64>(D, opt, st, check, lds, e0, e1); break;
   }
 }
 
@@ -294,13 +307,17 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   hipStream_t st = h->stream;
   (void)hipGetLastError();
   const bool tm = h->timing && h->ev_made;
+  // a timed call takes the event set the previous timed call did not use
+  const int es = (tm && h->timed_calls > 0) ? 1 - h->ev_set : 0;
+  hipEvent_t* ev = h->ev[es];
   auto mark = [&](int e) {
-    if (tm) (void)hipEventRecord(h->ev[e], st);
+    if (tm) (void)hipEventRecord(ev[e], st);
   };
+  auto at = [&](int e) -> hipEvent_t { return tm ? ev[e] : nullptr; };
   const int ms = sorted_count(D);
-  mark(0);
-  hipLaunchKernelGGL(k_front<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, D);
-  mark(1);
+  // every stage boundary is the start (or end) of a kernel
+  launch_timed(k_front<KIND>, dim3(1), dim3(FRONT_BLOCK), 0, st, at(0), nullptr, D);
+  if (ms == 0) mark(1);
   if (ms > 0) {
     // about SORT_GRID blocks in all (they return at once when k_front found the
     // order), each comparing its key tile against one or more chunks
@@ -308,15 +325,15 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
     const int64_t jt = (ms + SORT_BLOCK - 1) / SORT_BLOCK;
     const int64_t nchunks = (ms + SORT_CHUNK - 1) / SORT_CHUNK;
     const int64_t lc = std::max<int64_t>(1, std::min<int64_t>({nchunks, SORT_GRID / jt, 65535}));
-    hipLaunchKernelGGL(k_sort<KIND>, dim3((unsigned)jt, (unsigned)lc), dim3(SORT_BLOCK), 0, st, D, SORT_CHUNK,
-                       (int)nchunks);
+    launch_timed(k_sort<KIND>, dim3((unsigned)jt, (unsigned)lc), dim3(SORT_BLOCK), 0, st, at(1), nullptr, D,
+                 SORT_CHUNK, (int)nchunks);
   }
-  mark(2);
+  // the root and vector stages are timed by their kernels' own start and end;
+  // the stages between take up the dispatch gaps
   const int G = single_lanes(h, D.n);
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
   const size_t lds = (hot <= h->lds_max) ? hot : 0;
-  launch_rc_any<SK>(G, D, h->opt, st, false, lds);
-  mark(3);
+  launch_rc_any<SK>(G, D, h->opt, st, false, lds, at(2), at(3));
   launch_rc_any<SK>(G, D, h->opt, st, true, lds);
   {
     // deferred repairs; the block reductions add a little static LDS
@@ -326,15 +343,16 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
     if (lds_r > 0) hipLaunchKernelGGL((k_repair<SK, true, GR>), grid, dim3(REPAIR_BLOCK), lds_r, st, D, h->opt);
     else hipLaunchKernelGGL((k_repair<SK, false, GR>), grid, dim3(REPAIR_BLOCK), 0, st, D, h->opt);
   }
-  mark(4);
+  hipEvent_t v0 = D.V ? at(4) : nullptr, v1 = D.V ? at(5) : nullptr;
+  if (!v0) mark(4);
   if (KIND == KIND_HERM && D.V) {
     const VecShape sh = vec_shape(D.n);
     const int row_tiles = (int)((D.n + (int64_t)BLOCK * sh.rpt - 1) / ((int64_t)BLOCK * sh.rpt));
     const int col_chunks = (D.n + sh.cols - 1) / sh.cols;
     const dim3 grid((unsigned)((int64_t)row_tiles * col_chunks));
-    if (sh.rpt == 8) hipLaunchKernelGGL((k_vec_c<8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
-    else if (sh.rpt == 2) hipLaunchKernelGGL((k_vec_c<2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
-    else hipLaunchKernelGGL((k_vec_c<4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+    if (sh.rpt == 8) launch_timed(k_vec_c<8>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
+    else if (sh.rpt == 2) launch_timed(k_vec_c<2>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
+    else launch_timed(k_vec_c<4>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
   } else if (D.V) {
     const VecShape sh = vec_shape(D.n);
     const int row_tiles = (int)((D.n + (int64_t)BLOCK * sh.rpt - 1) / ((int64_t)BLOCK * sh.rpt));
@@ -343,18 +361,21 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
     const bool pair = (D.n % 2 == 0) && (D.ldv % 2 == 0) && (((uintptr_t)D.V & 15) == 0) &&
                       (!D.U || ((D.ldu % 2 == 0) && (((uintptr_t)D.U & 15) == 0)));
     if (sh.rpt == 8) {
-      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
-      else hipLaunchKernelGGL((k_vec<KIND, 1, 8>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      if (pair) launch_timed(k_vec<KIND, 2, 8>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
+      else launch_timed(k_vec<KIND, 1, 8>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
     } else if (sh.rpt == 2) {
-      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
-      else hipLaunchKernelGGL((k_vec<KIND, 1, 2>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      if (pair) launch_timed(k_vec<KIND, 2, 2>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
+      else launch_timed(k_vec<KIND, 1, 2>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
     } else {
-      if (pair) hipLaunchKernelGGL((k_vec<KIND, 2, 4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
-      else hipLaunchKernelGGL((k_vec<KIND, 1, 4>), grid, dim3(BLOCK), 0, st, D, row_tiles, sh.cols);
+      if (pair) launch_timed(k_vec<KIND, 2, 4>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
+      else launch_timed(k_vec<KIND, 1, 4>, grid, dim3(BLOCK), 0, st, v0, v1, D, row_tiles, sh.cols);
     }
   }
-  mark(5);
-  h->have_last = tm ? 1 : 0;
+  if (!v1) mark(5);
+  if (tm) {
+    h->ev_set = es;
+    h->timed_calls = std::min(h->timed_calls + 1, 2);
+  }
   h->last_n = D.n;
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
@@ -400,7 +421,8 @@ int arrow_destroy(arrow_handle_t h) {
   tridiag_release(h);
   if (h->ws) (void)hipFree(h->ws);
   if (h->ev_made)
-    for (int e = 0; e < 6; ++e) (void)hipEventDestroy(h->ev[e]);
+    for (int k = 0; k < 2; ++k)
+      for (int e = 0; e < 6; ++e) (void)hipEventDestroy(h->ev[k][e]);
   h->magic = 0;
   free(h);
   return ARROW_OK;
@@ -436,8 +458,9 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
     case ARROW_OPT_TIMING:
       if (value != 0.0 && !h->ev_made) {
         DeviceGuard g(h->device);
-        for (int e = 0; e < 6; ++e)
-          if (hipEventCreate(&h->ev[e]) != hipSuccess) return ARROW_ERR_HIP;
+        for (int k = 0; k < 2; ++k)
+          for (int e = 0; e < 6; ++e)
+            if (hipEventCreate(&h->ev[k][e]) != hipSuccess) return ARROW_ERR_HIP;
         h->ev_made = 1;
       }
       h->timing = value != 0.0;
@@ -455,19 +478,23 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
 
 size_t arrow_workspace_size(int64_t n) { return n < 1 ? 0 : ws_doubles(n) * sizeof(double); }
 
-int arrow_last_timing(arrow_handle_t h, double* ms) {
+int arrow_timing_of(arrow_handle_t h, int age, double* ms) {
   if (!valid(h)) return -1;
   if (!ms) return -2;
-  if (!h->have_last) return ARROW_ERR_STATE;
+  if (age != 0 && age != 1) return -3;
+  if (h->timed_calls <= age) return ARROW_ERR_STATE;
   DeviceGuard g(h->device);
-  if (hipEventSynchronize(h->ev[5]) != hipSuccess) return ARROW_ERR_HIP;
+  hipEvent_t* ev = h->ev[age == 0 ? h->ev_set : 1 - h->ev_set];
+  if (hipEventSynchronize(ev[5]) != hipSuccess) return ARROW_ERR_HIP;
   for (int e = 0; e < 5; ++e) {
     float t = 0.0f;
-    if (hipEventElapsedTime(&t, h->ev[e], h->ev[e + 1]) != hipSuccess) return ARROW_ERR_HIP;
+    if (hipEventElapsedTime(&t, ev[e], ev[e + 1]) != hipSuccess) return ARROW_ERR_HIP;
     ms[e] = t;
   }
   return ARROW_OK;
 }
+
+int arrow_last_timing(arrow_handle_t h, double* ms) { return arrow_timing_of(h, 0, ms); }
 
 int arrow_last_counters(arrow_handle_t h, int64_t* out) {
   if (!valid(h)) return -1;

@@ -18,9 +18,12 @@ struct arrow_handle_s {
   ahd::Options opt;
   int lanes;          // single problems: 0 = automatic, else lanes per eigenvalue
   int timing;         // record stage events
-  hipEvent_t ev[6];
+  // stage events of the two most recent timed calls, used in turn, so that a
+  // caller may read one call's stages after queuing the next
+  hipEvent_t ev[2][6];
   int ev_made;
-  int have_last;      // a timed call has been launched
+  int ev_set;         // set of the most recent timed call
+  int timed_calls;    // timed calls launched so far, up to 2
   int64_t last_n;
   size_t lds_max;     // bytes of dynamic LDS one block may use
   int cus;            // compute units of the device
