@@ -83,12 +83,25 @@ __global__ __launch_bounds__(FRONT_BLOCK) void k_front(ProbDesc D) {
     }
     return;
   }
-  for (int j = threadIdx.x; j < ms; j += FRONT_BLOCK) {
-    put_sorted<KIND>(D, w, rev ? ms - 1 - j : j, j);
-    w.st[j] = input_status<KIND>(D, j, false);
+  // the copy and the prologue of each sorted entry r by the thread that reads
+  // its source q, from registers; the corner partial sums run over r = t,
+  // t + FRONT_BLOCK, ... as in prologue_block, so the corner is the same bits
+  // either way the input arrives
+  const int m = D.n - 1;
+  const double dn = (KIND == KIND_DPR1) ? in_pole<KIND>(D, rev ? 0 : ms - 1) : 0.0;   // the last sorted pole
+  uint32_t st = 0, zp = 0;
+  dd acc = {0.0, 0.0};
+  for (int r = threadIdx.x; r < ms; r += FRONT_BLOCK) {
+    const int q = rev ? ms - 1 - r : r;
+    const SortedEntry e = put_sorted_v<KIND>(D, w, r, q);
+    st |= input_status<KIND>(D, q, false);
+    acc = dd_add(acc, corner_term_v<KIND>(D, e.z));
+    if (r < m) {
+      prologue_vals<KIND>(D, w, r, e.d, e.z, e.c, dn);
+      zp |= (e.d == 0.0) ? 1u : 0u;
+    }
   }
-  __syncthreads();
-  prologue_block<KIND, FRONT_BLOCK>(D);
+  prologue_reduce<KIND, FRONT_BLOCK>(D, w, acc, st, zp);
   if (threadIdx.x == 0) w.hdr[5] = 0.0;
 }
 

@@ -55,26 +55,16 @@ __device__ inline void deflate_block(const Ws& w, int m) {
 }
 
 // Shaft weights and corner of the (reduced) arrowhead in double-double, the
-// problem flags, and whether some pole is exactly zero.  One block of NT threads.
-template <int KIND, int NT = BLOCK>
-__device__ inline void prologue_block(const ProbDesc& D) {
+// problem flags, and whether some pole is exactly zero.  One block of NT
+// threads.  prologue_reduce combines the threads' corner partial sums (a
+// fixed tree), statuses and zero-pole bits and writes the header; a reducible
+// arrowhead is then deflated.
+template <int KIND, int NT>
+__device__ inline void prologue_reduce(const ProbDesc& D, const Ws& w, dd acc, uint32_t st, uint32_t zp) {
   __shared__ double shi[NT], slo[NT];
   __shared__ uint32_t sst[NT];
-  const Ws w = ws_view(D.ws, D.n);
-  const int ms = sorted_count(D);
   const int m = D.n - 1;
   const int t = threadIdx.x;
-  uint32_t st = 0;
-  uint32_t zp = 0;
-  dd acc = {0.0, 0.0};
-  for (int j = t; j < ms; j += NT) {
-    st |= w.st[j];
-    acc = dd_add(acc, corner_term<KIND>(D, w, j));
-  }
-  for (int j = t; j < m; j += NT) {
-    prologue_elem<KIND>(D, w, j);
-    zp |= (w.ds[j] == 0.0) ? 1u : 0u;
-  }
   shi[t] = acc.hi;
   slo[t] = acc.lo;
   sst[t] = st | (zp << 31);
@@ -104,6 +94,28 @@ __device__ inline void prologue_block(const ProbDesc& D) {
     if (flags == INFO_REDUCIBLE) deflate_block<NT>(w, m);
   }
   __syncthreads();
+}
+
+// The prologue over the sorted copy in the workspace: statuses (w.st), the
+// corner partial sums by thread over j = t, t + NT, ..., and the weights.
+template <int KIND, int NT = BLOCK>
+__device__ inline void prologue_block(const ProbDesc& D) {
+  const Ws w = ws_view(D.ws, D.n);
+  const int ms = sorted_count(D);
+  const int m = D.n - 1;
+  const int t = threadIdx.x;
+  uint32_t st = 0;
+  uint32_t zp = 0;
+  dd acc = {0.0, 0.0};
+  for (int j = t; j < ms; j += NT) {
+    st |= w.st[j];
+    acc = dd_add(acc, corner_term<KIND>(D, w, j));
+  }
+  for (int j = t; j < m; j += NT) {
+    prologue_elem<KIND>(D, w, j);
+    zp |= (w.ds[j] == 0.0) ? 1u : 0u;
+  }
+  prologue_reduce<KIND, NT>(D, w, acc, st, zp);
 }
 
 // Sort of one problem by one block: a copy when the input already has

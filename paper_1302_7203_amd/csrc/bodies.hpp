@@ -193,50 +193,79 @@ __host__ __device__ inline uint32_t input_status(const ProbDesc& D, int j, bool 
 // sorted entry r from the caller's entry q: the pole, the shaft entry (HERM:
 // the weight |z_q|^2 = re^2 + im^2 as an exact-product double-double, which
 // Sec. 6.1 asks for in doubled precision), and for ARROW the row's sorted index
+struct SortedEntry {
+  double d, z;   // the sorted pole and shaft entry as stored
+  dd c;          // HERM: the weight |z_q|^2 as stored; else unused
+};
+
 template <int KIND>
-__host__ __device__ inline void put_sorted(const ProbDesc& D, const Ws& w, int r, int q) {
-  w.ds[r] = in_pole<KIND>(D, q);
+__host__ __device__ inline SortedEntry put_sorted_v(const ProbDesc& D, const Ws& w, int r, int q) {
+  SortedEntry e;
+  e.d = in_pole<KIND>(D, q);
+  e.c = dd_from(0.0);
+  w.ds[r] = e.d;
   if constexpr (KIND == KIND_HERM) {
     const double re = D.z[2 * q], im = D.z[2 * q + 1];
-    const dd c = dd_add(two_prod(re, re), two_prod(im, im));
-    w.ch[r] = c.hi;
-    w.cl[r] = c.lo;
-    w.zs[r] = hypot(re, im);   // |z_q| rounded (only the bounds use it); exact when im = 0
+    e.c = dd_add(two_prod(re, re), two_prod(im, im));
+    w.ch[r] = e.c.hi;
+    w.cl[r] = e.c.lo;
+    e.z = hypot(re, im);   // |z_q| rounded (only the bounds use it); exact when im = 0
   } else {
-    w.zs[r] = D.z[q];
+    e.z = D.z[q];
   }
+  w.zs[r] = e.z;
   if constexpr (KIND == KIND_ARROW) w.iperm[q] = r;
+  return e;
+}
+
+template <int KIND>
+__host__ __device__ inline void put_sorted(const ProbDesc& D, const Ws& w, int r, int q) {
+  (void)put_sorted_v<KIND>(D, w, r, q);
 }
 
 // ---------------------------------------------------------------------------
 // prologue: the reduced arrowhead's shaft weights, exactly in double-double.
 
+// sorted entry j from its values: pole dj, shaft entry zj, HERM weight cj, and
+// for DPR1 the last pole dn
 template <int KIND>
-__host__ __device__ inline void prologue_elem(const ProbDesc& D, const Ws& w, int j) {
+__host__ __device__ inline void prologue_vals(const ProbDesc& D, const Ws& w, int j, double dj, double zj, dd cj,
+                                              double dn) {
   dd c;
   if constexpr (KIND == KIND_HERM) {
-    c = dd{w.ch[j], w.cl[j]};                             // |zeta_j|^2, formed by the sort
+    c = cj;                                               // |zeta_j|^2, formed by the sort
   } else if constexpr (KIND == KIND_ARROW) {
-    c = two_prod(w.zs[j], w.zs[j]);                       // zeta_j^2
+    c = two_prod(zj, zj);                                 // zeta_j^2
   } else if constexpr (KIND == KIND_SVD) {
-    const dd p = two_prod(w.ds[j], w.zs[j]);              // d_j zeta_j (Sec. 6.2)
+    const dd p = two_prod(dj, zj);                        // d_j zeta_j (Sec. 6.2)
     c = dd_mul(p, p);
   } else {
-    const double dn = w.ds[D.n - 1];                      // Sec. 6.3: zeta_j^2 = rho u_j^2 (d_j - d_n)
-    const dd diff = two_sum(w.ds[j], -dn);
-    c = dd_mul_d(dd_mul(two_prod(w.zs[j], w.zs[j]), diff), D.scalar);
+    const dd diff = two_sum(dj, -dn);                     // Sec. 6.3: zeta_j^2 = rho u_j^2 (d_j - d_n)
+    c = dd_mul_d(dd_mul(two_prod(zj, zj), diff), D.scalar);
   }
   w.ch[j] = c.hi;
   w.cl[j] = c.lo;
-  w.dz[j] = (KIND == KIND_ARROW || KIND == KIND_HERM) ? fabs(w.zs[j]) : sqrt(c.hi);
+  w.dz[j] = (KIND == KIND_ARROW || KIND == KIND_HERM) ? fabs(zj) : sqrt(c.hi);
 }
 
-// contribution of sorted entry j to the corner
+template <int KIND>
+__host__ __device__ inline void prologue_elem(const ProbDesc& D, const Ws& w, int j) {
+  const dd cj = (KIND == KIND_HERM) ? dd{w.ch[j], w.cl[j]} : dd_from(0.0);
+  const double dn = (KIND == KIND_DPR1) ? w.ds[D.n - 1] : 0.0;
+  prologue_vals<KIND>(D, w, j, w.ds[j], w.zs[j], cj, dn);
+}
+
+// contribution of a sorted shaft entry zj to the corner
+template <int KIND>
+__host__ __device__ inline dd corner_term_v(const ProbDesc& D, double zj) {
+  if constexpr (KIND == KIND_ARROW || KIND == KIND_HERM) return dd_from(0.0);
+  else if constexpr (KIND == KIND_SVD) return two_prod(zj, zj);                   // z^T z
+  else return dd_mul_d(two_prod(zj, zj), D.scalar);                                // rho u^T u
+}
+
 template <int KIND>
 __host__ __device__ inline dd corner_term(const ProbDesc& D, const Ws& w, int j) {
-  if constexpr (KIND == KIND_ARROW || KIND == KIND_HERM) return dd_from(0.0);
-  else if constexpr (KIND == KIND_SVD) return two_prod(w.zs[j], w.zs[j]);           // z^T z
-  else return dd_mul_d(two_prod(w.zs[j], w.zs[j]), D.scalar);                          // rho u^T u
+  return corner_term_v<KIND>(D, w.zs[j]);
 }
 
 template <int KIND>
