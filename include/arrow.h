@@ -313,11 +313,17 @@ int arrow_last_counters(arrow_handle_t h, int64_t* out);
  *   (16-byte aligned, not overlapping) with 16-byte loads and stores: a plain
  *   copy of known size, to scale hardware traffic counters.  Returns -1 bad
  *   dst, -2 bad src, -3 bad bytes.
+ * arrow_probe_rcp: the solver's three reciprocals of x[0 .. n) (device memory,
+ *   finite, nonzero, in the normal range): out[i] the hardware estimate alone,
+ *   out[n + i] after one Newton step, out[2n + i] after two (out: 3n doubles,
+ *   device memory, caller-owned).  Their accuracy is what the solver's choice
+ *   of reciprocal per pass relies on.  Returns -1 x null, -2 out null, -3 n < 1.
  * All return ARROW_ERR_HIP if the launch fails.
  */
 int arrow_probe_fma(double* out, int64_t blocks, int iters, void* stream);
 int arrow_probe_fill(double* dst, int64_t bytes, double value, void* stream);
 int arrow_probe_copy(double* dst, const double* src, int64_t bytes, void* stream);
+int arrow_probe_rcp(const double* x, double* out, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

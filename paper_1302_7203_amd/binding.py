@@ -82,7 +82,8 @@ def lib():
                 L.arrow_probe_fma.argtypes = [P, I64, I, P]
                 L.arrow_probe_fill.argtypes = [P, I64, D, P]
                 L.arrow_probe_copy.argtypes = [P, P, I64, P]
-                for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy",
+                L.arrow_probe_rcp.argtypes = [P, P, I64, P]
+                for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy", "arrow_probe_rcp",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
                           "arrow_eig", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing",
                           "arrow_timing_of", "arrow_last_counters",

@@ -1,11 +1,13 @@
 // Calibration kernels: what the device sustains for the two resources the
 // solver is bound by (FP64 vector FMA issue, HBM streaming writes), and a
 // plain copy of known size, the reference against which hardware traffic
-// counters are scaled.  They touch only the buffers they are given.
+// counters are scaled; and the solver's three reciprocals, whose accuracy
+// its error reasoning relies on.  They touch only the buffers they are given.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/arrow.h"
+#include "solver.hpp"
 
 namespace {
 
@@ -42,6 +44,18 @@ __global__ __launch_bounds__(PROBE_BLOCK) void k_probe_copy(v2d* dst, const v2d*
   for (int64_t i = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; i < n2; i += stride) dst[i] = src[i];
 }
 
+// the solver's reciprocals of x[i]: out[i] the bare estimate, out[n + i] one
+// Newton step, out[2n + i] two
+__global__ __launch_bounds__(PROBE_BLOCK) void k_probe_rcp(const double* x, double* out, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * PROBE_BLOCK;
+  for (int64_t i = (int64_t)blockIdx.x * PROBE_BLOCK + threadIdx.x; i < n; i += stride) {
+    const double v = x[i];
+    out[i] = ahd::recip_est(v);
+    out[n + i] = ahd::recip1(v);
+    out[2 * n + i] = ahd::recip(v);
+  }
+}
+
 int grid_for(int64_t items, int cap) {
   const int64_t g = (items + PROBE_BLOCK - 1) / PROBE_BLOCK;
   return (int)(g < cap ? (g > 0 ? g : 1) : cap);
@@ -76,6 +90,15 @@ int arrow_probe_copy(double* dst, const double* src, int64_t bytes, void* stream
   const int64_t n2 = bytes / 16;
   hipLaunchKernelGGL(k_probe_copy, dim3((unsigned)grid_for(n2, 1 << 16)), dim3(PROBE_BLOCK), 0, (hipStream_t)stream,
                      (v2d*)dst, (const v2d*)src, n2);
+  return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
+}
+
+int arrow_probe_rcp(const double* x, double* out, int64_t n, void* stream) {
+  if (!x) return -1;
+  if (!out) return -2;
+  if (n < 1) return -3;
+  hipLaunchKernelGGL(k_probe_rcp, dim3((unsigned)grid_for(n, 1 << 16)), dim3(PROBE_BLOCK), 0, (hipStream_t)stream, x,
+                     out, n);
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
 
