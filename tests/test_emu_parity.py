@@ -194,3 +194,18 @@ def test_power_of_two_scaling_is_exact(k, oracle_lib):
         b = emu.solve(kind, pr.d * s, zs, pr.scalar * s)
         assert np.array_equal(b["lam"], a["lam"] * s), kind
         assert np.array_equal(b["V"], a["V"]), kind
+
+
+@pytest.mark.parametrize("case,mean_max,worst_max", [
+    ("graded_1024", 2.5, 7), ("graded_2048_c16", 2.4, 6), ("uniform_512", 4.0, 7), ("graded_4096", 2.3, 8)])
+def test_rational_passes_stay_few(case, mean_max, worst_max):
+    """The secular iteration for the extreme eigenvalue of A_i^{-1}, with each step confined by
+    the lower (tangent of the far poles) and upper (nearest-pole fit) model bounds on the zero:
+    spectra spread over 20 decades with tight clusters converge in a few O(n) passes, the worst
+    eigenvalue included (it took 8-10 before the bounds were kept)."""
+    pr = {"graded_1024": lambda: W.graded_arrow(1024, np.random.default_rng(201)),
+          "graded_2048_c16": lambda: W.graded_arrow(2048, np.random.default_rng(202), clusters=16),
+          "uniform_512": W.single_uniform_512, "graded_4096": W.single_graded_4096}[case]()
+    r = emu.solve(0, pr.d, pr.z, pr.scalar, vectors=False)
+    it = r["cnt"][:, 0]
+    assert it.mean() <= mean_max and it.max() <= worst_max, (it.mean(), it.max())
