@@ -347,7 +347,12 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
   const size_t hot = (size_t)(ms + D.n - 1) * sizeof(double);
   const size_t lds = (hot <= h->lds_max) ? hot : 0;
   launch_rc_any<SK>(G, D, h->opt, st, false, lds, at(2), at(3));
-  launch_rc_any<SK>(G, D, h->opt, st, true, lds);
+  // the check stage reads the poles only for DPR1 norms or after bisection;
+  // otherwise the root pass left the norm and what remains per eigenvalue is
+  // scalar work: one lane each, no staged copy
+  const bool check_reads_poles = SK == KIND_DPR1 || h->opt.root != ROOT_RATIONAL;
+  if (check_reads_poles) launch_rc_any<SK>(G, D, h->opt, st, true, lds);
+  else launch_rc_any<SK>(1, D, h->opt, st, true, 0);
   {
     // deferred repairs; the block reductions add a little static LDS
     const size_t lds_r = (hot + 4096 <= h->lds_max) ? hot : 0;

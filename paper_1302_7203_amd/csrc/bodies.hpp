@@ -32,7 +32,7 @@ struct ProbDesc {
   double* ws;          // workspace of ws_doubles(n) doubles
 };
 
-__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 24; }
+__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 25; }
 
 // Workspace of one problem.
 struct Ws {
@@ -65,6 +65,7 @@ struct Ws {
   int32_t* df;      // ... and the first nonzero row of its run (-1: a unit vector)
   int32_t* cm;      // per output column: deflated eigenpair index, or -1
   int32_t* iperm;   // caller row -> sorted index
+  double* nr1;      // first pass: 1 / ||x|| at the first-pass mu, from the root's last pass (NaN: none)
 };
 
 __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
@@ -96,6 +97,7 @@ __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
   w.df = w.dm + N; p += N;
   w.cm = (int32_t*)p;
   w.iperm = w.cm + N; p += N;
+  w.nr1 = p; p += N;
   return w;
 }
 
@@ -386,6 +388,7 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   const Ws w = ws_view(D.ws, D.n);
   const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
+  if (ln == 0) w.nr1[k] = NAN;   // the norm from the root pass, set below when there is one
   if (k >= P.n) {   // past the order of a deflated problem
     if (ln == 0) { w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0; }
     return;
@@ -408,9 +411,25 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   select_shift<KIND, G>(P, k, ln, i, side);
   const BPass bp = b_pass<KIND, G>(P, i, side, ln, opt.fp64_b);
   int iters = 0;
+  double last[3] = {NAN, NAN, NAN};   // the rational pass's last point nu and its sums S2, S3
   const double nu = (opt.root == ROOT_RATIONAL)
-      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters)
+      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters, NAN, last)
       : bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
+  // ||x||^2 of eq. (eigenvecAi) at mu = 1/nu: with v_j = 1/(nu e_j - 1) the
+  // entry x_j = zeta_j/(e_j - mu) is nu zeta_j v_j (j != i) and x_i = -nu zeta_i, so
+  // ||x||^2 = nu^2 (S2 + zeta_i^2) + 1, S2 = sum_{j != i} zeta_j^2 v_j^2 -- the sum
+  // the rational pass forms for psi'.  It was formed at that pass's point;
+  // the step to the final nu is taken to first order, d/dnu (nu^2 S2(nu)) =
+  // 2 nu S2 - 2 nu^2 S3 with S3 = sum zeta_j^2 e_j v_j^3, also formed there.
+  // (DPR1's vector is not the arrowhead's: its norm takes a pass of its own.)
+  double nr1 = NAN;
+  if constexpr (KIND != KIND_DPR1) {
+    if (last[0] == last[0]) {
+      const double ln_ = last[0], a0 = last[1] + P.ch[i];
+      const double acc = ln_ * ln_ * a0 + 1.0 + (2.0 * ln_ * a0 - 2.0 * ln_ * ln_ * last[2]) * (nu - ln_);
+      nr1 = 1.0 / sqrt(acc);
+    }
+  }
   if (ln == 0) {
     w.cnt[6 * k + 0] = iters;
     w.cnt[6 * k + 1] = opt.fp64_b ? 0 : 1;
@@ -418,6 +437,7 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
     w.pv1[k] = P.ds[i];
     w.mu1[k] = 1.0 / nu;
     w.kb1[k] = bp.Kb;
+    w.nr1[k] = nr1;
     w.ip1[k] = i;
     uint32_t fl = opt.fp64_b ? 0u : INFO_DD_B;
     // Theorem 6 needs K_b <= O(1/eps); flag when the double-double b cannot hold it
@@ -561,7 +581,11 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       }
     }
   }
-  const double inrm = inv_norm<KIND, G>(P, pv, s, mu, ln);
+  // the first pass's norm holds while its shift and mu stand (no remedy)
+  const double nr1 = w.nr1[k];
+  const bool first = pv == w.pv1[k] && s == 0.0 && mu == w.mu1[k] && nr1 == nr1;
+  const double inrm = first ? nr1 : inv_norm<KIND, G>(P, pv, s, mu, ln);
+  if (first) c_plain -= 1;   // no norm pass
   if (ln == 0) {
     w.cnt[6 * k + 3] = c_it;
     w.cnt[6 * k + 4] = c_dd;

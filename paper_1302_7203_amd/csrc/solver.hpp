@@ -589,7 +589,7 @@ __host__ __device__ inline double bounded_next(double x, double h, double hnoise
 template <int KIND, int G>
 __host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
                                                    double hi, double ymax_nu, int ln, int* iters,
-                                                   double nu_est = NAN) {
+                                                   double nu_est = NAN, double* last = nullptr) {
   const double sg = (double)side;
   const double di = P.ds[i];
   const double rci = 1.0 / P.ch[i];
@@ -632,6 +632,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     const double nu = sg * x;
     double s1, s2, s3;
     psi_pass<KIND, G, false>(P, di, 0.0, i, nu, ln, s1, s2, s3);
+    if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
     const double rnu = 1.0 / nu;
     const double psi = (s1 + rnu) * rci;                       // psi(nu)
     const double dpsi = -(s2 + rnu * rnu) * rci;               // psi'(nu)

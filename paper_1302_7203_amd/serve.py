@@ -103,7 +103,7 @@ def request_parts(pr: Problem, vectors=True):
     104-byte descriptor and four table words)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 24 * pr.n)) + 128
+    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 25 * pr.n)) + 128
     return out, info, rest
 
 
