@@ -382,6 +382,18 @@ __host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, i
 // first pass for eigenvalue k: shift, b, bisection (Algorithm 5 without the
 // final K_nu test).
 
+// 1/||x|| of eq. (eigenvecAi) at the root nu of a rational pass over the poles
+// shifted by (pv, s), from that pass's last point last[0] and its sums
+// last[1] = S2 = sum zeta_j^2 v_j^2 and last[2] = S3 = sum zeta_j^2 e_j v_j^3,
+// v_j = 1/(nu e_j - 1): the entries are nu zeta_j v_j, the excluded pole's (weight
+// cx; 0 when none is excluded) -nu zeta_x, and -1, so ||x||^2 = nu^2 (S2 + cx) + 1,
+// carried from last[0] to nu to first order (d(nu^2 S2)/dnu = 2 nu S2 - 2 nu^2 S3).
+__host__ __device__ inline double norm_from_pass(const double* last, double nu, double cx) {
+  const double l = last[0], a0 = last[1] + cx;
+  const double acc = l * l * a0 + 1.0 + (2.0 * l * a0 - 2.0 * l * l * last[2]) * (nu - l);
+  return 1.0 / sqrt(acc);
+}
+
 template <int KIND, int G, bool HOT = false>
 __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln,
                                           const double* hot_d = nullptr, const double* hot_c = nullptr) {
@@ -424,11 +436,7 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   // (DPR1's vector is not the arrowhead's: its norm takes a pass of its own.)
   double nr1 = NAN;
   if constexpr (KIND != KIND_DPR1) {
-    if (last[0] == last[0]) {
-      const double ln_ = last[0], a0 = last[1] + P.ch[i];
-      const double acc = ln_ * ln_ * a0 + 1.0 + (2.0 * ln_ * a0 - 2.0 * ln_ * ln_ * last[2]) * (nu - ln_);
-      nr1 = 1.0 / sqrt(acc);
-    }
+    if (last[0] == last[0]) nr1 = norm_from_pass(last, nu, P.ch[i]);
   }
   if (ln == 0) {
     w.cnt[6 * k + 0] = iters;
@@ -494,6 +502,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   uint32_t fl = w.fl1[k];
   const int m = P.m;
   int c_it = 0, c_dd = 0, c_plain = 1;   // the norm pass
+  double rn = NAN;   // 1/||x|| from a remedy's last rational pass, when it ran one
   if (m > 0 && opt.remedies) {
     const int i = w.ip1[k];
     const int side = (k == i) ? +1 : -1;
@@ -516,8 +525,10 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     if (quot > opt.tau_zero && !zero_pole) {
       // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
       int z0 = 0, it = 0;
-      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root, 1.0 / lam1);
+      double last[3] = {NAN, NAN, NAN};
+      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root, 1.0 / lam1, last);
       pv = 0.0; s = 0.0; mu = z0 ? 0.0 : m2;
+      if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
       fl |= INFO_NEAR_ZERO;
       c_it += it; c_dd += 1;
     } else if (knu > opt.tau_nu) {
@@ -540,11 +551,13 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
           const int side2 = -side;
           // first-pass lambda seen from the other pole: 1 / (lambda - d_i2)
           const double nu_est = 1.0 / (pdiff<KIND>(di, d2) + mu);
+          double last[3] = {NAN, NAN, NAN};
           const double nu = (opt.root == ROOT_RATIONAL)
               ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it,
-                                          nu_est)
+                                          nu_est, last)
               : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
           pv = d2; s = 0.0; mu = 1.0 / nu;
+          if (KIND != KIND_DPR1 && last[0] == last[0]) rn = norm_from_pass(last, nu, P.ch[i2]);
           fl |= INFO_REMEDY_A;
           done = true;
           c_it += it; c_dd += opt.fp64_b ? 0 : 1; c_plain += opt.fp64_b ? 1 : 0;
@@ -555,8 +568,10 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
         // 2^-10 |mu| away from lambda
         s = mu - mu * (1.0 / 1024.0);
         int z0 = 0, it = 0;
-        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s));
+        double last[3] = {NAN, NAN, NAN};
+        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s), last);
         pv = di; mu = z0 ? 0.0 : m2;
+        if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
         fl |= INFO_REMEDY_B;
         c_it += it; c_dd += 1;
       }
@@ -584,8 +599,8 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   // the first pass's norm holds while its shift and mu stand (no remedy)
   const double nr1 = w.nr1[k];
   const bool first = pv == w.pv1[k] && s == 0.0 && mu == w.mu1[k] && nr1 == nr1;
-  const double inrm = first ? nr1 : inv_norm<KIND, G>(P, pv, s, mu, ln);
-  if (first) c_plain -= 1;   // no norm pass
+  const double inrm = first ? nr1 : (rn == rn ? rn : inv_norm<KIND, G>(P, pv, s, mu, ln));
+  if (first || rn == rn) c_plain -= 1;   // no norm pass
   if (ln == 0) {
     w.cnt[6 * k + 3] = c_it;
     w.cnt[6 * k + 4] = c_dd;

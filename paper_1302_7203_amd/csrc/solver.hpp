@@ -662,7 +662,8 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
 
 template <int KIND, int G>
 __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double s, int ln, int* zero,
-                                               int* iters, int method, double nu_est = NAN) {
+                                               int* iters, int method, double nu_est = NAN,
+                                               double* last = nullptr) {
   const int m = P.m;
   dd fs = {0.0, 0.0};
   double usum = 0.0, dmx = -INFINITY, dmn = INFINITY;
@@ -705,6 +706,7 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
       const double nu = sg * x;
       double s1, s2, s3;
       psi_pass<KIND, G, true>(P, pv, s, -1, nu, ln, s1, s2, s3);
+      if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
       const double rnu = 1.0 / nu;
       const double psi_x = sg * (s1 + rnu);
       const double dpsi_x = -(s2 + rnu * rnu);
