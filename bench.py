@@ -40,9 +40,9 @@ F_BISECT = 7      # bisection step: e = d_j - d_i (1), fma(-nu, e, 1) (2), e*(.)
 F_RATIONAL = 14   # rational step: e (1), fma(nu, e, -1) (2), e*(.) (1), 1/(.) (1), v = e q (1), fma(c_j, q, .) (2),
                   # (c_j v) v (2), sum (1), e v (1), fma(d1, e v, .) (2)
 F_SELECT = 5      # shift selection: (d_j - d_k) - mid (2), 1/(.) (1), fma(c_j, ., s) (2)
-F_DD = 30         # b in double-double: e (1), 1/e (1), the rest of TwoSum(d_j, -d_i) (5), two-digit quotient
-                  # (q1 1, TwoProd 3, remainder 5, second digit 1), TwoSum accumulate (8), Gershgorin
-                  # terms |w_j| (1), sum (1), side*delta_j (1), fma (2)
+F_DD = 28         # b in double-double: e (1), 1/e (1), the rest of TwoSum(d_j, -d_i) (5), two-digit quotient
+                  # (q1 1, TwoProd 3, remainder 5, second digit 1), TwoSum accumulate (8), the upper
+                  # bracket end's sum of zeta_j^2 / e_j^2: (1/e)^2 (1), fma (2)
 F_NORM = 7        # eigenvector norm: (e_j - s) - mu (3), 1/(.) (1), c_j r (1), fma(., r, acc) (2)
 
 WORKLOADS = {

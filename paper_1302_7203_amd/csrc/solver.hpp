@@ -298,14 +298,12 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   const double sg = (double)side;
   dd p1 = {0.0, 0.0}, p2 = {0.0, 0.0};  // sum over j < i (>= 0), j > i (<= 0)
   double f1 = 0.0, f2 = 0.0;            // the same sums in FP64 (Algorithm 2 only)
-  double wsum = 0.0;                    // sum_{j != i} |shaft_j| / |e_j|
-  double gx = -INFINITY;                // max over j != i of side*delta_j + |w_j|
-  const double rzi = 1.0 / P.dz[i];
+  double r2 = 0.0;                      // sum_{j != i} zeta_j^2 / e_j^2
   for_terms<G>(ln, m, i, [&](int j, bool above) {
     const double ej = pdiff<KIND>(P.ds[j], di);
     // delta_j, the diagonal of A_i^{-1}, within 11 ulps: the two-digit
     // quotient's remainder corrects its first digit, so c/e stays good to
-    // about 2^-98, and the Gershgorin end below is widened for it
+    // about 2^-98, and the upper end below is widened for it
     const double rj = recip1(ej);
     if constexpr (FP64_B) {
       const double t = P.ch[j] * rj;
@@ -314,12 +312,9 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
       const dd q = dd_div2_raw(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
-    const double wj = P.dz[j] * fabs(rj);           // |w_j| |zeta_i|
-    wsum += wj;
-    gx = fmax(gx, fma(wj, rzi, sg * rj));
+    r2 = fma(P.ch[j], rj * rj, r2);
   });
-  wsum = gsum<G>(wsum);
-  gx = gmax<G>(gx);
+  r2 = gsum<G>(r2);
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
   const double ci = P.ch[i];
   BPass r;
@@ -343,16 +338,24 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
     num_abs = fabs(num.hi);
   }
   r.Kb = (fabs(a.hi) + fabs(f1) + fabs(f2)) / num_abs;
-  // Gershgorin discs of A_i^{-1}: rows j != i (centre delta_j, radius |w_j|),
-  // row i (centre 0, radius 1/|zeta_i|), last row (centre b, radius ||w||_1).
-  // On the requested side, in the variable side*nu: the extreme eigenvalue
-  // lies right of every centre and left of every disc's far end.  The
-  // rightmost centre side*delta_j > 0 belongs to the pole next to d_i on
-  // that side (the smallest |e_j| of that sign); with none, the row-i centre 0.
-  const double w1 = (wsum + 1.0) * rzi;
+  // The bracket of the extreme eigenvalue on the requested side, in the
+  // variable x = side*nu.  Lower end: the rightmost pole of A_i^{-1}'s Pick
+  // function, y = side*delta_j of the pole next to d_i on that side (the
+  // smallest |e_j| of that sign), or 0 with none (Gershgorin's rightmost
+  // centre, as in Algorithm 3).  Upper end: right of y the Pick function is
+  // h(x) = c0 - x + sum_j R_j/(x - p_j) with every pole p_j <= y and R_j > 0,
+  // R_j = zeta_j^2/(zeta_i^2 e_j^2) and R = 1/zeta_i^2 at p = 0, so
+  // h(x) <= c0 - x + R_tot/(x - y); the zero of that bound, y + u with
+  // u^2 - (c0 - y) u - R_tot = 0, lies right of the wanted zero.  It takes
+  // one sum of zeta_j^2/e_j^2 instead of the Gershgorin discs' sum and maximum
+  // and is mostly much the tighter, which saves rational steps too.
   const int jn = i - side;
   const double xl = (jn >= 0 && jn < m) ? fmax(sg * recip(pdiff<KIND>(P.ds[jn], di)), 0.0) : 0.0;
-  const double xh = fmax(fmax(gx, rzi), sg * r.b + w1) * (1.0 + 64.0 * EPS);
+  const double rtot = (r2 + 1.0) / ci;
+  const double c0y = sg * r.b - xl;
+  const double disc = sqrt(c0y * c0y + 4.0 * rtot);
+  const double u = (c0y >= 0.0) ? 0.5 * (c0y + disc) : 2.0 * rtot / (disc - c0y);
+  const double xh = (xl + u) * (1.0 + 64.0 * EPS);
   if (side > 0) { r.lo = xl; r.hi = xh; }
   else { r.lo = -xh; r.hi = -xl; }
   return r;
