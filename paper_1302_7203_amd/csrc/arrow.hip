@@ -206,7 +206,7 @@ template <int KIND, int G, bool STAGE>
 __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
   extern __shared__ double lds[];
   if constexpr (STAGE) stage_hot(D, lds);
-  const int gid = blockIdx.x * ROOT_BLOCK + threadIdx.x;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;   // blocks of ROOT_BLOCK, or CHECK_LANE_BLOCK
   const int k = gid / G;
   if (k >= D.n) return;
   if constexpr (STAGE) check_body<KIND, G, true, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
@@ -270,10 +270,19 @@ static void launch_timed(F kern, dim3 grid, dim3 block, size_t lds, hipStream_t 
   else hipLaunchKernelGGL(kern, grid, block, lds, st, args...);
 }
 
+// the check with one lane per eigenvalue and nothing staged is latency-bound
+// scalar work: small blocks spread it over more compute units
+constexpr int CHECK_LANE_BLOCK = 64;
+
 template <int KIND, int G>
 static void launch_rc(const ProbDesc& D, const Options& opt, hipStream_t st, bool check, size_t lds,
                       hipEvent_t e0, hipEvent_t e1) {
   const int64_t threads = (int64_t)D.n * G;
+  if (check && G == 1 && lds == 0) {
+    const dim3 grid((unsigned)((threads + CHECK_LANE_BLOCK - 1) / CHECK_LANE_BLOCK));
+    launch_timed(k_check<KIND, G, false>, grid, dim3(CHECK_LANE_BLOCK), 0, st, e0, e1, D, opt);
+    return;
+  }
   const dim3 grid((unsigned)((threads + ROOT_BLOCK - 1) / ROOT_BLOCK));
   if (lds > 0) {
     if (!check) launch_timed(k_root<KIND, G, true>, grid, dim3(ROOT_BLOCK), lds, st, e0, e1, D, opt);

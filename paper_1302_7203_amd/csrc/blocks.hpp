@@ -56,42 +56,53 @@ __device__ inline void deflate_block(const Ws& w, int m) {
 
 // Shaft weights and corner of the (reduced) arrowhead in double-double, the
 // problem flags, and whether some pole is exactly zero.  One block of NT
-// threads.  prologue_reduce combines the threads' corner partial sums (a
-// fixed tree), statuses and zero-pole bits and writes the header; a reducible
-// arrowhead is then deflated.
+// threads.  prologue_reduce combines the threads' corner partial sums (in a
+// fixed order: each wavefront's by a butterfly, then the wavefronts'),
+// statuses and zero-pole bits and writes the header; a reducible arrowhead is
+// then deflated.
 template <int KIND, int NT>
 __device__ inline void prologue_reduce(const ProbDesc& D, const Ws& w, dd acc, uint32_t st, uint32_t zp) {
-  __shared__ double shi[NT], slo[NT];
-  __shared__ uint32_t sst[NT];
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  constexpr int NW = NT / 64;
+  __shared__ double whi[NW], wlo[NW];
+  __shared__ uint32_t wst[NW];
+  __shared__ uint32_t sflags;
   const int m = D.n - 1;
   const int t = threadIdx.x;
-  shi[t] = acc.hi;
-  slo[t] = acc.lo;
-  sst[t] = st | (zp << 31);
-  __syncthreads();
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if (t < o) {
-      const dd a = dd_add(dd{shi[t], slo[t]}, dd{shi[t + o], slo[t + o]});
-      shi[t] = a.hi;
-      slo[t] = a.lo;
-      sst[t] |= sst[t + o];
-    }
-    __syncthreads();
+  // each wavefront's partial sums by the lanes' butterfly (every lane ends
+  // with the same bits), then the wavefronts' in order by one thread
+  const dd a = gsum_dd<64>(acc);
+  uint32_t f = st | (zp << 31);
+  for (int o = 32; o > 0; o >>= 1) f |= (uint32_t)__shfl_xor((int)f, o, 64);
+  if ((t & 63) == 0) {
+    whi[t >> 6] = a.hi;
+    wlo[t >> 6] = a.lo;
+    wst[t >> 6] = f;
   }
-  const uint32_t flags = sst[0] & 0x7fffffffu;
+  __syncthreads();
   if (t == 0) {
-    const dd c = dd_add(corner_base<KIND>(D, w), dd{shi[0], slo[0]});
+    dd c = corner_base<KIND>(D, w);
+    uint32_t all = 0;
+    dd sum = {whi[0], wlo[0]};
+    all |= wst[0];
+    for (int q = 1; q < NW; ++q) {
+      sum = dd_add(sum, dd{whi[q], wlo[q]});
+      all |= wst[q];
+    }
+    c = dd_add(c, sum);
     w.hdr[0] = c.hi;
     w.hdr[1] = c.lo;
-    w.hdr[2] = (sst[0] >> 31) ? 1.0 : 0.0;
-    *prob_flags(w) = flags;
+    w.hdr[2] = (all >> 31) ? 1.0 : 0.0;
+    *prob_flags(w) = all & 0x7fffffffu;
     *repair_count(w) = 0u;
     *place_done(w) = 0u;
     w.hdr[8] = (double)m;
     w.hdr[9] = 0.0;
+    sflags = all & 0x7fffffffu;
   }
+  __syncthreads();
   if constexpr (KIND == KIND_ARROW) {
-    if (flags == INFO_REDUCIBLE) deflate_block<NT>(w, m);
+    if (sflags == INFO_REDUCIBLE) deflate_block<NT>(w, m);
   }
   __syncthreads();
 }
