@@ -361,9 +361,9 @@ def extensions_leg(args, binding, workloads, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--timing-every", type=int, default=4,
+    ap.add_argument("--timing-every", type=int, default=10,
                     help="record the stage events on every k-th timed step (each event adds a dispatch gap)")
     ap.add_argument("--workload", default="graded_4096", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=512, help="eigenpairs the oracle solves for the CPU baseline")
