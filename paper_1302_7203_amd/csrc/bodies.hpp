@@ -391,7 +391,11 @@ __host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, i
 __host__ __device__ inline double norm_from_pass(const double* last, double nu, double cx) {
   const double l = last[0], a0 = last[1] + cx;
   const double acc = l * l * a0 + 1.0 + (2.0 * l * a0 - 2.0 * l * l * last[2]) * (nu - l);
-  return 1.0 / sqrt(acc);
+  if (acc < INFINITY) return 1.0 / sqrt(acc);
+  // l^2 overflowed (lambda within about 2^-512 of its pole): in units of l^2
+  const double rl = 1.0 / l;
+  const double acc2 = a0 + rl * rl + (2.0 * a0 * rl - 2.0 * last[2]) * (nu - l);
+  return fabs(rl) / sqrt(acc2);
 }
 
 template <int KIND, int G, bool HOT = false>

@@ -254,6 +254,21 @@ __host__ __device__ inline void for_terms(int ln, int m, int excl, F&& f) {
   for (; j < m; j += G) f(j, true);
 }
 
+// The positive zero of t^2 - beta t - s^2 (s >= 0), in the form that avoids
+// cancellation.  beta and s are first brought below 2 by a power of two, so
+// neither square leaves the exponent range: x-space quantities are of the
+// order of 1/(lambda - d_i), whose square overflows once lambda lies within
+// about 2^-512 of its pole, long before the quantities themselves do.
+__host__ __device__ inline double pos_root(double beta, double s) {
+  const double mx = fmax(fabs(beta), s);
+  if (mx == 0.0) return 0.0;
+  if (mx == INFINITY) return (beta == -INFINITY && s < INFINITY) ? 0.0 : INFINITY;
+  const int k = ilogb(mx);
+  const double b = ldexp(beta, -k), q = ldexp(s, -k);
+  const double r = sqrt(fma(b, b, 4.0 * q * q));
+  return (b >= 0.0) ? ldexp(0.5 * (b + r), k) : (2.0 * s) * (q / (r - b));
+}
+
 // ---------------------------------------------------------------------------
 // Shift selection (Algorithm 1, first part): eigenvalue k (0-based, descending)
 // lies in (d_k, d_{k-1}); the sign of the Pick function (eq. Pick) at the
@@ -298,7 +313,13 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   const double sg = (double)side;
   dd p1 = {0.0, 0.0}, p2 = {0.0, 0.0};  // sum over j < i (>= 0), j > i (<= 0)
   double f1 = 0.0, f2 = 0.0;            // the same sums in FP64 (Algorithm 2 only)
-  double r2 = 0.0;                      // sum_{j != i} zeta_j^2 / e_j^2
+  // sum_{j != i} zeta_j^2 (gs / e_j)^2 with gs the power of two at or below
+  // the distance to the nearest pole, so that every gs / e_j is at most 1
+  double r2 = 0.0;
+  double dn = INFINITY;
+  if (i > 0) dn = fabs(pdiff<KIND>(P.ds[i - 1], di));
+  if (i + 1 < m) dn = fmin(dn, fabs(pdiff<KIND>(P.ds[i + 1], di)));
+  const double gs = (dn > 0.0 && dn < INFINITY) ? ldexp(1.0, ilogb(dn)) : 1.0;
   for_terms<G>(ln, m, i, [&](int j, bool above) {
     const double ej = pdiff<KIND>(P.ds[j], di);
     // delta_j, the diagonal of A_i^{-1}, within 11 ulps: the two-digit
@@ -312,7 +333,8 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
       const dd q = dd_div2_raw(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
-    r2 = fma(P.ch[j], rj * rj, r2);
+    const double rs = rj * gs;
+    r2 = fma(P.ch[j], rs * rs, r2);
   });
   r2 = gsum<G>(r2);
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
@@ -351,10 +373,9 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   // and is mostly much the tighter, which saves rational steps too.
   const int jn = i - side;
   const double xl = (jn >= 0 && jn < m) ? fmax(sg * recip(pdiff<KIND>(P.ds[jn], di)), 0.0) : 0.0;
-  const double rtot = (r2 + 1.0) / ci;
-  const double c0y = sg * r.b - xl;
-  const double disc = sqrt(c0y * c0y + 4.0 * rtot);
-  const double u = (c0y >= 0.0) ? 0.5 * (c0y + disc) : 2.0 * rtot / (disc - c0y);
+  // the square root of the total residue (sum_j c_j / e_j^2 + 1) / zeta_i^2
+  const double srt = (sqrt(fma(gs, gs, r2)) / gs) / sqrt(ci);
+  const double u = pos_root(sg * r.b - xl, srt);
   const double xh = (xl + u) * (1.0 + 64.0 * EPS);
   if (side > 0) { r.lo = xl; r.hi = xh; }
   else { r.lo = -xh; r.hi = -xl; }
@@ -446,17 +467,20 @@ __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int
 // fitted equation has no zero right of p.
 __host__ __device__ inline double rational_candidate(double x, double psi_x, double dpsi_x, double pole, double c0,
                                                      int kappa) {
+  // A = -psi' u^2, B = psi_x - A / u (psi' <= 0).  The zero un = u t is taken
+  // in units of u, t^2 - (beta / u) t + psi' = 0: A itself, of the order of
+  // x^2, would overflow when x passes about 2^512, while beta / u and psi'
+  // are ratios of x-sized quantities
   const double u = x - pole;
-  const double A = -dpsi_x * u * u;
-  const double B = psi_x - A / u;
+  const double B = fma(dpsi_x, u, psi_x);
   double un = NAN;
   if (kappa) {
-    const double beta = c0 + B - pole;
-    const double disc = sqrt(beta * beta + 4.0 * A);
-    un = (beta >= 0) ? 0.5 * (beta + disc) : 2.0 * A / (disc - beta);
+    const double bb = (c0 + B - pole) / u;
+    const double r = sqrt(fma(bb, bb, -4.0 * dpsi_x));
+    un = u * ((bb >= 0) ? 0.5 * (bb + r) : -2.0 * dpsi_x / (r - bb));
   } else {
     const double beta = c0 + B;
-    if (beta < 0) un = -A / beta;
+    if (beta < 0) un = (dpsi_x * u) * (u / beta);
   }
   return (un > 0) ? pole + un : NAN;
 }
@@ -523,20 +547,24 @@ __host__ __device__ inline double rational_next(double x, double h, double hnois
 // convex right of y, its tangent lies below it and the model's zero lies left
 // of the true one.  In u = t - y the model is beta - gamma u + ry/u with
 //   beta = h + u_x (1 - psi_x') - 2 ry/u_x,  gamma = 1 - psi_x' - ry/u_x^2 >= 1,
-// whose positive zero is taken in the form that avoids cancellation.  NaN or
-// a value outside the bracket (overflow, rounding) is ignored by the caller.
-__host__ __device__ inline double tangent_rest_bound(double x, double h, double dpsi_x, double y, double ry) {
+// whose positive zero u = u_x tau is taken in units of u_x,
+//   gamma tau^2 - (beta / u_x) tau - ry / u_x^2 = 0,
+// in the form that avoids cancellation.  The residue comes as sry = sqrt(ry):
+// ry, of the order of x^2, overflows when x passes about 2^512, while sry and
+// the coefficients in units of u_x stay in range.  NaN or a value outside the
+// bracket (rounding) is ignored by the caller.
+__host__ __device__ inline double tangent_rest_bound(double x, double h, double dpsi_x, double y, double sry) {
   const double ux = x - y;
-  const double rux = ry / ux;
-  const double beta = h + ux * (1.0 - dpsi_x) - 2.0 * rux;
-  const double gamma = fmax(1.0 - dpsi_x - rux / ux, 1.0);
-  const double disc = sqrt(beta * beta + 4.0 * gamma * ry);
-  const double u = (beta >= 0.0) ? (beta + disc) / (2.0 * gamma) : 2.0 * ry / (disc - beta);
-  return y + u;
+  const double t = sry / ux;   // sqrt(ry) / u_x
+  const double beta = h + ux * (1.0 - dpsi_x) - 2.0 * (sry * t);
+  const double gamma = fmax(1.0 - dpsi_x - t * t, 1.0);
+  const double bb = beta / ux;
+  const double r = sqrt(fma(bb, bb, 4.0 * gamma * (t * t)));
+  return y + ux * ((bb >= 0.0) ? (bb + r) / (2.0 * gamma) : 2.0 * (t * t) / (r - bb));
 }
 
 // The step of rational_inverse, which also knows the residue ry of psi_x at
-// its nearest pole y.  Two closed-form models bound the zero before rounding:
+// its nearest pole y, as sry = sqrt(ry).  Two closed-form models bound the zero before rounding:
 // the nearest-pole fit A/(t - y) + B lies above psi_x everywhere right of y
 // (for each pole p < y the difference times (t - y)(t - p) is a quadratic
 // with a double zero at x and a positive leading coefficient), so its zero is
@@ -549,7 +577,7 @@ __host__ __device__ inline double tangent_rest_bound(double x, double h, double 
 // mass of psi_x sits on poles far left of y; the lower bound is what lets the
 // split close in from both sides.  The stopping rules are rational_next's.
 __host__ __device__ inline double bounded_next(double x, double h, double hnoise, double psi_x, double dpsi_x,
-                                               double d2psi_x, double y, double ry, double c0, double lo,
+                                               double d2psi_x, double y, double sry, double c0, double lo,
                                                double hi, int it, int hi_open, double& slo, double& shi,
                                                int* done) {
   *done = 0;
@@ -571,7 +599,7 @@ __host__ __device__ inline double bounded_next(double x, double h, double hnoise
     slo = fmax(slo, lo);
     shi = fmin(shi, hi);
     if (!(slo < shi)) { slo = lo; shi = hi; }
-    const double down = tangent_rest_bound(x, h, dpsi_x, y, ry);
+    const double down = tangent_rest_bound(x, h, dpsi_x, y, sry);
     // the models agree when the lower bound meets the upper one to within the
     // zero's uncertainty from the rounding of h; then slo == shi
     const double tol = hnoise / (1.0 - dpsi_x);
@@ -596,6 +624,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
   const double sg = (double)side;
   const double di = P.ds[i];
   const double rci = 1.0 / P.ch[i];
+  const double src = 1.0 / sqrt(P.ch[i]);   // sqrt(rci)
   // x-space bracket
   double xlo = (side > 0) ? lo : -hi;
   double xhi = (side > 0) ? hi : -lo;
@@ -609,8 +638,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     // that two-by-two model (the corner block of A_i^{-1}) bounds the wanted
     // zero from below.  Across the decades between it and the Gershgorin bound
     // the iteration starts from the bit-pattern midpoint.
-    const double r = sqrt(c0 * c0 + 4.0 * rci);
-    const double x2 = (c0 >= 0.0) ? 0.5 * (c0 + r) : 2.0 * rci / (r - c0);
+    const double x2 = pos_root(c0, src);
     xlo = fmax(xlo, x2 * (1.0 - 4.0 * EPS));
     if (xlo > 0.0 && xhi > 16.0 * xlo) {
       x = bits_mid(xlo, xhi);
@@ -621,12 +649,13 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
   // inside the bracket is the better start
   const double x_est = sg * nu_est;
   if (x_est > xlo && x_est < xhi) x = x_est;
-  // residue of psi_x at y: c_jn / (zeta_i^2 e_jn^2) for the neighbouring pole
-  // jn, or 1/zeta_i^2 for the pole at 0 when no pole lies right of it
-  double ry = rci;
+  // square root of the residue of psi_x at y: c_jn / (zeta_i^2 e_jn^2) for the
+  // neighbouring pole jn, or 1/zeta_i^2 for the pole at 0 when no pole lies
+  // right of it
+  double sry = src;
   if (y > 0.0) {
     const double e = pdiff<KIND>(P.ds[i - side], di);
-    ry = P.ch[i - side] * rci / (e * e);
+    sry = sqrt(P.ch[i - side]) * src / fabs(e);
   }
   double slo = xlo, shi = xhi;
   int it = 0;
@@ -646,7 +675,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     if (h == 0) break;
     const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi_x));
     int done = 0;
-    x = bounded_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, ry, c0, xlo, xhi, it, hi_open, slo, shi, &done);
+    x = bounded_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, sry, c0, xlo, xhi, it, hi_open, slo, shi, &done);
     if (done) { ++it; break; }
   }
   if (iters) *iters = it;
@@ -822,25 +851,33 @@ __host__ __device__ inline double dpr1_from_last_pole(const Prob& P, double tau_
 //   DPR1:      q_j = u_j / ((d_j - pv) - s - mu) over all n DPR1 poles
 // The terms are all positive.
 
+// The squares are taken on g x, g the power of two at or below the distance
+// s + mu from the shift pole to lambda (kept within [2^-1000, 2^500]): the
+// entries are of the order of 1/(s + mu), whose square overflows when lambda
+// lies within about 2^-512 of that pole.  Scaling by a power of two is exact,
+// so where nothing overflows the result is that of the unscaled sum.
+
 template <int KIND, int G>
 __host__ __device__ inline double inv_norm(const Prob& P, double pv, double s, double mu, int ln) {
+  const double off = fabs(s + mu);
+  const double g = (off > 0.0) ? ldexp(1.0, ilogb(fmin(fmax(off, 0x1p-1000), 0x1p500))) : 1.0;
   double acc = 0.0;
   if constexpr (KIND == KIND_DPR1) {
 #pragma unroll 4
     for (int j = ln; j < P.nsorted; j += G) {
-      const double x = P.zs[j] * recip(((P.ds[j] - pv) - s) - mu);
+      const double x = P.zs[j] * (recip(((P.ds[j] - pv) - s) - mu) * g);
       acc = fma(x, x, acc);
     }
     acc = gsum<G>(acc);
   } else {
 #pragma unroll 4
     for (int j = ln; j < P.m; j += G) {
-      const double r = recip((pdiff<KIND>(P.ds[j], pv) - s) - mu);
+      const double r = recip((pdiff<KIND>(P.ds[j], pv) - s) - mu) * g;
       acc = fma(P.ch[j] * r, r, acc);
     }
-    acc = gsum<G>(acc) + 1.0;
+    acc = gsum<G>(acc) + g * g;
   }
-  return 1.0 / sqrt(acc);
+  return g / sqrt(acc);
 }
 
 }  // namespace ahd

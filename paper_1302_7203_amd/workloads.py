@@ -155,6 +155,21 @@ def serving_requests(count=2200, nmin=32, nmax=8192, rate=1.0, seed=SEED_BASE + 
     return out
 
 
+def wide_arrow(kind, n, rng, decades=300):
+    """Poles whose magnitudes spread log-uniformly over `decades` decades below 1
+    (signed for ARROW and DPR1, non-negative for SVD, whose poles are the squares
+    of d), shaft entries of order 1: eigenvalues lie far closer to their poles
+    than the square root of the smallest normal number."""
+    m = n if kind == KIND_DPR1 else n - 1
+    span = decades if kind != KIND_SVD else decades / 2
+    mag = 10.0 ** rng.uniform(-span, 0.0, m)
+    d = mag if kind == KIND_SVD else mag * np.where(rng.random(m) < 0.5, 1.0, -1.0)
+    d = np.sort(d)[::-1].copy()
+    z = rng.uniform(0.5, 1.5, m)
+    scalar = 0.7 if kind == KIND_DPR1 else 0.3
+    return Problem(kind, n, d, z, scalar)
+
+
 def herm_arrow(n, rng):
     """Hermitian arrowhead (Sec. 6.1): ``uniform`` poles in random order, z = r e^{i theta}
     with r ~ U(0.1, 1), theta ~ U(0, 2 pi)."""

@@ -209,3 +209,24 @@ def test_rational_passes_stay_few(case, mean_max, worst_max):
     r = emu.solve(0, pr.d, pr.z, pr.scalar, vectors=False)
     it = r["cnt"][:, 0]
     assert it.mean() <= mean_max and it.max() <= worst_max, (it.mean(), it.max())
+
+
+@pytest.mark.parametrize("kind,decades", [(0, 250), (0, 300), (1, 250), (2, 250)])
+def test_spectrum_spread_over_hundreds_of_decades(kind, decades, oracle_lib):
+    """Eigenvalues within 1e-240 of their poles: the x-space quantities are then near
+    1e240, so no square of one may be formed (bracket end, residue, norms)."""
+    pr = W.wide_arrow(kind, 160, np.random.default_rng(70 + decades + kind), decades)
+    r = emu.solve(kind, pr.d, pr.z, pr.scalar)
+    if kind == 1:
+        ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    elif kind == 2:
+        ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.sigma, ref.V
+        assert_close(r["U"], ref.U, "U")
+    else:
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    assert np.abs(lam ** 2 if kind == 2 else lam).min() < 1e-200   # SVD: the poles are d_j^2
+    assert_close(r["lam"], lam, "lambda")
+    assert_close(r["V"], vec, "V")

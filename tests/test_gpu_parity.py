@@ -434,3 +434,30 @@ def test_power_of_two_scaling_is_exact(gpu, k):
     d, z, al = _herm_case(600, 62)
     a, b = _herm(gpu, d, z, al), _herm(gpu, d * s, z * s, al * s)
     assert np.array_equal(_np(b.lam), _np(a.lam) * s) and np.array_equal(_np(b.V), _np(a.V))
+
+
+@pytest.mark.parametrize("kind", [W.KIND_ARROW, W.KIND_DPR1, W.KIND_SVD])
+def test_spectrum_spread_over_250_decades(gpu, kind, oracle_lib):
+    """Eigenvalues within 1e-240 of their poles, where a square of an x-space
+    quantity would overflow."""
+    torch, binding, dev = gpu
+    pr = W.wide_arrow(kind, 700, np.random.default_rng(80 + kind), 250)
+    d = torch.from_numpy(pr.d).to(dev)
+    z = torch.from_numpy(pr.z).to(dev)
+    if kind == W.KIND_DPR1:
+        out = binding.dpr1_eig(d, z, pr.scalar)
+        ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    elif kind == W.KIND_SVD:
+        out = binding.arrow_svd(d, z, pr.scalar)
+        ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.sigma, ref.V
+    else:
+        out = binding.arrow_eig(d, z, pr.scalar)
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    torch.cuda.synchronize(dev)
+    assert_close(_np(out.lam), lam, "lambda")
+    assert_close(_np(out.V), vec, "V")
+    if kind == W.KIND_SVD:
+        assert_close(_np(out.U), ref.U, "U")
