@@ -36,6 +36,9 @@ def _mixed(count, seed, nmin=16, nmax=300):
     inc = W.uniform_arrow(77, rng)                          # poles in increasing order
     inc.d, inc.z = inc.d[::-1].copy(), inc.z[::-1].copy()
     out.append(inc)
+    # spectra spread over 250 decades: eigenvalues within 1e-240 of their poles
+    out += [W.wide_arrow(W.KIND_ARROW, 180, rng, 250), W.wide_arrow(W.KIND_DPR1, 120, rng, 250),
+            W.wide_arrow(W.KIND_SVD, 90, rng, 250)]
     out += [W.uniform_arrow(1, rng), W.uniform_arrow(2, rng), W.dpr1(1, rng), W.svd_arrow(2, rng)]
     return out
 
