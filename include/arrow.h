@@ -67,6 +67,11 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_OPT_ROOT 7       /* root finder for the extreme eigenvalue of the inverse:
                                   0 = bisection (Algorithm 3), 1 = safeguarded rational
                                   (secular) iteration on the same function (default) */
+#define ARROW_OPT_TAU_B 8      /* K_b (eq. K2) at or below which b is taken from an FP64 pass
+                                  alone, as Algorithm 5 allows; the double-double pass (Theorem 6)
+                                  runs only above it.  0 = always double-double (default).  With a
+                                  bound of a few, eigenvalues carry about K_b times the FP64 sums'
+                                  rounding instead of double-double's: a few ulps to ~1e-14 */
 
 /* Create a handle on HIP device `device`.  *h receives the handle. */
 int arrow_create(arrow_handle_t* h, int device);

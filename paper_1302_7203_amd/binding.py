@@ -38,6 +38,7 @@ OPT_REMEDIES = 4
 OPT_LANES = 5
 OPT_TIMING = 6
 OPT_ROOT = 7
+OPT_TAU_B = 8
 ROOT_BISECT = 0
 ROOT_RATIONAL = 1
 SCHEDULE_SINGLE = 0

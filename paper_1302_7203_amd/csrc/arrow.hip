@@ -423,6 +423,7 @@ int arrow_create(arrow_handle_t* h, int device) {
   p->opt.tau_nu = 10.0;
   p->opt.tau_zero = 10.0;
   p->opt.fp64_b = 0;
+  p->opt.tau_b = 0.0;
   p->opt.remedies = 1;
   p->opt.root = ROOT_RATIONAL;
   p->lanes = 0;
@@ -471,6 +472,10 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
     case ARROW_OPT_TAU_ZERO:
       if (!(value >= 1.0)) return -3;
       h->opt.tau_zero = value;
+      return ARROW_OK;
+    case ARROW_OPT_TAU_B:
+      if (!(value >= 0.0 && value < INFINITY)) return -3;
+      h->opt.tau_b = value;
       return ARROW_OK;
     case ARROW_OPT_FP64_B:
       h->opt.fp64_b = value != 0.0;

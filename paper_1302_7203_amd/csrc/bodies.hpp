@@ -425,7 +425,18 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   }
   int i, side;
   select_shift<KIND, G>(P, k, ln, i, side);
-  const BPass bp = b_pass<KIND, G>(P, i, side, ln, opt.fp64_b);
+  // b in double-double (Theorem 6) unless FP64 is asked for, or unless the
+  // FP64 pass's K_b (eq. K2) is at most tau_b: Algorithm 5 keeps b from
+  // Algorithm 2 where its cancellation is mild.  K_b is the same in every lane
+  // of the eigenvalue, so the choice does not split them.
+  BPass bp;
+  bool dd_b = !opt.fp64_b;
+  if (opt.fp64_b || opt.tau_b > 0.0) {
+    bp = b_pass_t<KIND, G, true>(P, i, side, ln);
+    if (dd_b) dd_b = !(bp.Kb <= opt.tau_b);
+  }
+  if (dd_b) bp = b_pass_t<KIND, G, false>(P, i, side, ln);
+  const int plain_b = (opt.fp64_b || opt.tau_b > 0.0) ? 1 : 0;
   int iters = 0;
   double last[3] = {NAN, NAN, NAN};   // the rational pass's last point nu and its sums S2, S3
   const double nu = (opt.root == ROOT_RATIONAL)
@@ -444,14 +455,14 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   }
   if (ln == 0) {
     w.cnt[6 * k + 0] = iters;
-    w.cnt[6 * k + 1] = opt.fp64_b ? 0 : 1;
-    w.cnt[6 * k + 2] = ((k > 0 && k < P.m) ? 1 : 0) + (opt.fp64_b ? 1 : 0);
+    w.cnt[6 * k + 1] = dd_b ? 1 : 0;
+    w.cnt[6 * k + 2] = ((k > 0 && k < P.m) ? 1 : 0) + plain_b;
     w.pv1[k] = P.ds[i];
     w.mu1[k] = 1.0 / nu;
     w.kb1[k] = bp.Kb;
     w.nr1[k] = nr1;
     w.ip1[k] = i;
-    uint32_t fl = opt.fp64_b ? 0u : INFO_DD_B;
+    uint32_t fl = dd_b ? INFO_DD_B : 0u;
     // Theorem 6 needs K_b <= O(1/eps); flag when the double-double b cannot hold it
     if (bp.Kb * (double)(D.n + 4) * 4.930380657631324e-32 > 1e-3) fl |= INFO_KB_LARGE;
     w.fl1[k] = fl;

@@ -56,6 +56,8 @@ struct Options {
   int fp64_b;        // 1: b by Algorithm 2 in FP64 only (negative control)
   int remedies;      // 0: skip the K_nu and near-zero remedies
   int root;          // RootMethod for the extreme eigenvalue of the inverse
+  double tau_b;      // > 0: b from an FP64 pass alone where its K_b <= tau_b
+                     // (Algorithm 5's test), else the double-double pass; 0: always
 };
 
 // Read-only view of one problem after normalisation (sorted order).

@@ -32,7 +32,8 @@ def _load():
         L = ctypes.CDLL(build())
         P = ctypes.c_void_p
         L.emu_solve.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_double, P, P, P, P, P, P,
-                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
+                                ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
+                                ctypes.c_double]
         L.emu_solve.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -42,7 +43,7 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1):
+def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1, tau_b=0.0):
     """kind 0 arrowhead, 1 DPR1, 2 SVD, 3 Hermitian arrowhead (complex z; complex V).
     Returns dict of numpy arrays (V[:, k] = k-th vector)."""
     d = np.ascontiguousarray(d, dtype=np.float64)
@@ -55,6 +56,6 @@ def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0
     info = np.empty(n, dtype=np.uint32)
     cnt = np.empty((n, 6), dtype=np.int32)
     _load().emu_solve(kind, n, _p(d), _p(z), float(scalar), _p(lam), _p(Vb), _p(Ub), _p(sh), _p(mu), _p(info),
-                      tau_nu, tau_zero, fp64_b, remedies, _p(kb), root, _p(cnt))
+                      tau_nu, tau_zero, fp64_b, remedies, _p(kb), root, _p(cnt), tau_b)
     return {"lam": lam, "V": None if Vb is None else Vb.T, "U": None if Ub is None else Ub.T,
             "shift": sh, "mu": mu, "info": info, "kb": kb, "cnt": cnt}

@@ -93,7 +93,8 @@ static void run(ProbDesc D, const Options& opt, double* U) {
 
 extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, double scalar, double* lam,
                          double* V, double* U, double* shift, double* mu, uint32_t* info, double tau_nu,
-                         double tau_zero, int fp64_b, int remedies, double* kb, int root, int32_t* cnt) {
+                         double tau_zero, int fp64_b, int remedies, double* kb, int root, int32_t* cnt,
+                         double tau_b) {
   std::vector<double> ws(ws_doubles(n), 0.0);
   ProbDesc D{};
   D.kind = kind;
@@ -111,7 +112,7 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   D.mu = mu;
   D.info = info;
   D.ws = ws.data();
-  Options opt{tau_nu, tau_zero, fp64_b, remedies, root};
+  Options opt{tau_nu, tau_zero, fp64_b, remedies, root, tau_b};
   if (kind == KIND_ARROW) run<KIND_ARROW>(D, opt, U);
   else if (kind == KIND_DPR1) run<KIND_DPR1>(D, opt, U);
   else if (kind == KIND_HERM) run<KIND_HERM>(D, opt, U);

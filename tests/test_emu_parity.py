@@ -230,3 +230,29 @@ def test_spectrum_spread_over_hundreds_of_decades(kind, decades, oracle_lib):
     assert np.abs(lam ** 2 if kind == 2 else lam).min() < 1e-200   # SVD: the poles are d_j^2
     assert_close(r["lam"], lam, "lambda")
     assert_close(r["V"], vec, "V")
+
+
+@pytest.mark.parametrize("kind,name", [(0, "graded_1024"), (0, "uniform_512"), (1, "dpr1_600"), (2, "svd_500")])
+def test_fp64_b_where_kb_is_small(kind, name, oracle_lib):
+    """Algorithm 5's choice: b from the FP64 pass where its K_b is at most tau_b, the
+    double-double pass elsewhere.  Still within the bar, and on graded poles most
+    eigenvalues skip the double-double pass."""
+    rng = np.random.default_rng(90 + kind)
+    pr = {"graded_1024": lambda: W.graded_arrow(1024, rng), "uniform_512": W.single_uniform_512,
+          "dpr1_600": lambda: W.dpr1(600, rng), "svd_500": lambda: W.svd_arrow(500, rng)}[name]()
+    r = emu.solve(kind, pr.d, pr.z, pr.scalar, tau_b=4.0)
+    if kind == 1:
+        ref = oracle.dpr1_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    elif kind == 2:
+        ref = oracle.arrow_svd(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.sigma, ref.V
+    else:
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+        lam, vec = ref.lam, ref.vec
+    assert_close(r["lam"], lam, "lambda")
+    assert_close(r["V"], vec, "V")
+    dd = r["cnt"][:, 1]                    # double-double b passes per eigenvalue
+    assert np.all(dd[r["kb"] > 4.0] >= 1)   # large K_b: double-double
+    if name == "graded_1024":
+        assert dd.mean() < 0.2

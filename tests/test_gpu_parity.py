@@ -461,3 +461,23 @@ def test_spectrum_spread_over_250_decades(gpu, kind, oracle_lib):
     assert_close(_np(out.V), vec, "V")
     if kind == W.KIND_SVD:
         assert_close(_np(out.U), ref.U, "U")
+
+
+def test_fp64_b_where_kb_is_small(gpu, oracle_lib):
+    """ARROW_OPT_TAU_B = 4: b from the FP64 pass where K_b <= 4 (Algorithm 5), the
+    double-double pass elsewhere; same bar against the oracle.  Bad values are refused."""
+    torch, binding, dev = gpu
+    cases = [(W.single_graded_4096(), np.arange(0, 4096, 16)), (W.single_uniform_512(), None)]
+    binding.set_option(binding.OPT_TAU_B, 4.0)
+    try:
+        for pr, ks in cases:
+            out = _arrow(gpu, pr.d, pr.z, pr.scalar)
+            ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
+            kk = np.arange(pr.n) if ks is None else ks
+            assert_close(_np(out.lam)[kk], ref.lam, "lambda")
+            assert_close(_np(out.V)[:, kk], ref.vec, "V")
+        for bad in (-1.0, float("inf"), float("nan")):
+            with pytest.raises(binding.ArrowError):
+                binding.set_option(binding.OPT_TAU_B, bad)
+    finally:
+        binding.set_option(binding.OPT_TAU_B, 0.0)
