@@ -47,7 +47,8 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_INFO_DD_B 1u        /* b evaluated in double-double (Sec. 4, Theorem 6) */
 #define ARROW_INFO_REMEDY_A 2u    /* shifted to the other neighbouring pole (Remark 2(a)) */
 #define ARROW_INFO_REMEDY_B 4u    /* DPR1 inverse at a shift near lambda (Remark 2(b)) */
-#define ARROW_INFO_NEAR_ZERO 8u   /* eigenvalue closest to 0 taken from A^{-1} (Remark 1) */
+#define ARROW_INFO_NEAR_ZERO 8u   /* eigenvalue closest to 0 taken from A^{-1} (Remark 1), with
+                                     f(0) summed exactly where double-double cannot resolve it */
 #define ARROW_INFO_REDUCIBLE 16u  /* dpr1_eig / arrow_svd / arrow_eig_herm: some z_j = 0 or d_i = d_j
                                      (Sec. 1): not solved, outputs NaN (arrow_eig deflates instead) */
 #define ARROW_INFO_NONFINITE 32u  /* non-finite input: not solved, outputs NaN */
@@ -56,6 +57,13 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_INFO_BAD_INPUT 256u /* arrow_svd: some d_j = 0: not solved, outputs NaN */
 #define ARROW_INFO_POLE_SHIFT 512u /* dpr1_eig: smallest eigenvalue measured from the pole d_n */
 #define ARROW_INFO_DEFLATED 1024u  /* arrow_eig: eigenpair deflated from a reducible matrix (Sec. 1) */
+#define ARROW_INFO_F0_UNRESOLVED 2048u /* Remark 1: the Pick function at 0 is 0 as far as an exact sum of
+                                          its terms' FP64 quotient digits reaches (down to 2^-1074);
+                                          lambda carries that absolute uncertainty */
+
+/* largest order n that arrow_eig, arrow_eig_herm, dpr1_eig and arrow_svd accept (2^25; they
+ * return -2 above it): one solve launches up to 64 lanes per eigenvalue, n * 64 <= 2^31 */
+#define ARROW_N_MAX 33554432
 
 /* options for arrow_set_option */
 #define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 10) */
@@ -85,8 +93,9 @@ int arrow_set_stream(arrow_handle_t h, void* hip_stream);
 /* Set one ARROW_OPT_* option.  Returns -2 for an unknown option, -3 for a bad value. */
 int arrow_set_option(arrow_handle_t h, int option, double value);
 
-/* Device workspace (bytes) one problem of order n needs; the handle grows
- * its own workspace on demand (allocation synchronises its stream). */
+/* Device workspace (bytes) one problem of order n needs; 0 for an order outside
+ * 1..ARROW_N_MAX.  The handle grows its own workspace on demand (allocation
+ * synchronises its stream). */
 size_t arrow_workspace_size(int64_t n);
 
 /*
@@ -225,7 +234,10 @@ size_t arrow_batch_workspace_size(int64_t count, const arrow_desc_t* descs);
  * may be null when no problem asks for info).  workspace: device memory of at
  * least arrow_batch_workspace_size bytes owned by the caller, or null to let
  * the plan allocate (and free) its own.  The plan records the handle's options
- * and stream; the descriptor tables are copied to the device on that stream.
+ * (ARROW_OPT_*) and lanes table as they are at creation: later
+ * arrow_set_option calls change neither its eager nor its graph runs.  Each
+ * arrow_batch_run launches on the handle's stream as set at that call; the
+ * descriptor tables are copied to the device on the handle's stream.
  * Invalid descriptors fail with -3.
  */
 int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* descs, const double* in_pool,

@@ -37,10 +37,21 @@
  * stops and the remaining width is reported in relerr[].  Bisection halves
  * the set of binary128 numbers between the bracket ends (for brackets of one
  * sign this is the midpoint of their bit patterns), so it needs at most ~130
- * steps whatever the dynamic range.  A zero that lies much closer to 0 than
- * to its pole is refined once more in the unshifted variable.  Results are
- * rounded to FP64 once, at the end; lam/lam_lo etc. return the binary128
- * value as an unevaluated hi+lo pair of doubles.
+ * steps whatever the dynamic range.
+ *
+ * A zero in the interval that contains the origin may lie far closer to 0
+ * than to any pole (Sec. 3, Remark 1 and the exceptions of condition (C1) in
+ * Theorem 2); there the shifted variable cannot resolve it relative to itself.
+ * Near the origin the secular function is therefore written as
+ *     g(l) = C0 - l * S(l),   C0 = g(0) = K - sum_j c_j / d_j,
+ *     S(l) = s0 + sum_j c_j / (d_j (d_j - l))     (every term positive there),
+ * with K = alpha, s0 = 1 (arrowhead) or K = -1, s0 = 0 (DPR1).  C0 is summed
+ * exactly: each quotient is expanded into binary128 digits with exact
+ * remainders, the digits go into an exact floating-point expansion, and more
+ * digits are taken until the dropped tail is below 2^-116 of |C0|.  A zero
+ * that cannot be resolved this way is reported through relerr[], never hidden.
+ * Results are rounded to FP64 once, at the end; lam/lam_lo etc. return the
+ * binary128 value as an unevaluated hi+lo pair of doubles.
  *
  * No code here follows the printed listings of the paper.
  */
@@ -63,6 +74,14 @@ typedef struct {
   const R *d;     /* poles, strictly decreasing */
   const R *c;     /* weights > 0: zeta_j^2 (arrowhead) or rho*u_j^2 (DPR1) */
   R alpha;        /* arrowhead corner; unused for DPR1 */
+  /* The same function given exactly, for its value at the origin:
+   *   K = sum of k0[0..nk0-1],  sum_j c_j/(d_j - l) = sum_t tn[t]/(tp[t] - l)
+   * with every k0, tn and tp an exact binary128 number (the weights above
+   * may be roundings of these sums). */
+  int64_t nk0;
+  const R *k0;
+  int64_t nt;
+  const R *tn, *tp;
 } secular_t;
 
 typedef struct {
@@ -99,8 +118,8 @@ static R g_shifted(const secular_t *s, int64_t p, R tau, R *err) {
   return base - sum;
 }
 
-/* Same function evaluated directly at l (used only when l is far from every
- * pole compared with |l|, i.e. for a zero close to the origin). */
+/* Same function evaluated directly at l (the merge count of deflated values
+ * uses its sign). */
 static R g_plain(const secular_t *s, R l, R *err) {
   R sum = 0, mag = 0;
   for (int64_t j = 0; j < s->m; ++j) {
@@ -129,6 +148,140 @@ static R gprime_abs(const secular_t *s, int64_t p, R tau) {
     sum += s->c[j] / (den * den);
   }
   return sum;
+}
+
+/* ---- exact arithmetic for the value at the origin ----------------------
+ * Error-free transformations in binary128: TwoSum (Knuth), FastTwoSum
+ * (Dekker, |a| >= |b|), the product by Veltkamp's splitting (2^57 + 1 for a
+ * 113-bit significand) and Dekker's algorithm; expansions (sums of
+ * non-overlapping components, smallest first) grown one component at a time
+ * with zero elimination and compressed as in Shewchuk (1997), "Adaptive
+ * precision floating-point arithmetic and fast robust geometric predicates". */
+static void q_two_sum(R a, R b, R *s, R *e) {
+  R x = a + b, bv = x - a, av = x - bv;
+  *s = x;
+  *e = (a - av) + (b - bv);
+}
+
+static void q_fast_two_sum(R a, R b, R *s, R *e) {
+  R x = a + b;
+  *s = x;
+  *e = b - (x - a);
+}
+
+static void q_split(R a, R *hi, R *lo) {
+  const R c = 144115188075855873.0Q * a;   /* (2^57 + 1) a */
+  R big = c - a;
+  *hi = c - big;
+  *lo = a - *hi;
+}
+
+static void q_two_prod(R a, R b, R *p, R *e) {
+  R x = a * b, ah, al, bh, bl;
+  q_split(a, &ah, &al);
+  q_split(b, &bh, &bl);
+  *p = x;
+  *e = al * bl - (((x - ah * bh) - al * bh) - ah * bl);
+}
+
+typedef struct { R *v; int64_t len, cap; int oom; } expan_t;
+
+static void ex_add(expan_t *x, R b) {
+  if (b == 0 || x->oom) return;
+  if (x->len + 1 > x->cap) {
+    int64_t cap = x->cap ? 2 * x->cap : 64;
+    R *v = (R *)realloc(x->v, (size_t)cap * sizeof *v);
+    if (!v) { x->oom = 1; return; }
+    x->v = v;
+    x->cap = cap;
+  }
+  R q = b;
+  int64_t out = 0;
+  for (int64_t i = 0; i < x->len; ++i) {
+    R sum, h;
+    q_two_sum(q, x->v[i], &sum, &h);
+    q = sum;
+    if (h != 0) x->v[out++] = h;
+  }
+  x->v[out++] = q;
+  x->len = out;
+}
+
+/* In place; afterwards the largest component is within a relative 2^-112 of
+ * the expansion's value. */
+static void ex_compress(expan_t *x) {
+  int64_t m = x->len;
+  if (m < 2) return;
+  R *e = x->v;
+  R q = e[m - 1];
+  int64_t bottom = m - 1;
+  for (int64_t i = m - 2; i >= 0; --i) {
+    R sum, low;
+    q_fast_two_sum(q, e[i], &sum, &low);
+    if (low != 0) { e[bottom--] = sum; q = low; }
+    else q = sum;
+  }
+  e[bottom] = q;
+  int64_t top = 0;
+  for (int64_t i = bottom + 1; i < m; ++i) {
+    R sum, low;
+    q_fast_two_sum(e[i], q, &sum, &low);
+    if (low != 0) e[top++] = low;
+    q = sum;
+  }
+  e[top++] = q;
+  x->len = top;
+}
+
+/* C0 = g(0) = K - sum_t tn[t]/tp[t], with *e0 a bound on |*c0 - C0|.
+ * Quotient digits: r <- tn, then repeatedly q = fl(r/tp), r <- r - q tp,
+ * where the new remainder is exact (Sterbenz for r - fl(q tp), then the exact
+ * product error; the remainder of a rounded quotient is representable).
+ * Returns 0 when C0 is resolved to a relative 2^-110 (or exactly), 1 when the
+ * digit budget ran out first, -100 without memory. */
+static int origin_constant(const secular_t *s, R *c0, R *e0) {
+  const int64_t nt = s->nt;
+  R *r = (R *)malloc((size_t)(nt > 0 ? nt : 1) * sizeof *r);
+  expan_t x = { NULL, 0, 0, 0 };
+  if (!r) return -100;
+  for (int64_t i = 0; i < s->nk0; ++i) ex_add(&x, s->k0[i]);
+  for (int64_t t = 0; t < nt; ++t) r[t] = s->tn[t];
+  int rc = 1;
+  *c0 = 0;
+  *e0 = 0;
+  for (int level = 0; level < 24; ++level) {
+    R tail = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+      if (r[t] == 0) continue;
+      R q = r[t] / s->tp[t], p, pe;
+      q_two_prod(q, s->tp[t], &p, &pe);
+      r[t] = (r[t] - p) - pe;
+      ex_add(&x, -q);
+      tail += fabsq(r[t] / s->tp[t]);
+      if (x.len > 256) ex_compress(&x);
+    }
+    if (x.oom) { rc = -100; break; }
+    ex_compress(&x);
+    R approx = x.len ? x.v[x.len - 1] : 0;
+    tail *= 1 + (R)(nt + 4) * 4 * U113;          /* the rounding of the tail's own sum */
+    *c0 = approx;
+    *e0 = tail + fabsq(approx) * 4 * U113;
+    if (tail == 0 || fabsq(approx) > tail * 8.307674973655724e34Q /* 2^116 */) { rc = 0; break; }
+  }
+  free(x.v);
+  free(r);
+  return rc;
+}
+
+/* g(l) = C0 - l S(l), for |l| well below every |d_j| (every term of S is then
+ * positive, so S carries a relative error of a few units times m). */
+static R g_origin(const secular_t *s, R c0, R e0, R l, R *err, R *S_out) {
+  R S = (s->kind == KIND_ARROW) ? 1 : 0;
+  for (int64_t j = 0; j < s->m; ++j) S += s->c[j] / (s->d[j] * (s->d[j] - l));
+  R lS = l * S;
+  *err = e0 + fabsq(lS) * (R)(s->m + 16) * 4 * U113;
+  *S_out = S;
+  return c0 - lS;
 }
 
 /* Midpoint of two non-negative binary128 numbers in the ordering of their
@@ -191,40 +344,67 @@ static void solve_root(const secular_t *s, int64_t k, R upper, R lower, root_t *
   }
   R lam = s->d[p] + tau;
 
-  /* A zero much closer to the origin than to its pole: refine it in the
-   * unshifted variable so that it is also accurate relative to itself. */
-  if (fabsq(lam) < fabsq(tau) * 1e-6Q) {
-    R a = s->d[p] + sgn * lo, b = s->d[p] + sgn * hi;
-    R llo = a < b ? a : b, lhi = a < b ? b : a;
-    /* widen by the rounding of d_p + tau */
-    R pad = fabsq(s->d[p]) * 4 * U113 + fabsq(tau) * 4 * U113;
-    llo -= pad; lhi += pad;
-    int und2 = 0;
-    R l = llo + (lhi - llo) / 2;
-    for (int it = 0; it < 800; ++it) {
-      l = llo + (lhi - llo) / 2;
-      R w = lhi - llo;
-      if (w <= fabsq(l) * 1e-28Q || !(l > llo && l < lhi)) break;
-      R err, g = g_plain(s, l, &err);
-      if (fabsq(g) <= err) { und2 = 1; break; }
-      if (g > 0) llo = l; else lhi = l;
+  /* The interval that contains the origin: find out whether the zero lies in
+   * the window |l| <= delta, delta = min_j |d_j| / 256, and if so locate it
+   * in the origin form g = C0 - l S(l), relative to itself.  Outside the
+   * window |tau| <= 257 |lam|, so the shifted location is accurate enough. */
+  R lo_end, hi_end, pmin;
+  int lo_bound = 0, hi_bound = 0;     /* the end is a bound on the spectrum, not a pole */
+  if (k == 0) { lo_end = s->d[0]; hi_end = upper; hi_bound = 1; pmin = -s->d[0]; }
+  else if (s->kind == KIND_ARROW && k == m) { lo_end = lower; hi_end = s->d[m - 1]; lo_bound = 1; pmin = s->d[m - 1]; }
+  else { lo_end = s->d[k]; hi_end = s->d[k - 1]; pmin = fminq(-s->d[k], s->d[k - 1]); }
+  int near_zero = 0;
+  if (lo_end < 0 && hi_end > 0) {
+    R delta = pmin / 256, c0, e0;
+    R wlo = fmaxq(lo_end, -delta), whi = fminq(hi_end, delta);
+    int crc = origin_constant(s, &c0, &e0);
+    if (crc == -100) { rel = 1; }
+    else {
+      R err, S, g;
+      int in_lo = 1, in_hi = 1;                 /* zero >= wlo, zero <= whi */
+      if (!(lo_bound && wlo == lo_end)) { g = g_origin(s, c0, e0, wlo, &err, &S); in_lo = g > err; }
+      if (!(hi_bound && whi == hi_end)) { g = g_origin(s, c0, e0, whi, &err, &S); in_hi = -g > err; }
+      if (in_lo && in_hi) {
+        near_zero = 1;
+        R l, rel2;
+        if (c0 == 0 && e0 == 0) {               /* C0 exactly 0: the zero is the origin */
+          l = 0; rel2 = 0;
+        } else if (fabsq(c0) <= e0) {           /* C0 not resolved: report, do not guess */
+          (void)g_origin(s, c0, e0, 0, &err, &S);
+          l = c0 / S; rel2 = 1;
+        } else {
+          /* g(0) = C0 fixes the side; bisect the magnitude t of l = sg t */
+          int sg = c0 > 0 ? +1 : -1;
+          R lo2 = 0, hi2 = sg > 0 ? whi : -wlo;
+          int und2 = 0;
+          R t2 = hi2;
+          for (int it = 0; it < 600; ++it) {
+            if (hi2 - lo2 <= hi2 * 1e-32Q) break;
+            t2 = bits_mid(lo2, hi2);
+            if (!(t2 > lo2 && t2 < hi2)) break;
+            g = g_origin(s, c0, e0, sg * t2, &err, &S);
+            if (fabsq(g) <= err) { und2 = 1; break; }
+            int farther = (sg > 0) ? (g > 0) : (g < 0);
+            if (farther) lo2 = t2; else hi2 = t2;
+          }
+          if (und2) {
+            /* |g'| = s0 + sum c_j/(d_j - l)^2 >= S/2 inside the window */
+            (void)g_origin(s, c0, e0, sg * t2, &err, &S);
+            rel2 = 2 * err / (S * t2);
+          } else {
+            t2 = lo2 + (hi2 - lo2) / 2;
+            rel2 = (hi2 - lo2) / t2;
+          }
+          l = sg * t2;
+        }
+        lam = l;
+        tau = l - s->d[p];
+        rel = rel2;
+      }
     }
-    l = und2 ? l : llo + (lhi - llo) / 2;
-    R rel2;
-    if (und2) {
-      R err;
-      (void)g_plain(s, l, &err);
-      R gp = gprime_abs(s, p, l - s->d[p]);
-      rel2 = (l != 0) ? err / gp / fabsq(l) : 1;
-    } else {
-      rel2 = (l != 0) ? (lhi - llo) / fabsq(l) : 1;
-    }
-    lam = l;
-    tau = l - s->d[p];
-    if (rel2 > rel) rel = rel2;
-  } else if (fabsq(lam) < fabsq(tau) && lam != 0) {
-    rel = rel * fabsq(tau) / fabsq(lam);   /* width seen relative to lam */
   }
+  if (!near_zero && fabsq(lam) < fabsq(tau) && lam != 0)
+    rel = rel * fabsq(tau) / fabsq(lam);   /* width seen relative to lam */
   out->p = p;
   out->tau = tau;
   out->lam = lam;
@@ -352,7 +532,16 @@ static int arrow_eig_reducible(int64_t n, const double *d, const double *z, doub
   }
   if ((R)alpha + zsum > up) up = (R)alpha + zsum;
   if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
-  secular_t sec = { KIND_ARROW, mr, dq, cq, (R)alpha };
+  /* exact terms: every nonzero z_row^2 over its pole */
+  int64_t nz = 0;
+  for (int64_t j = 0; j < m; ++j) nz += z[j] != 0;
+  R *tn = (R *)malloc((size_t)(nz > 0 ? nz : 1) * sizeof *tn);
+  R *tp = (R *)malloc((size_t)(nz > 0 ? nz : 1) * sizeof *tp);
+  if (!tn || !tp) { free(tn); free(tp); free(dq); free(cq); free(rep); free(it); free(src); return -100; }
+  for (int64_t j = 0, t = 0; j < m; ++j)
+    if (z[j] != 0) { tn[t] = (R)z[j] * (R)z[j]; tp[t] = (R)d[j]; ++t; }
+  R k0 = (R)alpha;
+  secular_t sec = { KIND_ARROW, mr, dq, cq, (R)alpha, 1, &k0, nz, tn, tp };
   /* Merge: both lists descend; on equal double values the rest's eigenvalue
    * comes first.  Item s goes to column s + c_s, c_s = number of roots whose
    * double rounding is >= delta_s = number of roots above x, the midpoint of
@@ -361,7 +550,7 @@ static int arrow_eig_reducible(int64_t n, const double *d, const double *z, doub
    * decreases on each interval).  A sign lost in rounding error is settled by
    * solving that root.  The rest's roots fill the other columns in order. */
   int64_t *cs = (int64_t *)malloc((size_t)(nd > 0 ? nd : 1) * sizeof *cs);
-  if (!cs) { free(dq); free(cq); free(rep); free(it); free(src); return -100; }
+  if (!cs) { free(dq); free(cq); free(rep); free(it); free(src); free(tn); free(tp); return -100; }
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t b = 0; b < nd; ++b) {
     double v = it[b].value;
@@ -456,7 +645,7 @@ static int arrow_eig_reducible(int64_t n, const double *d, const double *z, doub
       }
     }
   }
-  free(dq); free(cq); free(rep); free(it); free(src);
+  free(dq); free(cq); free(rep); free(it); free(src); free(tn); free(tp);
   return fail ? -100 : 0;
 }
 
@@ -525,7 +714,8 @@ int oracle_arrow_eig(int64_t n, const double *d, const double *z, double alpha,
   /* Gershgorin discs bound the spectrum. */
   if ((R)alpha + zsum > up) up = (R)alpha + zsum;
   if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
-  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha };
+  R k0 = (R)alpha;
+  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha, 1, &k0, m, cq, dq };
 
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -590,15 +780,21 @@ int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
   if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
   int dup = sort_desc(m, d, order);
   if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R *tn = (R *)malloc((size_t)(2 * m) * sizeof *tn);
+  R *tp = (R *)malloc((size_t)(2 * m) * sizeof *tp);
+  if (!tn || !tp) { free(order); free(dq); free(cq); free(tn); free(tp); return -100; }
   R csum = 0;
   for (int64_t j = 0; j < m; ++j) {
     dq[j] = (R)d[order[j]];
     R uu = (R)u[order[j]];
     cq[j] = (R)rho * (uu * uu);
     csum += cq[j];
+    q_two_prod((R)rho, uu * uu, &tn[2 * j], &tn[2 * j + 1]);   /* rho u_j^2 exactly */
+    tp[2 * j] = tp[2 * j + 1] = dq[j];
   }
   R up = dq[0] + csum;      /* l_1 <= d_1 + rho ||u||^2 */
-  secular_t s = { KIND_DPR1, m, dq, cq, 0 };
+  R k0 = -1;
+  secular_t s = { KIND_DPR1, m, dq, cq, 0, 1, &k0, 2 * m, tn, tp };
 
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -624,7 +820,7 @@ int oracle_dpr1_eig(int64_t n, const double *d, const double *u, double rho,
       }
     }
   }
-  free(order); free(dq); free(cq);
+  free(order); free(dq); free(cq); free(tn); free(tp);
   return 0;
 }
 
@@ -669,11 +865,17 @@ int oracle_herm_eig(int64_t n, const double *d, const double *zr, const double *
   if (!order || !dq || !cq) { free(order); free(dq); free(cq); return -100; }
   int dup = sort_desc(m, d, order);
   if (dup) { free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R *tn = (R *)malloc((size_t)(2 * m) * sizeof *tn);
+  R *tp = (R *)malloc((size_t)(2 * m) * sizeof *tp);
+  if (!tn || !tp) { free(order); free(dq); free(cq); free(tn); free(tp); return -100; }
   R zsum = 0, up = (R)alpha, lowb = (R)alpha;
   for (int64_t j = 0; j < m; ++j) {
     int64_t o = order[j];
     dq[j] = (R)d[o];
     cq[j] = (R)zr[o] * (R)zr[o] + (R)zi[o] * (R)zi[o];
+    tn[2 * j] = (R)zr[o] * (R)zr[o];           /* each square exact */
+    tn[2 * j + 1] = (R)zi[o] * (R)zi[o];
+    tp[2 * j] = tp[2 * j + 1] = dq[j];
     R az = sqrtq(cq[j]);
     zsum += az;
     if (dq[j] + az > up) up = dq[j] + az;
@@ -681,7 +883,8 @@ int oracle_herm_eig(int64_t n, const double *d, const double *zr, const double *
   }
   if ((R)alpha + zsum > up) up = (R)alpha + zsum;
   if ((R)alpha - zsum < lowb) lowb = (R)alpha - zsum;
-  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha };
+  R k0 = (R)alpha;
+  secular_t s = { KIND_ARROW, m, dq, cq, (R)alpha, 1, &k0, 2 * m, tn, tp };
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t i = 0; i < nk; ++i) {
@@ -709,7 +912,7 @@ int oracle_herm_eig(int64_t n, const double *d, const double *zr, const double *
       col[2 * m + 1] = 0.0;
     }
   }
-  free(order); free(dq); free(cq);
+  free(order); free(dq); free(cq); free(tn); free(tp);
   return 0;
 }
 
@@ -805,15 +1008,23 @@ int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
   for (int64_t j = 0; j < m; ++j) key[j] = d[j] < 0 ? -d[j] : d[j];
   int dup = sort_desc(m, key, order);
   if (dup) { free(key); free(order); free(dq); free(cq); return dup < 0 ? dup : 1; }
+  R *k0 = (R *)malloc((size_t)(m + 1) * sizeof *k0);
+  R *tn = (R *)malloc((size_t)(2 * m) * sizeof *tn);
+  R *tp = (R *)malloc((size_t)(2 * m) * sizeof *tp);
+  if (!k0 || !tn || !tp) { free(key); free(order); free(dq); free(cq); free(k0); free(tn); free(tp); return -100; }
   /* B^T B = [D^2, D z; z^T D, alpha^2 + z^T z] */
   R corner = (R)alpha * (R)alpha, zsum = 0, up = -1e4000Q, lowb = 1e4000Q;
   for (int64_t j = 0; j < m; ++j) corner += (R)z[j] * (R)z[j];
+  k0[0] = (R)alpha * (R)alpha;                  /* the corner's parts, each exact */
+  for (int64_t j = 0; j < m; ++j) k0[j + 1] = (R)z[j] * (R)z[j];
   for (int64_t j = 0; j < m; ++j) {
     R dj = (R)d[order[j]], zj = (R)z[order[j]];
     dq[j] = dj * dj;
     R sh = dj * zj;
     cq[j] = sh * sh;
     zsum += fabsq(sh);
+    q_two_prod(sh, sh, &tn[2 * j], &tn[2 * j + 1]);   /* (d_j zeta_j)^2 exactly */
+    tp[2 * j] = tp[2 * j + 1] = dq[j];
   }
   for (int64_t j = 0; j < m; ++j) {
     R r = sqrtq(cq[j]);
@@ -822,7 +1033,7 @@ int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
   }
   if (corner + zsum > up) up = corner + zsum;
   if (corner - zsum < lowb) lowb = corner - zsum;
-  secular_t s = { KIND_ARROW, m, dq, cq, corner };
+  secular_t s = { KIND_ARROW, m, dq, cq, corner, m + 1, k0, 2 * m, tn, tp };
 
   set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -855,7 +1066,7 @@ int oracle_arrow_svd(int64_t n, const double *d, const double *z, double alpha,
       if (uc) uc[m] = (double)((R)alpha * vn / sg);   /* u_n = alpha v_n / sigma */
     }
   }
-  free(key); free(order); free(dq); free(cq);
+  free(key); free(order); free(dq); free(cq); free(k0); free(tn); free(tp);
   return 0;
 }
 

@@ -31,11 +31,16 @@
 
 using namespace ahd;
 
+// orders the single-problem calls accept: the root and check launches index
+// n * G <= 2^31 lanes (G <= 64) in 64-bit arithmetic
+static bool order_ok(int64_t n) { return n >= 1 && n <= ARROW_N_MAX; }
+
 static_assert(ARROW_INFO_DD_B == INFO_DD_B && ARROW_INFO_REMEDY_A == INFO_REMEDY_A &&
                   ARROW_INFO_REMEDY_B == INFO_REMEDY_B && ARROW_INFO_NEAR_ZERO == INFO_NEAR_ZERO &&
                   ARROW_INFO_REDUCIBLE == INFO_REDUCIBLE && ARROW_INFO_NONFINITE == INFO_NONFINITE &&
                   ARROW_INFO_KB_LARGE == INFO_KB_LARGE && ARROW_INFO_BAD_INPUT == INFO_BAD_INPUT &&
-                  ARROW_INFO_POLE_SHIFT == INFO_POLE_SHIFT && ARROW_INFO_DEFLATED == INFO_DEFLATED,
+                  ARROW_INFO_POLE_SHIFT == INFO_POLE_SHIFT && ARROW_INFO_DEFLATED == INFO_DEFLATED &&
+                  ARROW_INFO_F0_UNRESOLVED == INFO_F0_UNRESOLVED,
               "info bits");
 
 
@@ -195,22 +200,22 @@ template <int KIND, int G, bool STAGE>
 __global__ __launch_bounds__(ROOT_BLOCK) void k_root(ProbDesc D, Options opt) {
   extern __shared__ double lds[];
   if constexpr (STAGE) stage_hot(D, lds);
-  const int gid = blockIdx.x * ROOT_BLOCK + threadIdx.x;
-  const int k = gid / G;
+  const int64_t gid = (int64_t)blockIdx.x * ROOT_BLOCK + threadIdx.x;
+  const int k = (int)(gid / G);
   if (k >= D.n) return;
-  if constexpr (STAGE) root_body<KIND, G, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
-  else root_body<KIND, G>(D, opt, k, gid % G);
+  if constexpr (STAGE) root_body<KIND, G, true>(D, opt, k, (int)(gid % G), lds, lds + sorted_count(D));
+  else root_body<KIND, G>(D, opt, k, (int)(gid % G));
 }
 
 template <int KIND, int G, bool STAGE>
 __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
   extern __shared__ double lds[];
   if constexpr (STAGE) stage_hot(D, lds);
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;   // blocks of ROOT_BLOCK, or CHECK_LANE_BLOCK
-  const int k = gid / G;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // blocks of ROOT_BLOCK, or CHECK_LANE_BLOCK
+  const int k = (int)(gid / G);
   if (k >= D.n) return;
-  if constexpr (STAGE) check_body<KIND, G, true, true>(D, opt, k, gid % G, lds, lds + sorted_count(D));
-  else check_body<KIND, G, false, true>(D, opt, k, gid % G);
+  if constexpr (STAGE) check_body<KIND, G, true, true>(D, opt, k, (int)(gid % G), lds, lds + sorted_count(D));
+  else check_body<KIND, G, false, true>(D, opt, k, (int)(gid % G));
 }
 
 // The eigenvalues k_check deferred (Remarks 1 and 2, the DPR1 re-measure),
@@ -508,7 +513,7 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
   }
 }
 
-size_t arrow_workspace_size(int64_t n) { return n < 1 ? 0 : ws_doubles(n) * sizeof(double); }
+size_t arrow_workspace_size(int64_t n) { return order_ok(n) ? ws_doubles(n) * sizeof(double) : 0; }
 
 int arrow_timing_of(arrow_handle_t h, int age, double* ms) {
   if (!valid(h)) return -1;
@@ -553,7 +558,7 @@ int arrow_last_counters(arrow_handle_t h, int64_t* out) {
 int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
               double* V, int64_t ldv, double* shift, double* mu, uint32_t* info) {
   if (!valid(h)) return -1;
-  if (n < 1 || n > (int64_t)1 << 28) return -2;
+  if (!order_ok(n)) return -2;
   if (n > 1 && !d) return -3;
   if (n > 1 && !z) return -4;
   if (!finite_h(alpha)) return -5;
@@ -581,7 +586,7 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
 int arrow_eig_herm(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
                    double* U, int64_t ldu, double* shift, double* mu, uint32_t* info) {
   if (!valid(h)) return -1;
-  if (n < 1 || n > (int64_t)1 << 28) return -2;
+  if (!order_ok(n)) return -2;
   if (n > 1 && !d) return -3;
   if (n > 1 && (!z || ((uintptr_t)z & 7))) return -4;
   if (!finite_h(alpha)) return -5;
@@ -610,7 +615,7 @@ int arrow_eig_herm(arrow_handle_t h, int64_t n, const double* d, const double* z
 int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, double rho, double* lambda,
              double* Q, int64_t ldq, uint32_t* info) {
   if (!valid(h)) return -1;
-  if (n < 1 || n > (int64_t)1 << 28) return -2;
+  if (!order_ok(n)) return -2;
   if (!d) return -3;
   if (!u) return -4;
   if (!finite_h(rho) || rho == 0.0) return -5;
@@ -637,7 +642,7 @@ int dpr1_eig(arrow_handle_t h, int64_t n, const double* d, const double* u, doub
 int arrow_svd(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* sigma,
               double* U, int64_t ldu, double* V, int64_t ldv, uint32_t* info) {
   if (!valid(h)) return -1;
-  if (n < 1 || n > (int64_t)1 << 28) return -2;
+  if (!order_ok(n)) return -2;
   if (n > 1 && !d) return -3;
   if (n > 1 && !z) return -4;
   if (!finite_h(alpha)) return -5;

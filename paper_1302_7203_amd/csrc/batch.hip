@@ -188,6 +188,7 @@ struct arrow_batch_s {
   int flags;
   int32_t total_items, total_vec;
   int repair_per;       // k_b_repair blocks per problem
+  Options opt;          // the handle's options when the plan was created
   void* dev;            // device block: counters, descriptors, tables, workspaces
   int own_dev;          // dev allocated by the plan
   size_t dev_bytes;
@@ -288,6 +289,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   arrow_batch_s* b = new (std::nothrow) arrow_batch_s();
   if (!b) return ARROW_ERR_NOMEM;
   b->h = h;
+  b->opt = h->opt;
   b->count = count;
   b->flags = flags;
   b->dev_bytes = L.total;
@@ -393,7 +395,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
 
 static int batch_launch(arrow_batch_s* b, hipStream_t st) {
   const BatchArgs A = b->args;
-  const Options opt = b->h->opt;
+  const Options opt = b->opt;   // fixed at creation, so eager and graph runs agree
   hipLaunchKernelGGL(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), 0, st, A);
   hipLaunchKernelGGL((k_b_stage<false>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
   hipLaunchKernelGGL((k_b_stage<true>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);

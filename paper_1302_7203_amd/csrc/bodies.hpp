@@ -8,6 +8,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "exact.hpp"
 #include "solver.hpp"
 
 namespace ahd {
@@ -480,6 +481,50 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
 // The list reuses the sort's rank array, free once the poles are sorted; its
 // length sits in hdr[6] and is cleared by the prologue.
 
+// f(0) of the arrowhead the kernels solve, summed exactly from the caller's
+// inputs (exact.hpp) for Remark 1.
+//   ARROW / HERM: f(0) = alpha - sum_j |z_j|^2 / d_j, |z_j|^2 as exact products;
+//   DPR1 (Sec. 6.3 reduction, poles d_1 > ... > d_n of the solved sign):
+//     f(0) = alpha - sum_{j<n} zeta_j^2/d_j = d_n phi(0), phi(0) = 1 + |rho| sum_j u_j^2/d_j,
+//     or |rho| u_n^2 when d_n = 0;
+//   SVD: B^T B has corner alpha^2 + z^T z and terms (d_j z_j)^2 / d_j^2 = z_j^2,
+//     so f(0) = alpha^2 exactly.
+// *ok is 0 when the sum stays unresolved (f(0) = 0 as far as it reaches).
+template <int KIND, int G>
+__host__ __device__ inline double f_origin(const ProbDesc& D, const Prob& P, int ln, int* ok) {
+  *ok = 1;
+  if constexpr (KIND == KIND_SVD) {
+    return D.scalar * D.scalar;
+  } else if constexpr (KIND == KIND_DPR1) {
+    const double dn = P.ds[P.nsorted - 1];
+    const double rho = D.scalar;   // |rho|
+    if (dn == 0.0) {
+      const double un = P.zs[P.nsorted - 1];
+      return rho * un * un;
+    }
+    return origin_exact<KIND, G>(ln, D.n, 1.0, 1.0, dn, [&](int r, double* p, double* nn) {
+      *p = in_pole<KIND>(D, r);
+      const dd u2 = two_prod(D.z[r], D.z[r]);
+      const dd a = two_prod(rho, u2.hi), b = two_prod(rho, u2.lo);
+      nn[0] = a.hi; nn[1] = a.lo; nn[2] = b.hi; nn[3] = b.lo;
+      return 4;
+    }, ok);
+  } else {
+    const bool herm = D.kind == KIND_HERM;
+    return origin_exact<KIND, G>(ln, D.n - 1, D.scalar, -1.0, 1.0, [&](int r, double* p, double* nn) {
+      *p = D.d[r];
+      if (herm) {
+        const dd a = two_prod(D.z[2 * r], D.z[2 * r]), b = two_prod(D.z[2 * r + 1], D.z[2 * r + 1]);
+        nn[0] = a.hi; nn[1] = a.lo; nn[2] = b.hi; nn[3] = b.lo;
+        return (a.hi == 0.0 && b.hi == 0.0) ? 0 : 4;
+      }
+      const dd a = two_prod(D.z[r], D.z[r]);
+      nn[0] = a.hi; nn[1] = a.lo;
+      return a.hi == 0.0 ? 0 : 2;
+    }, ok);
+  }
+}
+
 __host__ __device__ inline uint32_t* repair_count(const Ws& w) { return (uint32_t*)(w.hdr + 6); }
 __host__ __device__ inline uint32_t* repair_list(const Ws& w, int64_t n) { return w.st + n; }
 
@@ -518,6 +563,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   const int m = P.m;
   int c_it = 0, c_dd = 0, c_plain = 1;   // the norm pass
   double rn = NAN;   // 1/||x|| from a remedy's last rational pass, when it ran one
+  double off_hint = -1.0;   // the norm pass's scale, when it is not |s + mu|
   if (m > 0 && opt.remedies) {
     const int i = w.ip1[k];
     const int side = (k == i) ? +1 : -1;
@@ -537,64 +583,71 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
         return;
       }
     }
-    if (quot > opt.tau_zero && !zero_pole) {
-      // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}
-      int z0 = 0, it = 0;
-      double last[3] = {NAN, NAN, NAN};
-      const double m2 = dpr1_inverse<KIND, G>(P, 0.0, 0.0, ln, &z0, &it, opt.root, 1.0 / lam1, last);
-      pv = 0.0; s = 0.0; mu = z0 ? 0.0 : m2;
-      if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
-      fl |= INFO_NEAR_ZERO;
-      c_it += it; c_dd += 1;
-    } else if (knu > opt.tau_nu) {
-      bool done = false;
-      const int i2 = (side > 0) ? i - 1 : i + 1;
-      if (i2 >= 0 && i2 < m) {
-        // Remark 2(a): the other neighbouring pole, if K_nu is small there and
-        // lambda is not so close to d_i that its vector entries would suffer
-        const double d2 = P.ds[i2];
-        const double mu2 = fabs(pdiff<KIND>(di, d2) + mu);
-        const int o2 = (side > 0) ? k - 1 : k + 1;
-        const double dist2 = fabs(pdiff<KIND>(w.pv1[o2], d2) + w.mu1[o2]);
-        const double knu2 = mu2 / fmin(mu2, dist2);
-        // the eigenvector entry of the nearer pole d_i is then formed as
-        // (d_i - d_{i2}) - mu2, which cancels by |d_i - d_{i2}| / |lambda - d_i|
-        const double cancel = fabs(pdiff<KIND>(di, d2)) / fabs(mu);
-        if (knu2 <= opt.tau_nu && cancel <= 8.0) {
-          const BPass bp = b_pass<KIND, G>(P, i2, -side, ln, opt.fp64_b);
-          int it = 0;
-          const int side2 = -side;
-          // first-pass lambda seen from the other pole: 1 / (lambda - d_i2)
-          const double nu_est = 1.0 / (pdiff<KIND>(di, d2) + mu);
-          double last[3] = {NAN, NAN, NAN};
-          const double nu = (opt.root == ROOT_RATIONAL)
-              ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it,
-                                          nu_est, last)
-              : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
-          pv = d2; s = 0.0; mu = 1.0 / nu;
-          if (KIND != KIND_DPR1 && last[0] == last[0]) rn = norm_from_pass(last, nu, P.ch[i2]);
-          fl |= INFO_REMEDY_A;
-          done = true;
-          c_it += it; c_dd += opt.fp64_b ? 0 : 1; c_plain += opt.fp64_b ? 1 : 0;
-        }
-      }
-      if (!done) {
-        // Remark 2(b): invert A - sigma I with sigma between d_i and lambda,
-        // 2^-10 |mu| away from lambda
-        s = mu - mu * (1.0 / 1024.0);
-        int z0 = 0, it = 0;
-        double last[3] = {NAN, NAN, NAN};
-        const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s), last);
-        pv = di; mu = z0 ? 0.0 : m2;
-        if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
-        fl |= INFO_REMEDY_B;
+    if constexpr (!DEFER) {   // the deferring check stage returned above
+      if (quot > opt.tau_zero && !zero_pole) {
+        // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}, whose
+        // weight rho = 1/f(0) is summed exactly where double-double cannot resolve it
+        int z0 = 0, it = 0, unres = 0;
+        const double l0 = origin_root<KIND, G>(P, ln, lam1, &z0, &unres, &it,
+                                               [&](int* ok) { return f_origin<KIND, G>(D, P, ln, ok); });
+        pv = 0.0; s = 0.0; mu = z0 ? 0.0 : l0;
+        // entries z_j / (d_j - lambda): their scale is the nearest pole's
+        // distance from the origin, which the norm pass below is given
+        off_hint = fabs(pval<KIND>(di));
+        fl |= INFO_NEAR_ZERO;
+        if (unres) fl |= INFO_F0_UNRESOLVED;
         c_it += it; c_dd += 1;
+      } else if (knu > opt.tau_nu) {
+        bool done = false;
+        const int i2 = (side > 0) ? i - 1 : i + 1;
+        if (i2 >= 0 && i2 < m) {
+          // Remark 2(a): the other neighbouring pole, if K_nu is small there and
+          // lambda is not so close to d_i that its vector entries would suffer
+          const double d2 = P.ds[i2];
+          const double mu2 = fabs(pdiff<KIND>(di, d2) + mu);
+          const int o2 = (side > 0) ? k - 1 : k + 1;
+          const double dist2 = fabs(pdiff<KIND>(w.pv1[o2], d2) + w.mu1[o2]);
+          const double knu2 = mu2 / fmin(mu2, dist2);
+          // the eigenvector entry of the nearer pole d_i is then formed as
+          // (d_i - d_{i2}) - mu2, which cancels by |d_i - d_{i2}| / |lambda - d_i|
+          const double cancel = fabs(pdiff<KIND>(di, d2)) / fabs(mu);
+          if (knu2 <= opt.tau_nu && cancel <= 8.0) {
+            const BPass bp = b_pass<KIND, G>(P, i2, -side, ln, opt.fp64_b);
+            int it = 0;
+            const int side2 = -side;
+            // first-pass lambda seen from the other pole: 1 / (lambda - d_i2)
+            const double nu_est = 1.0 / (pdiff<KIND>(di, d2) + mu);
+            double last[3] = {NAN, NAN, NAN};
+            const double nu = (opt.root == ROOT_RATIONAL)
+                ? rational_inverse<KIND, G>(P, i2, side2, bp.b, bp.lo, bp.hi, side2 > 0 ? bp.lo : bp.hi, ln, &it,
+                                            nu_est, last)
+                : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
+            pv = d2; s = 0.0; mu = 1.0 / nu;
+            if (KIND != KIND_DPR1 && last[0] == last[0]) rn = norm_from_pass(last, nu, P.ch[i2]);
+            fl |= INFO_REMEDY_A;
+            done = true;
+            c_it += it; c_dd += opt.fp64_b ? 0 : 1; c_plain += opt.fp64_b ? 1 : 0;
+          }
+        }
+        if (!done) {
+          // Remark 2(b): invert A - sigma I with sigma between d_i and lambda,
+          // 2^-10 |mu| away from lambda
+          s = mu - mu * (1.0 / 1024.0);
+          int z0 = 0, it = 0;
+          double last[3] = {NAN, NAN, NAN};
+          const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s), last);
+          pv = di; mu = z0 ? 0.0 : m2;
+          if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
+          fl |= INFO_REMEDY_B;
+          c_it += it; c_dd += 1;
+        }
       }
     }
   }
   if constexpr (KIND == KIND_DPR1) {
-    // the smallest eigenvalue, when nearer to d_n than to d_{n-1}
-    if (m > 0 && k == m) {
+    // the smallest eigenvalue, when nearer to d_n than to d_{n-1} (not after
+    // Remark 1, whose eigenvalue is accurate relative to itself and far from d_n)
+    if (m > 0 && k == m && !(fl & INFO_NEAR_ZERO)) {
       const double dn = P.ds[P.nsorted - 1];
       const double gap = P.ds[P.nsorted - 2] - dn;
       const double tau = (pv - dn) + s + mu;
@@ -614,7 +667,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   // the first pass's norm holds while its shift and mu stand (no remedy)
   const double nr1 = w.nr1[k];
   const bool first = pv == w.pv1[k] && s == 0.0 && mu == w.mu1[k] && nr1 == nr1;
-  const double inrm = first ? nr1 : (rn == rn ? rn : inv_norm<KIND, G>(P, pv, s, mu, ln));
+  const double inrm = first ? nr1 : (rn == rn ? rn : inv_norm<KIND, G>(P, pv, s, mu, ln, off_hint));
   if (first || rn == rn) c_plain -= 1;   // no norm pass
   if (ln == 0) {
     w.cnt[6 * k + 3] = c_it;

@@ -41,6 +41,7 @@ constexpr uint32_t INFO_KNU_LARGE = 128u; // K_nu above threshold after the reme
 constexpr uint32_t INFO_BAD_INPUT = 256u; // kind-specific domain error (SVD: d_j = 0)
 constexpr uint32_t INFO_POLE_SHIFT = 512u;// DPR1 eigenvalue re-measured from the pole d_n
 constexpr uint32_t INFO_DEFLATED = 1024u; // eigenpair deflated from a reducible arrowhead (Sec. 1)
+constexpr uint32_t INFO_F0_UNRESOLVED = 2048u; // Remark 1: f(0) is 0 to the reach of the exact sum
 constexpr uint32_t INFO_NOT_SOLVED = INFO_REDUCIBLE | INFO_NONFINITE | INFO_BAD_INPUT;
 
 constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 3
@@ -692,7 +693,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
 //   phi(nu) = 1 + rho sum_j u_j^2 / (Delta_j - nu),  Delta_j = 1/e_j, Delta_n = 0,
 // i.e. phi(nu) = 1 + rho (S(nu) - 1/nu) with S as in bisect_inverse.  The
 // wanted zero is exterior on the side of sign(rho).  Returns mu = 1/nu, or
-// sets *zero when f(sigma) evaluates to 0 (then lambda = sigma, Remark 1).
+// sets *zero when f(sigma) evaluates to 0 (then lambda = sigma).
 
 template <int KIND, int G>
 __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double s, int ln, int* zero,
@@ -779,6 +780,88 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
 }
 
 // ---------------------------------------------------------------------------
+// Remark 1: the eigenvalue nearest the origin from the extreme eigenvalue nu of
+// A^{-1}, the DPR1 matrix diag(1/d_j, 0) + rho u u^T, u = [D^{-1} z; -1],
+// rho = 1/f(0).  Its secular equation 1 + rho sum_j u_j^2 / (Delta_j - nu) = 0
+// (Delta_j = 1/d_j, Delta_n = 0), multiplied by f(0) and written in
+// lambda = 1/nu, reads
+//   h(lambda) = f(0) - lambda S(lambda),  S(lambda) = 1 + sum_j c_j / (d_j (d_j - lambda)),
+// since u_j^2/(Delta_j - nu) = -lambda c_j / (d_j (d_j - lambda)) and the last
+// term is -lambda.  Between the two poles around the origin every term of S is
+// positive, so S >= 1, h is decreasing with h' = -(1 + sum_j c_j/(d_j - lambda)^2),
+// the zero lies on the side of sign f(0) within |f(0)| and the nearer pole, and
+// h carries the relative error of f(0) plus a few ulps.  In lambda, unlike in
+// nu, nothing leaves the exponent range when lambda is tiny.  f(0) = corner -
+// sum_j c_j / d_j is summed in double-double; where that does not resolve it,
+// exact_f() (every lane of the group calls it) returns the exact sum, or NaN.
+// Safeguarded Newton steps, a bisection of the bracket when a step leaves it.
+// Sets *zero when f(0) is 0 (lambda = 0) and *unres when f(0) stays unresolved.
+template <int KIND, int G, class Exact>
+__host__ __device__ inline double origin_root(const Prob& P, int ln, double lam_est, int* zero, int* unres,
+                                              int* iters, Exact&& exact_f) {
+  const int m = P.m;
+  dd fs = {0.0, 0.0};
+  double fmag = 0.0, ppos = INFINITY, pneg = INFINITY;
+  for_terms<G>(ln, m, -1, [&](int j, bool) {
+    const dd e = pval_dd<KIND>(P.ds[j]);
+    const dd t = dd_div(dd{P.ch[j], P.cl[j]}, e);
+    fs = dd_add(fs, t);
+    fmag += fabs(t.hi);
+    if (e.hi > 0.0) ppos = fmin(ppos, e.hi);
+    else pneg = fmin(pneg, -e.hi);
+  });
+  fs = gsum_dd<G>(fs);
+  fmag = gsum<G>(fmag);
+  ppos = gmin<G>(ppos);
+  pneg = gmin<G>(pneg);
+  dd f = dd_sub(P.corner, fs);
+  *zero = 0;
+  *unres = 0;
+  // double-double (and, for DPR1 and SVD, the reduction to the arrowhead) is
+  // good to about (m + 8) 2^-100 of the terms' size
+  const double err = (double)(m + 8) * 0x1p-100 * (fmag + fabs(P.corner.hi));
+  if (!(fabs(f.hi) > err * 0x1p56)) {
+    int ok = 1;
+    const double fx = exact_f(&ok);
+    if (fx == fx) f = dd_from(fx);
+    *unres = !ok;
+  }
+  const double f0 = dd_to_d(f);
+  int it = 0;
+  if (f0 == 0.0) { *zero = 1; *iters = 0; return 0.0; }
+  const double sg = f0 > 0.0 ? 1.0 : -1.0;
+  // t = sg * lambda in (0, thi)
+  double tlo = 0.0, thi = fmin(fabs(f0), sg > 0.0 ? ppos : pneg);
+  double t = sg * lam_est;
+  if (!(t > tlo && t < thi)) t = (thi < INFINITY) ? 0.5 * thi : fabs(f0);
+  for (; it < 60; ++it) {
+    const double lam = sg * t;
+    double a = 0.0, b = 0.0;
+#pragma unroll 4
+    for (int j = ln; j < m; j += G) {
+      const double dj = pval<KIND>(P.ds[j]);
+      const double r = recip(dj - lam);
+      const double cr = P.ch[j] * r;
+      a = fma(cr, recip(dj), a);     // c_j / (d_j (d_j - lambda))
+      b = fma(cr, r, b);             // c_j / (d_j - lambda)^2
+    }
+    a = gsum<G>(a) + 1.0;
+    b = gsum<G>(b) + 1.0;
+    const double h = f0 - lam * a;
+    const double ht = sg * h;        // decreasing in t
+    if (ht > 0.0) tlo = t; else thi = t;
+    if (h == 0.0) break;
+    double tn = t + ht / b;
+    if (!(tn > tlo && tn < thi)) tn = (thi > 16.0 * tlo && tlo > 0.0) ? bits_mid(tlo, thi) : 0.5 * (tlo + thi);
+    const bool stop = fabs(tn - t) <= 2.0 * EPS * t || !(thi - tlo > 2.0 * EPS * thi);
+    t = tn;
+    if (stop) { ++it; break; }
+  }
+  *iters = it;
+  return sg * t;
+}
+
+// ---------------------------------------------------------------------------
 // DPR1 only: the smallest eigenvalue lies in (d_n, d_{n-1}) and may sit much
 // closer to d_n, which is not a pole of the reduced arrowhead.  Re-measure it
 // from d_n: tau = lambda - d_n is the zero in (0, d_{n-1} - d_n) of
@@ -859,9 +942,13 @@ __host__ __device__ inline double dpr1_from_last_pole(const Prob& P, double tau_
 // lies within about 2^-512 of that pole.  Scaling by a power of two is exact,
 // so where nothing overflows the result is that of the unscaled sum.
 
+// off, when given, replaces the distance |s + mu| as the scale: the shift of
+// Remark 1 is the origin, not a pole, and the entries are of the order of the
+// reciprocal distance to the nearest pole instead.
 template <int KIND, int G>
-__host__ __device__ inline double inv_norm(const Prob& P, double pv, double s, double mu, int ln) {
-  const double off = fabs(s + mu);
+__host__ __device__ inline double inv_norm(const Prob& P, double pv, double s, double mu, int ln,
+                                           double off_hint = -1.0) {
+  const double off = off_hint >= 0.0 ? off_hint : fabs(s + mu);
   const double g = (off > 0.0) ? ldexp(1.0, ilogb(fmin(fmax(off, 0x1p-1000), 0x1p500))) : 1.0;
   double acc = 0.0;
   if constexpr (KIND == KIND_DPR1) {

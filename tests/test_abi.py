@@ -57,3 +57,15 @@ def test_null_handle_is_rejected(libarrow):
     f.restype = ctypes.c_int
     assert f(None, ctypes.c_int64(4), None, None, ctypes.c_double(0.0), None, None, ctypes.c_int64(4),
              None, None, None) == -1
+
+
+def test_order_cap_is_host_side(libarrow):
+    """Orders above ARROW_N_MAX (where n * 64 lanes would pass 2^31) are refused
+    before any device work: the workspace query, host-only, says 0 there."""
+    src = open(HEADER).read()
+    cap = int(re.search(r"#define ARROW_N_MAX (\d+)", src).group(1))
+    assert cap * 64 <= 2 ** 31
+    f = libarrow.arrow_workspace_size
+    f.argtypes = [ctypes.c_int64]
+    f.restype = ctypes.c_size_t
+    assert f(cap) > 0 and f(cap + 1) == 0 and f(2 ** 28) == 0 and f(-1) == 0

@@ -256,3 +256,54 @@ def test_fp64_b_where_kb_is_small(kind, name, oracle_lib):
     assert np.all(dd[r["kb"] > 4.0] >= 1)   # large K_b: double-double
     if name == "graded_1024":
         assert dd.mean() < 0.2
+
+
+# ---------------------------------------------------------------------------
+# eigenvalues near the origin (Sec. 3, Remark 1): f(0) summed exactly where its
+# terms cancel beyond double-double, the root in lambda, the norm at the scale of
+# the nearest pole
+
+import near_zero_cases as NZ  # noqa: E402
+
+
+@pytest.mark.parametrize("case", NZ.arrow_cases(), ids=lambda c: c[0])
+def test_near_zero_arrow(case, oracle_lib):
+    _, d, z, a = case
+    r = emu.solve(0, d, z, a)
+    ref = oracle.arrow_eig(d, z, a)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "V")
+    k = int(np.argmin(np.abs(ref.lam)))
+    assert r["info"][k] & 8 and not r["info"][k] & 2048
+
+
+@pytest.mark.parametrize("case", NZ.dpr1_cases(), ids=lambda c: c[0])
+def test_near_zero_dpr1(case, oracle_lib):
+    _, d, u, rho = case
+    r = emu.solve(1, d, u, rho)
+    ref = oracle.dpr1_eig(d, u, rho)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close(r["V"], ref.vec, "Q")
+    k = int(np.argmin(np.abs(ref.lam)))
+    assert r["info"][k] & 8 and not r["info"][k] & 2048
+
+
+@pytest.mark.parametrize("case", NZ.svd_cases(), ids=lambda c: c[0])
+def test_near_zero_svd(case, oracle_lib):
+    _, d, z, a = case
+    r = emu.solve(2, d, z, a)
+    ref = oracle.arrow_svd(d, z, a)
+    assert_close(r["lam"], ref.sigma, "sigma")
+    assert_close(r["V"], ref.V, "V")
+    assert_close(r["U"], ref.U, "U")
+    assert r["info"][-1] & 8
+
+
+@pytest.mark.parametrize("case", NZ.herm_cases(), ids=lambda c: c[0])
+def test_near_zero_hermitian(case, oracle_lib):
+    _, d, z, a = case
+    r = emu.solve(3, d, z, a)
+    ref = oracle.herm_eig(d, z, a)
+    assert_close(r["lam"], ref.lam, "lambda")
+    assert_close_c(r["V"], ref.vec, "U")
+    assert r["info"][int(np.argmin(np.abs(ref.lam)))] & 8

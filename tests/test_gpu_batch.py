@@ -175,3 +175,30 @@ def test_full_size_batch_sampled(env, oracle_lib):
     b.close()
     del b
     torch.cuda.empty_cache()
+
+
+def test_options_fixed_at_creation(env):
+    """A plan keeps the handle's options from its creation: changing the root
+    finder (ARROW_OPT_ROOT) or the FP64-b bound (ARROW_OPT_TAU_B) afterwards
+    changes neither its eager nor its graph runs (bitwise)."""
+    torch, batch, dev = env
+    from paper_1302_7203_amd import binding
+    probs = _mixed(12, 21, nmax=200)
+    eager = batch.Batch(probs, device=dev)
+    graph = batch.Batch(probs, device=dev, graph=True)
+    eager.run()
+    torch.cuda.synchronize()
+    ref = [tuple(t.clone() if t is not None else None for t in eager.result(p)) for p in range(len(probs))]
+    try:
+        binding.set_option(binding.OPT_ROOT, binding.ROOT_BISECT)
+        binding.set_option(binding.OPT_TAU_B, 4.0)
+        for b in (eager, graph):
+            b.run()
+            torch.cuda.synchronize()
+            for p in range(len(probs)):
+                got = b.result(p)
+                for a, r in zip(got, ref[p]):
+                    assert (a is None and r is None) or torch.equal(a, r), p
+    finally:
+        binding.set_option(binding.OPT_ROOT, binding.ROOT_RATIONAL)
+        binding.set_option(binding.OPT_TAU_B, 0.0)

@@ -575,6 +575,155 @@ def test_tridiag_against_lapack(n, seed, oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# eigenvalues near the origin: Sec. 3, Remark 1 and the exceptions (a)-(c) of
+# condition (C1) in Theorem 2 (an eigenvalue far closer to 0 than to any pole)
+
+FINE = Fraction(1, 2 ** 1400)     # bisection floor well below the smallest double
+
+
+def _bracket_count(A, lam, k, rel=Fraction(1, 10 ** 25)):
+    """Exact inertia on both sides of lam: True when exactly the eigenvalue of
+    rank k (0 = largest) lies within lam (1 +- rel)."""
+    n = len(A)
+    w = abs(lam) * rel + Fraction(1, 2 ** 1072)    # hi + lo with a subnormal lo word
+    lo, hi = brute._count_below(A, lam - w), brute._count_below(A, lam + w)
+    return lo == n - 1 - k and hi == n - k
+
+
+# (d, z, alpha): 3x3 cases have closed forms near alpha/(1 + sum z^2/d^2); the
+# quotients z^2/d of (3, -3) and (6, 3, -2) are not dyadic, so their exact
+# cancellation needs more than one binary128 digit
+NEAR_ZERO = [
+    ([1.0, -1.0], [1.0, 1.0], 1e-12),
+    ([1.0, -1.0], [1.0, 1.0], 1e-20),
+    ([1.0, -1.0], [1.0, 1.0], 1e-30),
+    ([1.0, -1.0], [1.0, 1.0], -3e-200),
+    ([3.0, -3.0], [1.0, 1.0], 1e-30),
+    ([3.0, -3.0], [1.0, 1.0], -3e-200),
+    ([6.0, 3.0, -2.0], [1.0, 1.0, 1.0], 1e-30),
+    ([6.0, 3.0, -2.0], [1.0, 1.0, 1.0], -2.5e-300),
+    ([6.0, 3.0, -2.0], [1.0, 1.0, 1.0], 3e-3),       # inside the window, |l/d| ~ 1e-3
+    ([-0.5, -4.0], [1.0, 2.0], -3.0 + 2.0 ** -40),    # exterior: poles < 0, f(0) = 2^-40, l_1 ~ 2e-13
+    ([2.0, 2.0, -1.0], [1.0, 1.0, 1.0], 1e-30),       # reducible: a repeated pole merged first
+]
+
+
+@pytest.mark.parametrize("case", range(len(NEAR_ZERO)))
+def test_near_zero_exact(case, oracle_lib):
+    d, z, alpha = (np.array(NEAR_ZERO[case][0]), np.array(NEAR_ZERO[case][1]), NEAR_ZERO[case][2])
+    n = d.size + 1
+    A = brute.dense_arrow(d, z, alpha)
+    lam_exact = brute.exact_eigvals(A, rel_bits=170, abs_floor=FINE)
+    r = oracle.arrow_eig(d, z, alpha)
+    assert np.all(r.relerr <= 1e-25), r.relerr
+    k0 = int(np.argmin(np.abs(r.lam)))
+    for k in range(n):
+        got = hilo(r.lam[k], r.lam_lo[k])
+        # the lo word of a value near 1e-300 is subnormal: its last bit is 2^-1074
+        tol = abs(lam_exact[k]) * Fraction(1, 10 ** 25) + Fraction(1, 2 ** 1074)
+        assert abs(got - lam_exact[k]) <= tol, (k, float(got), float(lam_exact[k]))
+        assert r.lam[k] == float(lam_exact[k])
+        if k == k0 and d.size == len(set(d.tolist())):
+            x = brute.exact_null_vector(A, lam_exact[k])
+            scale = -F(r.vec[-1, k])
+            for j in range(n - 1):
+                assert abs(F(r.vec[j, k]) / scale - x[j]) <= abs(x[j]) * Fraction(4, 10 ** 16), (k, j)
+
+
+def test_near_zero_random_200(oracle_lib):
+    """n = 201, poles of both signs, alpha the double nearest to sum z_j^2/d_j, so
+    that f(0) is a rounding error: the eigenvalue near 0 is ~1e-20, pinned by
+    exact inertia on both sides of it."""
+    rng = np.random.default_rng(5)
+    d = np.sort(rng.uniform(-1, 1, 200))[::-1]
+    z = rng.uniform(0.1, 1, 200)
+    alpha = float(sum(F(b) ** 2 / F(a) for a, b in zip(d, z)))
+    r = oracle.arrow_eig(d, z, alpha)
+    assert np.all(r.relerr <= 1e-25)
+    k = int(np.argmin(np.abs(r.lam)))
+    assert abs(r.lam[k]) < 1e-15 * np.min(np.abs(d))
+    assert _bracket_count(brute.dense_arrow(d, z, alpha), hilo(r.lam[k], r.lam_lo[k]), k)
+
+
+@pytest.mark.parametrize("rho", [4.0, 4.0 + 2.0 ** -50, 4.0 - 2.0 ** -48])
+def test_near_zero_dpr1(rho, oracle_lib):
+    """D + rho uu^T with d = (2, -1, 4), u = 1: singular at rho = 4 exactly (an
+    eigenvalue 0), and an eigenvalue of size ~1e-15 next to it."""
+    d, u = np.array([2.0, -1.0, 4.0]), np.ones(3)
+    M = brute.dense_dpr1(d, u, rho)
+    lam_exact = brute.exact_eigvals(M, rel_bits=170, abs_floor=FINE)
+    r = oracle.dpr1_eig(d, u, rho)
+    assert np.all(r.relerr <= 1e-25)
+    for k in range(3):
+        got = hilo(r.lam[k], r.lam_lo[k])
+        if lam_exact[k] == 0 or abs(lam_exact[k]) < FINE:
+            assert got == 0 and rho == 4.0
+        else:
+            assert abs(got - lam_exact[k]) <= abs(lam_exact[k]) * Fraction(1, 10 ** 25), (k, float(got))
+
+
+def test_near_zero_dpr1_random(oracle_lib):
+    """Random d of both signs and u, rho the double nearest to -1/sum(u_j^2/d_j)."""
+    rng = np.random.default_rng(8)
+    d = W._sorted_with_gap(rng, 8, -1.0, 1.0)
+    u = rng.uniform(0.2, 1.0, 8)
+    s = sum(F(b) ** 2 / F(a) for a, b in zip(d, u))
+    if s > 0:
+        d = -d
+        s = -s
+    rho = float(-1 / s)
+    M = brute.dense_dpr1(d, u, rho)
+    r = oracle.dpr1_eig(d, u, rho)
+    assert np.all(r.relerr <= 1e-25)
+    k = int(np.argmin(np.abs(r.lam)))
+    assert abs(r.lam[k]) < 1e-12
+    assert _bracket_count(M, hilo(r.lam[k], r.lam_lo[k]), k)
+
+
+@pytest.mark.parametrize("alpha", [1e-30, -1e-100, 3e-150])
+def test_near_zero_svd(alpha, oracle_lib):
+    """B = [D z; 0 alpha] with tiny alpha: the smallest singular value is ~|alpha|,
+    so B^T B has an eigenvalue ~alpha^2 next to its corner alpha^2 + z^T z.
+    Pinned by exact inertia of B^T B and by prod(sigma) = |alpha prod d|."""
+    d, z = np.array([0.5, 0.75, 0.3]), np.array([0.9, 0.4, 0.7])
+    n = 4
+    B = [[Fraction(0)] * n for _ in range(n)]
+    for j in range(3):
+        B[j][j] = F(d[j])
+        B[j][3] = F(z[j])
+    B[3][3] = F(alpha)
+    BtB = [[sum(B[r][i] * B[r][j] for r in range(n)) for j in range(n)] for i in range(n)]
+    lam_exact = brute.exact_eigvals(BtB, rel_bits=170, abs_floor=FINE)
+    r = oracle.arrow_svd(d, z, alpha)
+    assert np.all(r.relerr <= 1e-25)
+    with mp.workdps(80):
+        for k in range(n):
+            s2 = mpf2(r.sigma[k], r.sigma_lo[k]) ** 2
+            ex = mp.mpf(lam_exact[k].numerator) / lam_exact[k].denominator
+            assert abs(s2 - ex) <= ex * mp.mpf("1e-25"), k
+        prod = mp.fprod([mpf2(a, b) for a, b in zip(r.sigma, r.sigma_lo)])
+        ref = abs(mp.mpf(alpha) * mp.fprod([mp.mpf(float(x)) for x in d]))
+        assert abs(prod - ref) <= ref * mp.mpf("1e-25")
+
+
+def test_near_zero_hermitian(oracle_lib):
+    """[diag(6, 3, -2) z; z^* alpha] with |z_j| = 1 and alpha = 1e-30, against
+    mpmath's dense Hermitian solver."""
+    d = np.array([6.0, 3.0, -2.0])
+    z = np.array([1j, -1.0, 1j * -1.0])
+    assert _herm_failures(d, z, 1e-30, oracle.herm_eig(d, z, 1e-30), dps=90) == []
+    assert np.all(oracle.herm_eig(d, z, 1e-30).relerr <= 1e-25)
+
+
+def test_origin_unresolved_is_reported(oracle_lib):
+    """f(0) = 0 exactly with non-dyadic quotients (1/3 - 1/3): no finite number of
+    binary128 digits settles it, and the oracle says so instead of guessing."""
+    r = oracle.arrow_eig(np.array([3.0, -3.0]), np.array([1.0, 1.0]), 0.0)
+    assert r.relerr[1] >= 1 and abs(r.lam[1]) < 1e-300
+    assert np.all(r.relerr[[0, 2]] <= 1e-25)
+
+
+# ---------------------------------------------------------------------------
 # planted mistakes: every one must be caught by the pins above
 
 _MUTANTS = {
@@ -598,6 +747,14 @@ _MUTANTS = {
     "herm_modulus_real_part_only": ("cq[j] = (R)zr[o] * (R)zr[o] + (R)zi[o] * (R)zi[o];", "cq[j] = (R)zr[o] * (R)zr[o];"),
     "tridiag_sturm_b_not_squared": ("b2[i] = bq[i] * bq[i];", "b2[i] = fabsq(bq[i]);"),
     "tridiag_back_substitution_sign": ("s -= u1[i] * x[i + 1];", "s += u1[i] * x[i + 1];"),
+    "origin_one_digit": ("for (int level = 0; level < 24; ++level)", "for (int level = 0; level < 1; ++level)"),
+    "origin_digit_sign": ("ex_add(&x, -q);", "ex_add(&x, q);"),
+    "origin_inexact_remainder": ("r[t] = (r[t] - p) - pe;", "r[t] = (r[t] - p);"),
+    "origin_slope_sign": ("S += s->c[j] / (s->d[j] * (s->d[j] - l));", "S += s->c[j] / (s->d[j] * (s->d[j] + l));"),
+    "origin_window_skipped": ("if (lo_end < 0 && hi_end > 0) {", "if (0) {"),
+    "origin_dpr1_low_part_dropped": ("q_two_prod((R)rho, uu * uu, &tn[2 * j], &tn[2 * j + 1]);",
+                                     "tn[2 * j] = cq[j]; tn[2 * j + 1] = 0;"),
+    "origin_svd_corner_dropped": ("k0[0] = (R)alpha * (R)alpha;", "k0[0] = 0;"),
     "vector_tau_sign": ("R x = (R)z[j] / (((R)d[j] - dp) - r.tau);\n        col[j]",
                         "R x = (R)z[j] / (((R)d[j] - dp) + r.tau);\n        col[j]"),
 }
@@ -680,8 +837,41 @@ def _quick_extension_pins(lib):
     return failed
 
 
+def _quick_origin_pins(lib):
+    """Eigenvalues near the origin, each bracketed by exact inertia."""
+    failed = []
+    try:
+        d, z = np.array([6.0, 3.0, -2.0]), np.ones(3)
+        for alpha in (1e-30, -2.5e-300, 3e-3):
+            r = oracle.arrow_eig(d, z, alpha, lib=lib)
+            k = int(np.argmin(np.abs(r.lam)))
+            if not _bracket_count(brute.dense_arrow(d, z, alpha), hilo(r.lam[k], r.lam_lo[k]), k):
+                failed.append(f"arrow near zero {alpha}")
+        rng = np.random.default_rng(8)
+        d = W._sorted_with_gap(rng, 8, -1.0, 1.0)
+        u = rng.uniform(0.2, 1.0, 8)
+        sm = sum(F(b) ** 2 / F(a) for a, b in zip(d, u))
+        if sm > 0:
+            d, sm = -d, -sm
+        rho = float(-1 / sm)
+        r = oracle.dpr1_eig(d, u, rho, lib=lib)
+        k = int(np.argmin(np.abs(r.lam)))
+        if not _bracket_count(brute.dense_dpr1(d, u, rho), hilo(r.lam[k], r.lam_lo[k]), k):
+            failed.append("dpr1 near zero")
+        d, z, alpha = np.array([0.5, 0.75, 0.3]), np.array([0.9, 0.4, 0.7]), 1e-30
+        r = oracle.arrow_svd(d, z, alpha, lib=lib)
+        with mp.workdps(60):
+            prod = mp.fprod([mpf2(a, b) for a, b in zip(r.sigma, r.sigma_lo)])
+            ref = abs(mp.mpf(alpha) * mp.fprod([mp.mpf(float(x)) for x in d]))
+            if not abs(prod - ref) <= ref * mp.mpf("1e-25"):
+                failed.append("svd near zero")
+    except (oracle.oracle.OracleError, ValueError, ZeroDivisionError):
+        failed.append("near zero error")
+    return failed
+
+
 def test_pins_catch_planted_mistakes(oracle_lib):
-    assert _quick_pins(None) == [] and _quick_extension_pins(None) == []
+    assert _quick_pins(None) == [] and _quick_extension_pins(None) == [] and _quick_origin_pins(None) == []
     src = open(os.path.join(os.path.dirname(oracle.oracle.__file__), "oracle.c")).read()
     tmp = tempfile.mkdtemp(prefix="oracle_mut_")
     try:
@@ -692,6 +882,16 @@ def test_pins_catch_planted_mistakes(oracle_lib):
                 f.write(src.replace(old, new))
             so = os.path.join(tmp, f"lib_{name}.so")
             subprocess.run(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-o", so, path, "-lquadmath"], check=True)
-            assert _quick_pins(so) + _quick_extension_pins(so) != [], f"planted mistake '{name}' not caught"
+            assert _quick_pins(so) + _quick_extension_pins(so) + _quick_origin_pins(so) != [], \
+                f"planted mistake '{name}' not caught"
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
+
+
+def test_parity_helper_refuses_unresolved_reference(oracle_lib, monkeypatch):
+    """tests/parity.py refuses a reference whose zero the oracle could not resolve."""
+    import parity
+    parity.guard_oracle(monkeypatch)
+    with pytest.raises(parity.UntrustedReference):
+        oracle.arrow_eig(np.array([3.0, -3.0]), np.array([1.0, 1.0]), 0.0)
+    assert oracle.arrow_eig(np.array([3.0, -3.0]), np.array([1.0, 1.0]), 1e-30).lam[1] > 0
