@@ -783,19 +783,24 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
 // Remark 1: the eigenvalue nearest the origin from the extreme eigenvalue nu of
 // A^{-1}, the DPR1 matrix diag(1/d_j, 0) + rho u u^T, u = [D^{-1} z; -1],
 // rho = 1/f(0).  Its secular equation 1 + rho sum_j u_j^2 / (Delta_j - nu) = 0
-// (Delta_j = 1/d_j, Delta_n = 0), multiplied by f(0) and written in
-// lambda = 1/nu, reads
-//   h(lambda) = f(0) - lambda S(lambda),  S(lambda) = 1 + sum_j c_j / (d_j (d_j - lambda)),
-// since u_j^2/(Delta_j - nu) = -lambda c_j / (d_j (d_j - lambda)) and the last
-// term is -lambda.  Between the two poles around the origin every term of S is
-// positive, so S >= 1, h is decreasing with h' = -(1 + sum_j c_j/(d_j - lambda)^2),
-// the zero lies on the side of sign f(0) within |f(0)| and the nearer pole, and
-// h carries the relative error of f(0) plus a few ulps.  In lambda, unlike in
-// nu, nothing leaves the exponent range when lambda is tiny.  f(0) = corner -
-// sum_j c_j / d_j is summed in double-double; where that does not resolve it,
-// exact_f() (every lane of the group calls it) returns the exact sum, or NaN.
-// Safeguarded Newton steps, a bisection of the bracket when a step leaves it.
-// Sets *zero when f(0) is 0 (lambda = 0) and *unres when f(0) stays unresolved.
+// (Delta_j = 1/d_j, Delta_n = 0), multiplied by f(0), reads
+//   h = f(0) - 1/nu - sum_j T_j,   T_j = c_j / (d_j (nu d_j - 1)),
+// since u_j^2/(Delta_j - nu) = -c_j/(d_j (nu d_j - 1)) and the last term is -1/nu.
+// It is solved for lambda = 1/nu with nu d_j formed as d_j/lambda: between the
+// two poles around the origin every T_j has the sign of lambda (no
+// cancellation in lambda + sum T_j), d_j/lambda - 1 is of order one at the
+// poles that matter, and neither nu nor a square of 1/d_j is ever formed, so
+// nothing leaves the exponent range when lambda or the poles are tiny.  Where
+// |d_j/lambda| passes 2^900, T_j = (c_j/d_j) lambda / d_j, its limit to far
+// below rounding.  h decreases; with W_j = T_j / (1 - lambda/d_j),
+// -dh/dlambda = (lambda + sum_j W_j) / lambda, so a Newton step moves lambda
+// by lambda h / (lambda + sum_j W_j).  The zero lies on the side of sign f(0),
+// within |f(0)| (every term of h/lambda beyond -1 is negative) and the nearer
+// pole; a step that leaves that bracket is replaced by its midpoint.
+// f(0) = corner - sum_j c_j / d_j is summed in double-double; where that does
+// not resolve it, exact_f(&ok) (every lane of the group calls it) returns the
+// exact sum (ok = 0: unresolved), or NaN.  Sets *zero when f(0) is 0 (lambda
+// = 0) and *unres when f(0) stays unresolved.
 template <int KIND, int G, class Exact>
 __host__ __device__ inline double origin_root(const Prob& P, int ln, double lam_est, int* zero, int* unres,
                                               int* iters, Exact&& exact_f) {
@@ -830,29 +835,29 @@ __host__ __device__ inline double origin_root(const Prob& P, int ln, double lam_
   int it = 0;
   if (f0 == 0.0) { *zero = 1; *iters = 0; return 0.0; }
   const double sg = f0 > 0.0 ? 1.0 : -1.0;
-  // t = sg * lambda in (0, thi)
+  // t = sg * lambda in (0, thi]
   double tlo = 0.0, thi = fmin(fabs(f0), sg > 0.0 ? ppos : pneg);
   double t = sg * lam_est;
-  if (!(t > tlo && t < thi)) t = (thi < INFINITY) ? 0.5 * thi : fabs(f0);
-  for (; it < 60; ++it) {
+  if (!(t > tlo && t < thi)) t = fmin(fabs(f0), 0.5 * thi);
+  for (; it < 80; ++it) {
     const double lam = sg * t;
-    double a = 0.0, b = 0.0;
+    double a = 0.0, w = 0.0;
 #pragma unroll 4
     for (int j = ln; j < m; j += G) {
       const double dj = pval<KIND>(P.ds[j]);
-      const double r = recip(dj - lam);
-      const double cr = P.ch[j] * r;
-      a = fma(cr, recip(dj), a);     // c_j / (d_j (d_j - lambda))
-      b = fma(cr, r, b);             // c_j / (d_j - lambda)^2
+      const double q = dj / lam;
+      const double T = (fabs(q) < 0x1p900) ? P.ch[j] / (dj * (q - 1.0)) : ((P.ch[j] / dj) * lam) / dj;
+      a += T;
+      w += T / (1.0 - lam / dj);
     }
-    a = gsum<G>(a) + 1.0;
-    b = gsum<G>(b) + 1.0;
-    const double h = f0 - lam * a;
+    a = gsum<G>(a);
+    w = gsum<G>(w);
+    const double h = (f0 - lam) - a;
     const double ht = sg * h;        // decreasing in t
     if (ht > 0.0) tlo = t; else thi = t;
     if (h == 0.0) break;
-    double tn = t + ht / b;
-    if (!(tn > tlo && tn < thi)) tn = (thi > 16.0 * tlo && tlo > 0.0) ? bits_mid(tlo, thi) : 0.5 * (tlo + thi);
+    double tn = t + sg * (lam * h / (lam + w));
+    if (!(tn > tlo && tn < thi)) tn = (tlo > 0.0 && thi > 16.0 * tlo) ? bits_mid(tlo, thi) : 0.5 * (tlo + thi);
     const bool stop = fabs(tn - t) <= 2.0 * EPS * t || !(thi - tlo > 2.0 * EPS * thi);
     t = tn;
     if (stop) { ++it; break; }
