@@ -128,6 +128,25 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
               double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info);
 
 /*
+ * arrow_eig without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as arrow_eig, for
+ * 1 <= n <= ARROW_NOALLOC_N_MAX (above it: -2).  Instead of the handle's
+ * workspace it uses a scratch array in static device memory, 16 + 25
+ * ARROW_NOALLOC_N_MAX doubles (6.25 MiB), which every device the library runs
+ * on holds until the process ends; its address is looked up in arrow_create
+ * (ARROW_ERR_HIP if that failed).  It calls no hipMalloc, hipFree or other
+ * allocating routine.  The scratch is shared by every arrow_eig_noalloc call on
+ * that device, through any handle: calls whose executions overlap on one
+ * device (different streams, or different host threads) race and give wrong
+ * results; calls ordered on one stream are safe.  Each call's kernels set up
+ * every scratch word they read (the last call's contents stay behind).
+ */
+#define ARROW_NOALLOC_N_MAX 32768
+int arrow_eig_noalloc(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+                      double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info);
+
+/*
  * Eigen-decomposition of the Hermitian arrowhead C = [ diag(d)  z ; z^*  alpha ]
  * (Sec. 6.1) of order n >= 1: d real (n-1), z complex (n-1 (re, im) pairs of
  * doubles, any order; 8-byte aligned), alpha real.  Solved as the real

@@ -41,6 +41,7 @@ OPT_ROOT = 7
 OPT_TAU_B = 8
 ROOT_BISECT = 0
 ROOT_RATIONAL = 1
+NOALLOC_N_MAX = 32768   # ARROW_NOALLOC_N_MAX: largest order arrow_eig_noalloc takes
 SCHEDULE_SINGLE = 0
 SCHEDULE_BATCH = 1
 INT32_MAX = 2147483647
@@ -72,6 +73,7 @@ def lib():
                 L.arrow_workspace_size.argtypes = [I64]
                 L.arrow_workspace_size.restype = ctypes.c_size_t
                 L.arrow_eig.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
+                L.arrow_eig_noalloc.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
                 L.arrow_eig_herm.argtypes = [P, I64, P, P, D, P, P, I64, P, P, P]
                 L.tridiag_eig.argtypes = [P, I64, P, P, P, P, I64, P]
                 L.dpr1_eig.argtypes = [P, I64, P, P, D, P, P, I64, P]
@@ -86,8 +88,8 @@ def lib():
                 L.arrow_probe_rcp.argtypes = [P, P, I64, P]
                 for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy", "arrow_probe_rcp",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
-                          "arrow_eig", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd", "arrow_last_timing",
-                          "arrow_timing_of", "arrow_last_counters",
+                          "arrow_eig", "arrow_eig_noalloc", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd",
+                          "arrow_last_timing", "arrow_timing_of", "arrow_last_counters",
                           "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
                 _lib = L
@@ -207,8 +209,9 @@ def _colmajor(n, device):
 
 
 def arrow_eig(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool = True,
-              pairs: bool = False) -> EigOut:
-    """Eigenpairs of A = [diag(d) z; z^T alpha]; d, z float64 CUDA tensors of length n-1."""
+              pairs: bool = False, noalloc: bool = False) -> EigOut:
+    """Eigenpairs of A = [diag(d) z; z^T alpha]; d, z float64 CUDA tensors of length n-1.
+    noalloc: call arrow_eig_noalloc (the library allocates nothing; n <= NOALLOC_N_MAX)."""
     device = d.device
     n = d.numel() + 1
     d = _dev_vec(d, n - 1, device, "d")
@@ -221,9 +224,9 @@ def arrow_eig(d: torch.Tensor, z: torch.Tensor, alpha: float, *, vectors: bool =
         shift = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
         mu = torch.empty(n, dtype=torch.float64, device=device) if pairs else None
         info = torch.empty(n, dtype=torch.int32, device=device)
-        rc = lib().arrow_eig(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(lam), _ptr(buf), n,
-                             _ptr(shift), _ptr(mu), _ptr(info))
-    _check(rc, "arrow_eig")
+        f = lib().arrow_eig_noalloc if noalloc else lib().arrow_eig
+        rc = f(h, n, _ptr(d), _ptr(z), float(alpha), _ptr(lam), _ptr(buf), n, _ptr(shift), _ptr(mu), _ptr(info))
+    _check(rc, "arrow_eig_noalloc" if noalloc else "arrow_eig")
     return EigOut(lam, None if buf is None else buf.t(), None, shift, mu, info)
 
 

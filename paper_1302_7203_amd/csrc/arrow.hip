@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <math.h>
+#include <mutex>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -414,6 +415,42 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
 
 static bool finite_h(double x) { return x - x == 0.0; }
 
+// ---------------------------------------------------------------------------
+// Scratch of arrow_eig_noalloc: one problem's workspace at the largest order
+// that call takes, in static device memory (each device holds its own copy
+// until the process ends).  Host code never uses the array's name as a device
+// address: arrow_create looks up each device's address once, with that device
+// current, and every later use goes through scratch_dev[].
+constexpr size_t NOALLOC_WS_DOUBLES = 16 + (size_t)ARROW_NOALLOC_N_MAX * 25;
+static __device__ __align__(256) double scratch[NOALLOC_WS_DOUBLES];
+constexpr int SCRATCH_DEVICES = 64;
+static double* scratch_dev[SCRATCH_DEVICES];
+static int scratch_rc[SCRATCH_DEVICES];   // 0: not looked up yet, 1: found, -1: lookup failed
+static std::mutex scratch_mu;
+
+static void scratch_lookup(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_rc[device] != 0) return;
+  DeviceGuard g(device);
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr) {
+    scratch_dev[device] = (double*)ptr;
+    scratch_rc[device] = 1;
+  } else {
+    (void)hipGetLastError();
+    scratch_rc[device] = -1;
+  }
+}
+
+static double* scratch_of(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_rc[device] == 1 ? scratch_dev[device] : nullptr;
+}
+
+static_assert(NOALLOC_WS_DOUBLES == 16 + (size_t)ARROW_NOALLOC_N_MAX * 25, "workspace of ws_doubles()");
+
 extern "C" {
 
 int arrow_create(arrow_handle_t* h, int device) {
@@ -442,6 +479,7 @@ int arrow_create(arrow_handle_t* h, int device) {
   }
   p->ntab[ARROW_SCHEDULE_SINGLE] = 0;
   default_batch_table(p);
+  scratch_lookup(device);   // arrow_eig_noalloc's scratch address on this device
   p->magic = HANDLE_MAGIC;
   *h = p;
   return ARROW_OK;
@@ -555,8 +593,13 @@ int arrow_last_counters(arrow_handle_t h, int64_t* out) {
   return ARROW_OK;
 }
 
-int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
-              double* V, int64_t ldv, double* shift, double* mu, uint32_t* info) {
+}  // extern "C"
+
+// arrow_eig's body: ws = null grows and uses the handle's workspace, else ws
+// (room for ws_doubles(n) doubles) is used and nothing is allocated
+static int arrow_eig_in(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+                        double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info,
+                        double* ws) {
   if (!valid(h)) return -1;
   if (!order_ok(n)) return -2;
   if (n > 1 && !d) return -3;
@@ -565,8 +608,11 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
   if (!lambda) return -6;
   if (V && ldv < n) return -8;
   DeviceGuard g(h->device);
-  const int rc = ensure_ws(h, ws_doubles(n));
-  if (rc) return rc;
+  if (!ws) {
+    const int rc = ensure_ws(h, ws_doubles(n));
+    if (rc) return rc;
+    ws = h->ws;
+  }
   ProbDesc D{};
   D.kind = KIND_ARROW;
   D.n = (int32_t)n;
@@ -579,8 +625,24 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
   D.shift = shift;
   D.mu = mu;
   D.info = info;
-  D.ws = h->ws;
+  D.ws = ws;
   return launch_problem<KIND_ARROW>(h, D);
+}
+
+extern "C" {
+
+int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
+              double* V, int64_t ldv, double* shift, double* mu, uint32_t* info) {
+  return arrow_eig_in(h, n, d, z, alpha, lambda, V, ldv, shift, mu, info, nullptr);
+}
+
+int arrow_eig_noalloc(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha,
+                      double* lambda, double* V, int64_t ldv, double* shift, double* mu, uint32_t* info) {
+  if (!valid(h)) return -1;
+  if (n > ARROW_NOALLOC_N_MAX) return -2;   // beyond what the scratch holds
+  double* ws = scratch_of(h->device);
+  if (!ws) return ARROW_ERR_HIP;            // the address lookup at arrow_create failed
+  return arrow_eig_in(h, n, d, z, alpha, lambda, V, ldv, shift, mu, info, ws);
 }
 
 int arrow_eig_herm(arrow_handle_t h, int64_t n, const double* d, const double* z, double alpha, double* lambda,
