@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the accurate arrowhead eigensolver on one MI355X.
 
-A step is one full solve -- every eigenvalue and the full eigenvector matrix --
-of one synthetic arrowhead problem whose inputs are already resident in HBM.
-The default workload is the graded n=4096 arrowhead (|d| log-uniform in
-[1e-10, 1e10] with random signs plus 64 clusters of 8 poles with relative gaps
-~1e-12, z log-uniform in [1e-8, 1], alpha = 1e-3; V is 128 MiB).
+Default workload (the batched comparison the metric names): 10,000 independent
+problems, n = round(exp U(ln 16, ln 1024)), half arrowhead (d ~ U(-1,1) with
+minimum gap 1e-6, z ~ U(0.1,1), alpha ~ U(-1,1)), half diagonal-plus-rank-one
+(u = g/|g|, rho ~ U(0.1,10)); every eigenvalue and eigenvector of every
+problem, inputs resident in HBM.  A step is one run of the hipGraph-captured
+batched plan over all of them; the same problems solved with one launch
+sequence per problem are timed beside it.  --workload selects a single large
+problem instead (the graded n = 4096 arrowhead, uniform n = 16384 or n = 512),
+where a step is one full solve.
 
 Prints one JSON line.  Besides the throughput it reports, from HIP events
-recorded by the library on the solve's stream during the timed steps, the
-average duration of each stage and the roofline position of the dominant
-kernel (the root stage, bound by FP64 vector ALU work) and of the vector
-kernel (bound by HBM writes).  A bounded sample of the same workload is solved
-by the CPU oracle on the host cores, and the timed GPU outputs are checked
-against it at the 1e-13 relative bar.
+stamped by the kernels' own dispatches, the duration of each kernel and the
+roofline position of the dominant kernel (the root stage, bound by FP64 vector
+ALU work) and of the vector kernel (bound by HBM writes), the single graded
+n = 4096 solve, the serving loop and the extensions as further legs, and a
+bounded sample of the workload solved by the CPU oracle on the host cores,
+against which the GPU outputs are checked at the 1e-13 relative bar.
 """
 from __future__ import annotations
 
@@ -45,7 +49,12 @@ F_DD = 28         # b in double-double: e (1), 1/e (1), the rest of TwoSum(d_j, 
                   # bracket end's sum of zeta_j^2 / e_j^2: (1/e)^2 (1), fma (2)
 F_NORM = 7        # eigenvector norm: (e_j - s) - mu (3), 1/(.) (1), c_j r (1), fma(., r, acc) (2)
 
+BATCH_DESC = ("10,000 problems in one plan: n = round(exp U(ln16, ln1024)); even: arrowhead (d~U(-1,1) min gap "
+              "1e-6, z~U(0.1,1), alpha~U(-1,1)), odd: DPR1 (d as above, u = g/|g|, rho~U(0.1,10)); all eigenvalues "
+              "+ vectors (9.6 GB)")
+
 WORKLOADS = {
+    "batch_mixed": (BATCH_DESC, "batch_mixed"),
     "graded_4096": ("single graded arrowhead n=4096: |d| log-uniform [1e-10,1e10] with random signs "
                     "+ 64 clusters of 8 poles (relative gaps ~1e-12), z log-uniform [1e-8,1], alpha=1e-3; "
                     "all eigenvalues + full V (128 MiB)", "single_graded_4096"),
@@ -121,9 +130,11 @@ def measured_peaks(binding, dev):
                    "arrow_probe_copy (1 GiB read + 1 GiB write); best of 5, HIP events"}
 
 
-def batched_leg(args, binding, workloads, dev):
-    """10,000 independent problems (n log-uniform in [16, 1024]; half arrowhead, half DPR1) in one
-    hipGraph-captured plan, against the same problems solved one launch sequence each."""
+def batched_headline(args, workloads, dev, steps, cpu=True):
+    """The metric's workload: 10,000 problems of uneven order in one hipGraph-captured plan (the
+    timed steps), the same plan's kernels timed by their own dispatch events over further eager
+    runs, the algorithmic work from the plan's pass counters, and the same problems solved with
+    one launch sequence per problem."""
     import numpy as np
     import torch
 
@@ -131,44 +142,101 @@ def batched_leg(args, binding, workloads, dev):
 
     probs = workloads.batch_mixed()
     pairs = sum(p.n for p in probs)
-    b = batch.Batch(probs, device=dev, graph=True)
-    b.run()
+    g = batch.Batch(probs, device=dev, graph=not args.no_graph)
+    for _ in range(max(1, args.warmup)):
+        g.run()
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    for _ in range(args.batch_steps):
-        b.run()
+    for _ in range(steps):
+        g.run()
     torch.cuda.synchronize(dev)
-    t_b = (time.perf_counter() - t0) / args.batch_steps
-    out_batched = b.out_pool.clone()
+    elapsed = time.perf_counter() - t0
+    # the plan's five kernels, each timed by the events its dispatch stamps
+    tp = batch.Batch(probs, device=dev, timing=True)
+    tp.run()
+    stages = np.zeros(5)
+    for _ in range(args.timing_runs):
+        tp.run()
+        stages += np.array(tp.timing())
+    stages /= max(1, args.timing_runs)
+    cnt = tp.counters()
+    same_eager = bool(torch.equal(tp.out_pool, g.out_pool))
+    info = tp.info_pool.cpu().numpy().astype(np.uint32)
+    info_counts = {name: int(np.sum((info & bit) != 0)) for name, bit in
+                   (("dd_b", 1), ("remedy_a", 2), ("remedy_b", 4), ("near_zero", 8), ("pole_shift", 512),
+                    ("not_solved", 304))}
+    tp.close()
+    del tp
+    torch.cuda.empty_cache()
+    # one launch sequence per problem, on the same stream
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    b.run_sequential()
+    g.run_sequential()
     torch.cuda.synchronize(dev)
-    t_s = time.perf_counter() - t0
-    same = bool(torch.equal(b.out_pool, out_batched))
-    res = {"workload": "10,000 problems, n = round(exp U(ln16, ln1024)); even: arrowhead (d~U(-1,1), "
-                       "z~U(0.1,1)), odd: DPR1 (u = g/|g|, rho~U(0.1,10)); all eigenvalues + vectors",
-           "eigenpairs": pairs, "ms_batched": t_b * 1e3, "ms_sequential": t_s * 1e3,
-           "eigenpairs_per_s_batched": pairs / t_b, "eigenpairs_per_s_sequential": pairs / t_s,
-           "speedup": t_s / t_b, "graph": True, "sequential_bitwise_equal": same}
-    if not args.no_cpu_baseline:
+    t_seq = time.perf_counter() - t0
+    out = g.out_pool.clone()          # the sequential results, for the comparison below
+    g.run()
+    torch.cuda.synchronize(dev)
+    f_iter = F_RATIONAL if args.root == "rational" else F_BISECT
+    root_flops = f_iter * cnt["root_iter_terms"] + F_DD * cnt["root_dd_terms"] + F_SELECT * cnt["root_plain_terms"]
+    roof = {"kernel": "k_b_stage<false> (root stage)", "bound": "alu", "achieved": root_flops / (stages[1] * 1e-3) / 1e12,
+            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": profiled_traffic("batch_mixed", "k_b_stage<false>"),
+            "flops_per_launch": root_flops}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    vec_bytes = float(sum(8.0 * p.n * p.n + 16.0 * p.n for p in probs))
+    roof_v = {"kernel": "k_b_vec", "bound": "hbm", "achieved": vec_bytes / (stages[4] * 1e-3) / 1e9,
+              "peak": PEAK_HBM / 1e9, "unit": "GB/s", "traffic": profiled_traffic("batch_mixed", "k_b_vec"),
+              "bytes_per_launch": vec_bytes}
+    roof_v["frac"] = roof_v["achieved"] / roof_v["peak"]
+    res = {"value": pairs * steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "steps": steps,
+           "config": {"workload": BATCH_DESC, "problems": len(probs), "eigenpairs_per_step": pairs,
+                      "parallelism": "single GPU", "schedule": "persistent work queues" +
+                      (", hipGraph-captured plan" if not args.no_graph else ", eager launches"),
+                      "root_finder": args.root},
+           "stages_ms": {k: float(v) for k, v in zip(("prologue", "root", "check", "repair", "vectors"), stages)},
+           "stage_timing": {"runs": args.timing_runs,
+                            "how": "an eager plan of the same problems whose five kernels stamp HIP events by their "
+                                   "own dispatches (hipExtLaunchKernel) on the plan's stream; its outputs are "
+                                   "bitwise those of the timed graph plan: " + str(same_eager)},
+           "counters": cnt, "info_counts": info_counts, "roofline": roof, "roofline_vector": roof_v,
+           "per_solve_launch": {"ms": t_seq * 1e3, "eigenpairs_per_s": pairs / t_seq,
+                                "how": "arrow_solve_sequential: the single-problem launch sequence per problem, "
+                                       "back to back on the same stream"}}
+    res["vs_per_solve_launch"] = res["value"] / res["per_solve_launch"]["eigenpairs_per_s"]
+    if cpu:
         import oracle
-        rng = np.random.default_rng(3)
+        threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        oracle.build(force=False)
+        sample = list(range(0, len(probs), args.cpu_every))
         worst_l = worst_v = 0.0
-        idx = rng.choice(len(probs), 24, replace=False)
-        for p in idx:
-            pr = probs[int(p)]
-            lam, V, _, _ = b.result(int(p))
-            ref = (oracle.arrow_eig if pr.kind == 0 else oracle.dpr1_eig)(pr.d, pr.z, pr.scalar)
-            lam_b = out_batched[b.packed.descs[int(p)].lam_off:b.packed.descs[int(p)].lam_off + pr.n]
-            worst_l = max(worst_l, float(np.max(np.abs(lam_b.cpu().numpy() - ref.lam) / np.abs(ref.lam))))
-            off = b.packed.descs[int(p)].vec_off
-            Vb = out_batched[off:off + pr.n * pr.n].view(pr.n, pr.n).t().cpu().numpy()
-            worst_v = max(worst_v, float(np.max(np.abs(Vb - ref.vec) / np.abs(ref.vec))))
-        res["parity"] = {"sample_problems": int(idx.size), "max_rel_err_lambda": worst_l, "max_rel_err_V": worst_v,
+        spairs = 0
+        t_cpu = 0.0
+        for p in sample:
+            pr = probs[p]
+            t1 = time.perf_counter()
+            ref = (oracle.arrow_eig if pr.kind == 0 else oracle.dpr1_eig)(pr.d, pr.z, pr.scalar, threads=threads)
+            t_cpu += time.perf_counter() - t1
+            spairs += pr.n
+            lam, V, _, _ = g.result(p)
+            worst_l = max(worst_l, float(np.max(np.abs(lam.cpu().numpy() - ref.lam) / np.abs(ref.lam))))
+            worst_v = max(worst_v, float(np.max(np.abs(V.cpu().numpy() - ref.vec) / np.abs(ref.vec))))
+        res["cpu_baseline"] = {"value": spairs / t_cpu, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
+                               "sample": f"every {args.cpu_every}th problem of the same 10,000 ({len(sample)} problems, "
+                                         f"{spairs} eigenpairs, every eigenvalue and eigenvector), binary128 oracle, "
+                                         f"{t_cpu:.1f} s wall"}
+        res["parity"] = {"sample_problems": len(sample), "sample_eigenpairs": spairs, "max_rel_err_lambda": worst_l,
+                         "max_rel_err_V": worst_v, "tolerance": 1e-13,
                          "pass": bool(worst_l <= 1e-13 and worst_v <= 1e-13)}
-    b.close()
-    del b, out_batched
+        # the one-launch-per-problem results agree to rounding (other sums' order), checked on the same sample
+        wl = 0.0
+        for p in sample:
+            D = g.packed.descs[p]
+            a = out[D.lam_off:D.lam_off + D.n]
+            b = g.out_pool[D.lam_off:D.lam_off + D.n]
+            wl = max(wl, float(torch.max(torch.abs(a - b) / torch.abs(b)).item()))
+        res["per_solve_launch"]["max_rel_diff_lambda_vs_batched"] = wl
+    g.close()
+    del g, out
     torch.cuda.empty_cache()
     return res
 
@@ -358,117 +426,53 @@ def extensions_leg(args, binding, workloads, dev):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--timing-every", type=int, default=10,
-                    help="record the stage events on every k-th timed step (each event adds a dispatch gap)")
-    ap.add_argument("--workload", default="graded_4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=512, help="eigenpairs the oracle solves for the CPU baseline")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--root", default="rational", choices=["rational", "bisect"],
-                    help="root finder for the extreme eigenvalue of the shifted inverse")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched vs one-launch-per-solve leg")
-    ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
-    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-max-batch", type=int, default=4096, help="most requests one launch may take")
-    ap.add_argument("--no-extensions", action="store_true",
-                    help="skip the Hermitian / reducible / rho < 0 legs")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the eigenpairs are independent, see the sharding notes in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-
+def single_run(args, workload, binding, workloads, dev, steps, cpu=True):
+    """One large problem (graded n = 4096, uniform n = 16384 or n = 512): `steps` full solves back
+    to back, the stage events stamped on every k-th one, the root and vector kernels' rooflines,
+    and (cpu) a bounded oracle sample that also checks the outputs."""
     import numpy as np
     import torch
 
-    from paper_1302_7203_amd import binding, workloads
-
-    desc, gen = WORKLOADS[args.workload]
+    desc, gen = WORKLOADS[workload]
     pr = getattr(workloads, gen)()
     n = pr.n
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     d = torch.from_numpy(pr.d).to(dev)
     z = torch.from_numpy(pr.z).to(dev)
     torch.cuda.synchronize(dev)
-
-    binding.set_option(binding.OPT_ROOT, binding.ROOT_RATIONAL if args.root == "rational" else binding.ROOT_BISECT)
-    binding.set_option(binding.OPT_TIMING, 0)
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):
         out = binding.arrow_eig(d, z, pr.scalar)
     torch.cuda.synchronize(dev)
-
-    stages, sampled = sampled_steps(lambda: binding.arrow_eig(d, z, pr.scalar), args.steps,
+    stages, sampled = sampled_steps(lambda: binding.arrow_eig(d, z, pr.scalar), steps,
                                     max(1, args.timing_every), dev)
     elapsed = sampled["elapsed_s"]
     out = sampled["last"]
-    ms_per_step = elapsed / args.steps * 1e3
-    stages_ms = stages
     cnt = binding.last_counters()
     m = n - 1
-
     f_iter = F_RATIONAL if args.root == "rational" else F_BISECT
     root_flops = m * (f_iter * cnt["root_bisect"] + F_DD * cnt["root_dd"] + F_SELECT * cnt["root_plain"])
-    root_s = stages_ms[2] * 1e-3
-    roof = {"kernel": "k_root", "bound": "alu", "achieved": root_flops / root_s / 1e12,
-            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
-            "traffic": profiled_traffic(args.workload, "k_root<")}
+    roof = {"kernel": "k_root", "bound": "alu", "achieved": root_flops / (stages[2] * 1e-3) / 1e12,
+            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": profiled_traffic(workload, "k_root<"),
+            "flops_per_launch": root_flops}
     roof["frac"] = roof["achieved"] / roof["peak"]
     vec_bytes = 8.0 * n * n + 16.0 * n
-    vec_s = stages_ms[4] * 1e-3
-    roof_v = {"kernel": "k_vec", "bound": "hbm", "achieved": vec_bytes / vec_s / 1e9, "peak": PEAK_HBM / 1e9,
-              "unit": "GB/s", "traffic": profiled_traffic(args.workload, "k_vec<")}
+    roof_v = {"kernel": "k_vec", "bound": "hbm", "achieved": vec_bytes / (stages[4] * 1e-3) / 1e9,
+              "peak": PEAK_HBM / 1e9, "unit": "GB/s", "traffic": profiled_traffic(workload, "k_vec<"),
+              "bytes_per_launch": vec_bytes}
     roof_v["frac"] = roof_v["achieved"] / roof_v["peak"]
-
-    result = {
-        "metric": METRIC,
-        "value": n * args.steps / elapsed,
-        "unit": "eigenpairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": desc, "n": n, "problems_per_step": 1, "parallelism": "single GPU",
-                   "root_finder": args.root},
-        "stages_ms": {k: float(v) for k, v in zip(("front", "sort", "root", "check", "vectors"), stages_ms)},
-        "stage_timing": {"sampled_steps": sampled["sampled_steps"], "every": max(1, args.timing_every),
-                         "how": "HIP events stamped by the kernels' own dispatches (hipExtLaunchKernel) on the "
-                                "solve's stream, on every k-th timed step; root and vectors are the kernels' "
-                                "durations"},
-        "counters": cnt,
-        "roofline": roof,
-        "roofline_vector": roof_v,
-    }
-
-    lam_gpu = out.lam.cpu().numpy()
+    res = {"value": n * steps / elapsed, "unit": "eigenpairs/s", "steps": steps,
+           "ms_per_step": elapsed / steps * 1e3,
+           "config": {"workload": desc, "n": n, "problems_per_step": 1, "parallelism": "single GPU",
+                      "root_finder": args.root},
+           "stages_ms": {k: float(v) for k, v in zip(("front", "sort", "root", "check", "vectors"), stages)},
+           "stage_timing": {"sampled_steps": sampled["sampled_steps"], "every": max(1, args.timing_every),
+                            "how": "HIP events stamped by the kernels' own dispatches (hipExtLaunchKernel) on the "
+                                   "solve's stream, on every k-th timed step; root and vectors are the kernels' "
+                                   "durations"},
+           "counters": cnt, "roofline": roof, "roofline_vector": roof_v}
     info = out.info.cpu().numpy().astype(np.uint32)
-    result["info_counts"] = {name: int(np.sum((info & bit) != 0)) for name, bit in
-                             (("dd_b", 1), ("remedy_a", 2), ("remedy_b", 4), ("near_zero", 8), ("not_solved", 304))}
-
-    peaks = measured_peaks(binding, dev)
-    result["measured_peaks"] = peaks
-    roof["frac_of_measured"] = roof["achieved"] / peaks["fp64_fma_tflops"]
-    roof_v["frac_of_measured"] = roof_v["achieved"] / peaks["store_gbs"]
-    if not args.no_batch:
-        result["batched"] = batched_leg(args, binding, workloads, dev)
-    if not args.no_serve:
-        result["serving"] = serving_leg(args, dev)
-    if not args.no_extensions:
-        result["extensions"] = extensions_leg(args, binding, workloads, dev)
-
-    if not args.no_cpu_baseline:
+    res["info_counts"] = {name: int(np.sum((info & bit) != 0)) for name, bit in
+                          (("dd_b", 1), ("remedy_a", 2), ("remedy_b", 4), ("near_zero", 8), ("not_solved", 304))}
+    if cpu:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
         step = max(1, n // args.cpu_sample)
@@ -477,16 +481,103 @@ def main():
         t0 = time.perf_counter()
         ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks, threads=threads)
         t_cpu = time.perf_counter() - t0
-        result["cpu_baseline"] = {
+        res["cpu_baseline"] = {
             "value": ks.size / t_cpu, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{ks.size} of {n} eigenpairs (every {step}th, eigenvalue + full eigenvector) of the "
                       f"same workload, binary128 oracle, {t_cpu:.1f} s wall"}
         Vs = out.V[:, torch.from_numpy(ks).to(dev)].cpu().numpy()
-        el = np.abs(lam_gpu[ks] - ref.lam) / np.abs(ref.lam)
+        el = np.abs(out.lam.cpu().numpy()[ks] - ref.lam) / np.abs(ref.lam)
         ev = np.abs(Vs - ref.vec) / np.abs(ref.vec)
-        result["parity"] = {"sample_eigenpairs": int(ks.size), "max_rel_err_lambda": float(el.max()),
-                            "max_rel_err_V": float(ev.max()), "tolerance": 1e-13,
-                            "pass": bool(el.max() <= 1e-13 and ev.max() <= 1e-13)}
+        res["parity"] = {"sample_eigenpairs": int(ks.size), "max_rel_err_lambda": float(el.max()),
+                         "max_rel_err_V": float(ev.max()), "tolerance": 1e-13,
+                         "pass": bool(el.max() <= 1e-13 and ev.max() <= 1e-13)}
+    del out, d, z
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 batched runs, or 40 single solves)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--timing-every", type=int, default=10,
+                    help="single solves: record the stage events on every k-th timed step (each event adds a "
+                         "dispatch gap)")
+    ap.add_argument("--timing-runs", type=int, default=3, help="batched: eager runs whose kernels are timed")
+    ap.add_argument("--workload", default="batch_mixed", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-graph", action="store_true", help="batched: time eager launches instead of the graph")
+    ap.add_argument("--cpu-sample", type=int, default=512,
+                    help="single solves: eigenpairs the oracle solves for the CPU baseline")
+    ap.add_argument("--cpu-every", type=int, default=50, help="batched: the oracle solves every k-th problem")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--root", default="rational", choices=["rational", "bisect"],
+                    help="root finder for the extreme eigenvalue of the shifted inverse")
+    ap.add_argument("--no-single", action="store_true", help="batched headline: skip the single n=4096 solve leg")
+    ap.add_argument("--single-steps", type=int, default=40)
+    ap.add_argument("--no-batch", action="store_true", help="single headline: skip the batched leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-batch", type=int, default=4096, help="most requests one launch may take")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the Hermitian / reducible / rho < 0 legs")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the calibration kernels")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (every eigenpair and every "
+              f"problem is independent: the work would shard by whole problems, or by eigenvalue ranges of one "
+              f"problem, with no collective on the solve path)", file=sys.stderr)
+        sys.exit(2)
+    batched = args.workload == "batch_mixed"
+    if args.steps is None:
+        args.steps = 20 if batched else 40
+
+    import torch
+
+    from paper_1302_7203_amd import binding, workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    binding.set_option(binding.OPT_ROOT, binding.ROOT_RATIONAL if args.root == "rational" else binding.ROOT_BISECT)
+    binding.set_option(binding.OPT_TIMING, 0)
+
+    head = batched_headline(args, workloads, dev, args.steps, cpu=not args.no_cpu_baseline) if batched else \
+        single_run(args, args.workload, binding, workloads, dev, args.steps, cpu=not args.no_cpu_baseline)
+    result = {
+        "metric": METRIC,
+        "value": head.pop("value"),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": head.pop("config"),
+    }
+    head.pop("unit", None)
+    head.pop("steps", None)
+    result.update(head)
+    if not args.no_peaks:
+        peaks = measured_peaks(binding, dev)
+        result["measured_peaks"] = peaks
+        result["roofline"]["frac_of_measured"] = result["roofline"]["achieved"] / peaks["fp64_fma_tflops"]
+        result["roofline_vector"]["frac_of_measured"] = result["roofline_vector"]["achieved"] / peaks["store_gbs"]
+    if batched and not args.no_single:
+        result["single_graded_4096"] = single_run(args, "graded_4096", binding, workloads, dev, args.single_steps,
+                                                  cpu=not args.no_cpu_baseline)
+    if not batched and not args.no_batch:
+        result["batched"] = batched_headline(args, workloads, dev, 5, cpu=False)
+    if not args.no_serve:
+        result["serving"] = serving_leg(args, dev)
+    if not args.no_extensions:
+        result["extensions"] = extensions_leg(args, binding, workloads, dev)
     print(json.dumps(result))
 
 

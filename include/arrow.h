@@ -66,7 +66,7 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_N_MAX 33554432
 
 /* options for arrow_set_option */
-#define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 10) */
+#define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 30) */
 #define ARROW_OPT_TAU_ZERO 2   /* (|d_i|+|mu|)/|lambda| above which Remark 1 applies (default 10) */
 #define ARROW_OPT_FP64_B 3     /* 1: b in FP64 only (Algorithm 2), a negative control (default 0) */
 #define ARROW_OPT_REMEDIES 4   /* 0: no K_nu / near-zero remedies (default 1) */
@@ -80,6 +80,9 @@ typedef struct arrow_handle_s* arrow_handle_t;
                                   runs only above it.  0 = always double-double (default).  With a
                                   bound of a few, eigenvalues carry about K_b times the FP64 sums'
                                   rounding instead of double-double's: a few ulps to ~1e-14 */
+#define ARROW_OPT_CHECK_LANES 9 /* batched plans: lanes per eigenvalue in the check stage (K_nu test,
+                                  Remark 2 remedies, norms): 4, 8, 16 (default), 32 or 64, or 0 for
+                                  those of the first pass */
 
 /* Create a handle on HIP device `device`.  *h receives the handle. */
 int arrow_create(arrow_handle_t* h, int device);
@@ -243,6 +246,8 @@ typedef struct {
 typedef struct arrow_batch_s* arrow_batch_t;
 
 #define ARROW_BATCH_GRAPH 1   /* capture the plan's launches in a HIP graph on its first run */
+#define ARROW_BATCH_TIMING 2  /* (without ARROW_BATCH_GRAPH) every run stamps HIP events at the start and end
+                                 of each of its five kernels, by the kernels' own dispatches */
 
 /* Device bytes a plan for these problems needs (descriptor tables + per-problem workspace). */
 size_t arrow_batch_workspace_size(int64_t count, const arrow_desc_t* descs);
@@ -268,6 +273,26 @@ int arrow_batch_run(arrow_batch_t plan);
 
 /* Synchronise the handle's stream and free the plan (and its own workspace). */
 int arrow_batch_destroy(arrow_batch_t plan);
+
+/*
+ * Diagnostics of a plan.
+ *
+ * arrow_batch_timing: ms[0..4] receive the durations (milliseconds) of the five
+ *   kernels of the plan's latest run -- prologue (sort, weights, corner), root
+ *   stage (shift, b, root of the inverse, for every eigenvalue), check stage
+ *   (K_nu, norms, the repair list), repairs, vectors -- from the events their
+ *   dispatches stamped (ARROW_BATCH_TIMING).  Waits for that run.
+ *   ARROW_ERR_STATE when the plan has no timed run.
+ * arrow_batch_counters: out[0..5] receive, summed over all problems p, m_p times
+ *   the bisection (or rational) steps, double-double O(n) passes and plain O(n)
+ *   passes of the root stage (out[0..2]) and of the check stage and repairs
+ *   (out[3..5]) over the eigenvalues of p, m_p being the number of poles a pass
+ *   of p visits; out[6] = sum of the orders.  So out[c] counts pole terms.
+ *   Reads the counters of the plan's latest run (synchronises the stream;
+ *   allocates and frees a small device buffer).
+ */
+int arrow_batch_timing(arrow_batch_t plan, double* ms);
+int arrow_batch_counters(arrow_batch_t plan, double* out);
 
 /* The same problems solved one after another with the single-problem entry
  * points (one launch sequence per problem, on the handle's stream, sharing the

@@ -16,6 +16,7 @@ from . import binding
 from .workloads import KIND_ARROW, KIND_DPR1, KIND_HERM, KIND_SVD, Problem
 
 BATCH_GRAPH = 1
+BATCH_TIMING = 2
 
 
 class ArrowDesc(ctypes.Structure):
@@ -38,8 +39,10 @@ def _setup(L):
     L.arrow_batch_destroy.argtypes = [P]
     L.arrow_solve_batched.argtypes = [P, I64, P, P, P, P]
     L.arrow_solve_sequential.argtypes = [P, I64, P, P, P, P]
+    L.arrow_batch_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    L.arrow_batch_counters.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     for f in ("arrow_batch_create", "arrow_batch_run", "arrow_batch_destroy", "arrow_solve_batched",
-              "arrow_solve_sequential"):
+              "arrow_solve_sequential", "arrow_batch_timing", "arrow_batch_counters"):
         getattr(L, f).restype = I
     L._batch_ready = True
     return L
@@ -110,7 +113,7 @@ class Batch:
 
     def __init__(self, problems: list[Problem], device=None, vectors=True, graph=False, packed: Packed | None = None,
                  in_pool: torch.Tensor | None = None, out_pool: torch.Tensor | None = None,
-                 info_pool: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+                 info_pool: torch.Tensor | None = None, workspace: torch.Tensor | None = None, timing=False):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.packed = packed or pack(problems, vectors=vectors)
         pk = self.packed
@@ -132,7 +135,8 @@ class Batch:
                                       ctypes.c_void_p(self.in_pool.data_ptr()),
                                       ctypes.c_void_p(self.out_pool.data_ptr()),
                                       ctypes.c_void_p(self.info_pool.data_ptr()), ws_ptr, ws_bytes,
-                                      BATCH_GRAPH if graph else 0, ctypes.byref(self.plan))
+                                      (BATCH_GRAPH if graph else 0) | (BATCH_TIMING if timing else 0),
+                                      ctypes.byref(self.plan))
         binding._check(rc, "arrow_batch_create")
 
     def run(self):
@@ -149,6 +153,22 @@ class Batch:
                                               ctypes.c_void_p(self.out_pool.data_ptr()),
                                               ctypes.c_void_p(self.info_pool.data_ptr()))
         binding._check(rc, "arrow_solve_sequential")
+
+    def timing(self) -> list[float]:
+        """Durations (ms) of the latest timed run's kernels: prologue, root, check, repairs, vectors."""
+        ms = (ctypes.c_double * 5)()
+        binding._check(lib().arrow_batch_timing(self.plan, ms), "arrow_batch_timing")
+        return list(ms)
+
+    def counters(self) -> dict:
+        """Pole terms visited by the latest run's passes, summed over problems (m_p x steps)."""
+        out = (ctypes.c_double * 7)()
+        with torch.cuda.device(self.device):
+            binding._bind_stream(self.h, self.device)
+            binding._check(lib().arrow_batch_counters(self.plan, out), "arrow_batch_counters")
+        keys = ("root_iter_terms", "root_dd_terms", "root_plain_terms", "check_iter_terms", "check_dd_terms",
+                "check_plain_terms", "eigenpairs")
+        return {k: float(v) for k, v in zip(keys, out)}
 
     def result(self, p: int):
         """(values, vectors or None, left vectors or None, info or None) views of problem p."""

@@ -39,6 +39,7 @@ OPT_LANES = 5
 OPT_TIMING = 6
 OPT_ROOT = 7
 OPT_TAU_B = 8
+OPT_CHECK_LANES = 9
 ROOT_BISECT = 0
 ROOT_RATIONAL = 1
 NOALLOC_N_MAX = 32768   # ARROW_NOALLOC_N_MAX: largest order arrow_eig_noalloc takes

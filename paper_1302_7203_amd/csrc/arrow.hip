@@ -215,8 +215,8 @@ __global__ __launch_bounds__(ROOT_BLOCK) void k_check(ProbDesc D, Options opt) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // blocks of ROOT_BLOCK, or CHECK_LANE_BLOCK
   const int k = (int)(gid / G);
   if (k >= D.n) return;
-  if constexpr (STAGE) check_body<KIND, G, true, true>(D, opt, k, (int)(gid % G), lds, lds + sorted_count(D));
-  else check_body<KIND, G, false, true>(D, opt, k, (int)(gid % G));
+  if constexpr (STAGE) check_body<KIND, G, true, DEFER_ALL>(D, opt, k, (int)(gid % G), lds, lds + sorted_count(D));
+  else check_body<KIND, G, false, DEFER_ALL>(D, opt, k, (int)(gid % G));
 }
 
 // The eigenvalues k_check deferred (Remarks 1 and 2, the DPR1 re-measure),
@@ -462,7 +462,8 @@ int arrow_create(arrow_handle_t* h, int device) {
   if (!p) return ARROW_ERR_NOMEM;
   p->device = device;
   p->stream = nullptr;
-  p->opt.tau_nu = 10.0;
+  p->opt.tau_nu = 30.0;
+  p->opt.check_lanes = 16;
   p->opt.tau_zero = 10.0;
   p->opt.fp64_b = 0;
   p->opt.tau_b = 0.0;
@@ -530,6 +531,12 @@ int arrow_set_option(arrow_handle_t h, int option, double value) {
       if (value != 0.0 && value != 1.0) return -3;
       h->opt.root = (int)value;
       return ARROW_OK;
+    case ARROW_OPT_CHECK_LANES: {
+      const int g = (int)value;
+      if (!((double)g == value && (g == 0 || (g >= 4 && g <= 64 && (g & (g - 1)) == 0)))) return -3;
+      h->opt.check_lanes = g;
+      return ARROW_OK;
+    }
     case ARROW_OPT_TIMING:
       if (value != 0.0 && !h->ev_made) {
         DeviceGuard g(h->device);

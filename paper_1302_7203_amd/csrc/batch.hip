@@ -6,9 +6,10 @@
 //               items from an atomic queue and runs the first pass (shift,
 //               b, root of the inverse) on them; problems are queued by
 //               decreasing order n so the long items start first
-//   k_b_stage   the same queue again for the K_nu test and norms; eigenvalues
-//               that need a repair (Remarks 1-2, DPR1 re-measure) are listed
-//   k_b_repair  the listed repairs, a block per eigenvalue; then the
+//   k_b_stage   the same queue again for the K_nu test, the remedies of Remark 2
+//               and the DPR1 re-measure, and the norms; eigenvalues near the
+//               origin (Remark 1) are listed
+//   k_b_repair  the listed Remark 1 repairs, a block per eigenvalue; then the
 //               eigenpairs of a deflated arrowhead (Sec. 1) are placed
 //   k_b_vec     every problem's vector tiles (row tiles for large n, flat
 //               column-major runs for small n) mapped onto blocks
@@ -17,6 +18,7 @@
 // consecutive eigenvalues of one problem; G comes from the handle's table of
 // lanes by order n (filled by the autotuner).
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -43,9 +45,12 @@ struct BatchArgs {
   const int32_t* lanes;      // G per problem
   const int32_t* vec_start;  // count + 1 prefix sums of vector tiles
   const int32_t* vec_mode;   // per problem: 0 flat tiles, 1 row tiles, 2 row tiles with 16-byte stores
+  const int32_t* check_start;// count + 1 prefix sums of check-stage items
+  const int32_t* check_lanes;// lanes per eigenvalue in the check stage, per problem
   uint32_t* counters;        // [0] first-pass queue, [1] check queue
   int32_t count;
   int32_t total_items;
+  int32_t total_check;
 };
 
 __device__ inline int find_problem(const int32_t* start, int count, int x) {
@@ -78,7 +83,9 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
 
 template <bool CHECK, int KIND, int G>
 __device__ inline void run_item(const ProbDesc& D, const Options& opt, int k, int ln) {
-  if (CHECK) check_body<KIND, G, false, true>(D, opt, k, ln);   // repairs listed for k_b_repair
+  // Remark 2 and the DPR1 re-measure on the item's G lanes; only Remark 1 is
+  // listed for k_b_repair (its exact sum of f(0) runs on a whole block)
+  if (CHECK) check_body<KIND, G, false, DEFER_NEAR_ZERO>(D, opt, k, ln);
   else root_body<KIND, G>(D, opt, k, ln);
 }
 
@@ -93,27 +100,40 @@ __device__ inline void run_kind(const ProbDesc& D, const Options& opt, int G, in
   }
 }
 
+// Items are taken from the queue a chunk at a time (one atomic per chunk): the
+// queue counter is a single L2 address, and with one atomic per item its
+// serialised updates (a few ns each over ~10^6 items) set the stage's time.
+// The check stage's items are short and alike, so its chunks are longer.
+constexpr int ROOT_CHUNK = 2;
+constexpr int CHECK_CHUNK = 8;
+
 // at least four wavefronts per SIMD: the pole loads come from L2 and need company to hide
 template <bool CHECK>
 __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_stage(BatchArgs B,
                                                                                                  Options opt) {
+  constexpr int CHUNK = CHECK ? CHECK_CHUNK : ROOT_CHUNK;
   const int lane = threadIdx.x & (WAVE - 1);
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = (int)atomicAdd(&B.counters[CHECK ? 1 : 0], 1u);
-    item = __shfl(item, 0);
-    if (item >= B.total_items) break;
-    const int p = find_problem(B.item_start, B.count, item);
-    const ProbDesc D = B.descs[p];
-    const int G = B.lanes[p];
-    const int k = (item - B.item_start[p]) * (WAVE / G) + lane / G;
-    const int ln = lane & (G - 1);
-    if (k < D.n) {
-      switch (D.kind) {
-        case KIND_ARROW:
-        case KIND_HERM: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
-        case KIND_DPR1: run_kind<CHECK, KIND_DPR1>(D, opt, G, k, ln); break;
-        default: run_kind<CHECK, KIND_SVD>(D, opt, G, k, ln); break;
+    int first = 0;
+    if (lane == 0) first = (int)atomicAdd(&B.counters[CHECK ? 1 : 0], (unsigned)CHUNK);
+    first = __shfl(first, 0);
+    const int total = CHECK ? B.total_check : B.total_items;
+    if (first >= total) break;
+    const int last = min(first + CHUNK, total);
+    const int32_t* start = CHECK ? B.check_start : B.item_start;
+    for (int item = first; item < last; ++item) {
+      const int p = find_problem(start, B.count, item);
+      const ProbDesc D = B.descs[p];
+      const int G = CHECK ? B.check_lanes[p] : B.lanes[p];
+      const int k = (item - start[p]) * (WAVE / G) + lane / G;
+      const int ln = lane & (G - 1);
+      if (k < D.n) {
+        switch (D.kind) {
+          case KIND_ARROW:
+          case KIND_HERM: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
+          case KIND_DPR1: run_kind<CHECK, KIND_DPR1>(D, opt, G, k, ln); break;
+          default: run_kind<CHECK, KIND_SVD>(D, opt, G, k, ln); break;
+        }
       }
     }
   }
@@ -177,6 +197,31 @@ __global__ __launch_bounds__(BLOCK) void k_b_vec(BatchArgs B) {
   }
 }
 
+// diagnostics: per problem, the six pass counters of the root and check stages
+// summed over its eigenvalues, and the number of poles a pass visits
+__global__ __launch_bounds__(BLOCK) void k_b_counters(BatchArgs B, long long* out) {
+  __shared__ unsigned long long part[6];
+  const ProbDesc D = B.descs[blockIdx.x];
+  const Ws w = ws_view(D.ws, D.n);
+  if (threadIdx.x < 6) part[threadIdx.x] = 0ull;
+  __syncthreads();
+  long long s[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < D.n; k += blockDim.x)
+    for (int c = 0; c < 6; ++c) s[c] += w.cnt[6 * k + c];
+  for (int c = 0; c < 6; ++c)
+    if (s[c]) atomicAdd(&part[c], (unsigned long long)s[c]);
+  __syncthreads();
+  if (threadIdx.x < 6) out[7 * (int64_t)blockIdx.x + threadIdx.x] = (long long)part[threadIdx.x];
+  if (threadIdx.x == 6) out[7 * (int64_t)blockIdx.x + 6] = reduced_m(w);
+}
+
+// a launch whose start and end events, when given, are stamped by the dispatch itself
+template <typename F, typename... Args>
+void launch_ev(F kern, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0) hipExtLaunchKernelGGL(kern, grid, block, 0u, st, e0, e1, 0u, args...);
+  else hipLaunchKernelGGL(kern, grid, block, 0, st, args...);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -193,12 +238,16 @@ struct arrow_batch_s {
   int own_dev;          // dev allocated by the plan
   size_t dev_bytes;
   std::vector<ProbDesc> descs;
-  std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1), vec_mode (count)
+  std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1), vec_mode (count),
+                               // check_start (count+1), check_lanes (count)
   BatchArgs args;
   int persistent_blocks;
   hipGraph_t graph;
   hipGraphExec_t exec;
   int captured;
+  hipEvent_t ev[10];    // ARROW_BATCH_TIMING: start and end of each of the five kernels
+  int ev_made;
+  int timed_runs;
   uint32_t magic;
 };
 
@@ -216,7 +265,7 @@ static Layout plan_layout(int64_t count, const arrow_desc_t* descs) {
   L.off_desc = off;
   off = align_up(off + (size_t)count * sizeof(ProbDesc), 256);
   L.off_tab = off;
-  off = align_up(off + (size_t)(4 * count + 2) * sizeof(int32_t), 256);
+  off = align_up(off + (size_t)(6 * count + 3) * sizeof(int32_t), 256);
   L.off_ws = off;
   for (int64_t p = 0; p < count; ++p) off += align_up(ws_doubles(descs[p].n) * sizeof(double), 256);
   L.total = off;
@@ -309,14 +358,16 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t c) { return descs[a].n > descs[c].n; });
   b->descs.resize((size_t)count);
-  b->tabs.assign((size_t)(4 * count + 2), 0);
+  b->tabs.assign((size_t)(6 * count + 3), 0);
   int32_t* item_start = b->tabs.data();
   int32_t* lanes = item_start + count + 1;
   int32_t* vec_start = lanes + count;
   int32_t* vec_mode = vec_start + count + 1;
+  int32_t* check_start = vec_mode + count;
+  int32_t* check_lanes = check_start + count + 1;
   char* base = (char*)b->dev;
   size_t wsoff = L.off_ws;
-  int64_t items = 0, vchunks = 0;
+  int64_t items = 0, vchunks = 0, citems = 0;
   for (int64_t q = 0; q < count; ++q) {
     const arrow_desc_t& a = descs[order[(size_t)q]];
     ProbDesc D{};
@@ -339,6 +390,10 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     lanes[q] = G;
     item_start[q] = (int32_t)items;
     items += (a.n + (WAVE / G) - 1) / (WAVE / G);
+    const int Gc = b->opt.check_lanes ? b->opt.check_lanes : G;
+    check_lanes[q] = Gc;
+    check_start[q] = (int32_t)citems;
+    citems += (a.n + (WAVE / Gc) - 1) / (WAVE / Gc);
     vec_start[q] = (int32_t)vchunks;
     if (D.V && a.kind == ARROW_KIND_HERM) {
       const int64_t n = a.n;
@@ -358,7 +413,8 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   }
   item_start[count] = (int32_t)items;
   vec_start[count] = (int32_t)vchunks;
-  if (items > INT32_MAX / 2 || vchunks > INT32_MAX / 2) {
+  check_start[count] = (int32_t)citems;
+  if (items > INT32_MAX / 2 || vchunks > INT32_MAX / 2 || citems > INT32_MAX / 2) {
     if (b->own_dev) (void)hipFree(b->dev);
     delete b;
     return -2;
@@ -381,6 +437,9 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   A.lanes = A.item_start + count + 1;
   A.vec_start = A.lanes + count;
   A.vec_mode = A.vec_start + count + 1;
+  A.check_start = A.vec_mode + count;
+  A.check_lanes = A.check_start + count + 1;
+  A.total_check = (int32_t)citems;
   A.counters = (uint32_t*)base;
   A.count = (int32_t)count;
   A.total_items = b->total_items;
@@ -388,6 +447,11 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   const int64_t want = (int64_t)h->cus * 16 * WAVE / STAGE_BLOCK;
   const int64_t need = ((int64_t)items * WAVE + STAGE_BLOCK - 1) / STAGE_BLOCK;
   b->persistent_blocks = (int)std::max<int64_t>(1, std::min(want, need));
+  if ((flags & ARROW_BATCH_TIMING) && !(flags & ARROW_BATCH_GRAPH)) {
+    b->ev_made = 1;
+    for (int e = 0; e < 10; ++e)
+      if (hipEventCreate(&b->ev[e]) != hipSuccess) b->ev_made = 0;
+  }
   b->magic = BATCH_MAGIC;
   *plan = b;
   return ARROW_OK;
@@ -396,12 +460,16 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
 static int batch_launch(arrow_batch_s* b, hipStream_t st) {
   const BatchArgs A = b->args;
   const Options opt = b->opt;   // fixed at creation, so eager and graph runs agree
-  hipLaunchKernelGGL(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), 0, st, A);
-  hipLaunchKernelGGL((k_b_stage<false>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
-  hipLaunchKernelGGL((k_b_stage<true>), dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), 0, st, A, opt);
-  hipLaunchKernelGGL(k_b_repair, dim3((unsigned)(b->count * b->repair_per)), dim3(REPAIR_BLOCK), 0, st, A, opt,
-                     b->repair_per);
-  if (b->total_vec > 0) hipLaunchKernelGGL(k_b_vec, dim3((unsigned)b->total_vec), dim3(BLOCK), 0, st, A);
+  const bool tm = b->ev_made && !(b->flags & ARROW_BATCH_GRAPH);
+  auto ev = [&](int e) -> hipEvent_t { return tm ? b->ev[e] : nullptr; };
+  launch_ev(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), st, ev(0), ev(1), A);
+  launch_ev(k_b_stage<false>, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(2), ev(3), A, opt);
+  launch_ev(k_b_stage<true>, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(4), ev(5), A, opt);
+  launch_ev(k_b_repair, dim3((unsigned)(b->count * b->repair_per)), dim3(REPAIR_BLOCK), st, ev(6), ev(7), A, opt,
+            b->repair_per);
+  if (b->total_vec > 0) launch_ev(k_b_vec, dim3((unsigned)b->total_vec), dim3(BLOCK), st, ev(8), ev(9), A);
+  else if (tm) { (void)hipEventRecord(b->ev[8], st); (void)hipEventRecord(b->ev[9], st); }
+  if (tm) b->timed_runs += 1;
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
 
@@ -430,10 +498,50 @@ int arrow_batch_run(arrow_batch_t b) {
   return hipGraphLaunch(b->exec, st) == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
 
+int arrow_batch_timing(arrow_batch_t b, double* ms) {
+  if (!b || b->magic != BATCH_MAGIC || !valid(b->h)) return -1;
+  if (!ms) return -2;
+  if (!b->ev_made || b->timed_runs < 1) return ARROW_ERR_STATE;
+  DeviceGuard g(b->h->device);
+  if (hipEventSynchronize(b->ev[9]) != hipSuccess) return ARROW_ERR_HIP;
+  for (int k = 0; k < 5; ++k) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, b->ev[2 * k], b->ev[2 * k + 1]) != hipSuccess) return ARROW_ERR_HIP;
+    ms[k] = (double)t;
+  }
+  return ARROW_OK;
+}
+
+int arrow_batch_counters(arrow_batch_t b, double* out) {
+  if (!b || b->magic != BATCH_MAGIC || !valid(b->h)) return -1;
+  if (!out) return -2;
+  DeviceGuard g(b->h->device);
+  long long* dev = nullptr;
+  const size_t bytes = (size_t)b->count * 7 * sizeof(long long);
+  if (hipMalloc((void**)&dev, bytes) != hipSuccess) return ARROW_ERR_NOMEM;
+  std::vector<long long> host((size_t)b->count * 7);
+  hipLaunchKernelGGL(k_b_counters, dim3((unsigned)b->count), dim3(BLOCK), 0, b->h->stream, b->args, dev);
+  int rc = hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
+  if (rc == ARROW_OK && (hipStreamSynchronize(b->h->stream) != hipSuccess ||
+                         hipMemcpy(host.data(), dev, bytes, hipMemcpyDeviceToHost) != hipSuccess))
+    rc = ARROW_ERR_HIP;
+  (void)hipFree(dev);
+  if (rc != ARROW_OK) return rc;
+  for (int c = 0; c < 7; ++c) out[c] = 0.0;
+  for (int64_t p = 0; p < b->count; ++p) {
+    const double m = (double)host[(size_t)(7 * p + 6)];
+    for (int c = 0; c < 6; ++c) out[c] += m * (double)host[(size_t)(7 * p + c)];
+    out[6] += (double)b->descs[(size_t)p].n;
+  }
+  return ARROW_OK;
+}
+
 int arrow_batch_destroy(arrow_batch_t b) {
   if (!b || b->magic != BATCH_MAGIC) return -1;
   DeviceGuard g(b->h->device);
   (void)hipStreamSynchronize(b->h->stream);
+  if (b->ev_made)
+    for (int e = 0; e < 10; ++e) (void)hipEventDestroy(b->ev[e]);
   if (b->captured) {
     (void)hipGraphExecDestroy(b->exec);
     (void)hipGraphDestroy(b->graph);

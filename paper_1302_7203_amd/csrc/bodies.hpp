@@ -474,10 +474,13 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
 // K_nu test and remedies (Algorithm 5, last part; Remarks 1 and 2), then the
 // eigenvector norm.  Writes the final shift pair and the caller's outputs.
 //
-// DEFER: an eigenvalue that needs one of the O(n)-per-step repairs (Remark 1,
-// Remark 2, the DPR1 re-measure from d_n) is only appended to the problem's
-// repair list and left for a second launch, which runs check_body on the
-// listed eigenvalues with wider lane groups; everything else is finished here.
+// DEFER = DEFER_ALL: an eigenvalue that needs one of the O(n)-per-step repairs
+// (Remark 1, Remark 2, the DPR1 re-measure from d_n) is only appended to the
+// problem's repair list and left for a second launch, which runs check_body on
+// the listed eigenvalues with a whole block each; everything else is finished
+// here.  DEFER = DEFER_NEAR_ZERO: only Remark 1 is listed (its exact sum of f(0)
+// runs on whole wavefronts); Remark 2 and the DPR1 re-measure run here on the
+// caller's G lanes, as the first pass does.
 // The list reuses the sort's rank array, free once the poles are sorted; its
 // length sits in hdr[6] and is cleared by the prologue.
 
@@ -538,7 +541,9 @@ __host__ __device__ inline void defer_repair(const Ws& w, int64_t n, int k, int 
   repair_list(w, n)[at] = (uint32_t)k;
 }
 
-template <int KIND, int G, bool HOT = false, bool DEFER = false>
+constexpr int DEFER_NONE = 0, DEFER_ALL = 1, DEFER_NEAR_ZERO = 2;
+
+template <int KIND, int G, bool HOT = false, int DEFER = DEFER_NONE>
 __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln,
                                            const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);
@@ -577,26 +582,38 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     const double dist_o = fabs(pdiff<KIND>(w.pv1[o], di) + w.mu1[o]);
     const double knu = fabs(mu) / fmin(fabs(mu), dist_o);
     const bool zero_pole = w.hdr[2] != 0.0;
-    if constexpr (DEFER) {
-      if ((quot > opt.tau_zero && !zero_pole) || knu > opt.tau_nu) {
+    const bool near_zero = quot > opt.tau_zero && !zero_pole;
+    if constexpr (DEFER == DEFER_ALL) {
+      if (near_zero || knu > opt.tau_nu) {
         defer_repair(w, D.n, k, ln);
         return;
       }
     }
-    if constexpr (!DEFER) {   // the deferring check stage returned above
-      if (quot > opt.tau_zero && !zero_pole) {
-        // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}, whose
-        // weight rho = 1/f(0) is summed exactly where double-double cannot resolve it
-        int z0 = 0, it = 0, unres = 0;
-        const double l0 = origin_root<KIND, G>(P, ln, lam1, &z0, &unres, &it,
-                                               [&](int* ok) { return f_origin<KIND, G>(D, P, ln, ok); });
-        pv = 0.0; s = 0.0; mu = z0 ? 0.0 : l0;
-        // entries z_j / (d_j - lambda): their scale is the nearest pole's
-        // distance from the origin, which the norm pass below is given
-        off_hint = fabs(pval<KIND>(di));
-        fl |= INFO_NEAR_ZERO;
-        if (unres) fl |= INFO_F0_UNRESOLVED;
-        c_it += it; c_dd += 1;
+    if constexpr (DEFER == DEFER_NEAR_ZERO) {
+      if (near_zero) {
+        defer_repair(w, D.n, k, ln);
+        return;
+      }
+    }
+    if constexpr (DEFER != DEFER_ALL) {   // the fully deferring check stage returned above
+      // Remark 1 runs only where nothing was deferred: its exact sum needs whole wavefronts
+      bool r1 = false;
+      if constexpr (DEFER == DEFER_NONE) r1 = near_zero;
+      if (r1) {
+        if constexpr (DEFER == DEFER_NONE) {
+          // Remark 1: lambda from the absolutely largest eigenvalue of A^{-1}, whose
+          // weight rho = 1/f(0) is summed exactly where double-double cannot resolve it
+          int z0 = 0, it = 0, unres = 0;
+          const double l0 = origin_root<KIND, G>(P, ln, lam1, &z0, &unres, &it,
+                                                 [&](int* ok) { return f_origin<KIND, G>(D, P, ln, ok); });
+          pv = 0.0; s = 0.0; mu = z0 ? 0.0 : l0;
+          // entries z_j / (d_j - lambda): their scale is the nearest pole's
+          // distance from the origin, which the norm pass below is given
+          off_hint = fabs(pval<KIND>(di));
+          fl |= INFO_NEAR_ZERO;
+          if (unres) fl |= INFO_F0_UNRESOLVED;
+          c_it += it; c_dd += 1;
+        }
       } else if (knu > opt.tau_nu) {
         bool done = false;
         const int i2 = (side > 0) ? i - 1 : i + 1;
@@ -652,7 +669,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       const double gap = P.ds[P.nsorted - 2] - dn;
       const double tau = (pv - dn) + s + mu;
       if (tau < 0.5 * gap) {
-        if constexpr (DEFER) {
+        if constexpr (DEFER == DEFER_ALL) {
           defer_repair(w, D.n, k, ln);
           return;
         }

@@ -59,6 +59,7 @@ struct Options {
   int root;          // RootMethod for the extreme eigenvalue of the inverse
   double tau_b;      // > 0: b from an FP64 pass alone where its K_b <= tau_b
                      // (Algorithm 5's test), else the double-double pass; 0: always
+  int check_lanes;   // batched plans: lanes per eigenvalue in the check stage (0: the first pass's)
 };
 
 // Read-only view of one problem after normalisation (sorted order).

@@ -100,10 +100,10 @@ BATCH_OVERHEAD = 8 * ALIGN
 def request_parts(pr: Problem, vectors=True):
     """(outputs, info, rest): arena bytes of a request's results, of its info words, and of
     its share of the batch's input chunk and plan workspace (inputs, solver workspace,
-    104-byte descriptor and four table words)."""
+    112-byte descriptor and six table words, with room to spare)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 25 * pr.n)) + 128
+    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 25 * pr.n)) + 160
     return out, info, rest
 
 

@@ -35,6 +35,8 @@ def _load():
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
                                 ctypes.c_double]
         L.emu_solve.restype = ctypes.c_int
+        L.emu_set_batch_check.argtypes = [ctypes.c_int]
+        L.emu_set_batch_check.restype = None
         _lib = L
     return _lib
 
@@ -43,7 +45,13 @@ def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def solve(kind, d, z, scalar, vectors=True, tau_nu=10.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1, tau_b=0.0):
+def set_batch_check(on: bool):
+    """Run the check stage as the batched plan does: Remark 2 and the DPR1 re-measure inline,
+    eigenvalues near the origin listed and repaired afterwards."""
+    _load().emu_set_batch_check(1 if on else 0)
+
+
+def solve(kind, d, z, scalar, vectors=True, tau_nu=30.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1, tau_b=0.0):
     """kind 0 arrowhead, 1 DPR1, 2 SVD, 3 Hermitian arrowhead (complex z; complex V).
     Returns dict of numpy arrays (V[:, k] = k-th vector)."""
     d = np.ascontiguousarray(d, dtype=np.float64)

@@ -13,6 +13,10 @@
 
 using namespace ahd;
 
+// 1: the batched plan's check stage -- Remark 2 and the DPR1 re-measure in the
+// check itself, eigenvalues near the origin listed and repaired afterwards
+static int g_batch_check = 0;
+
 template <int KIND>
 static void run(ProbDesc D, const Options& opt, double* U) {
   const int ms = sorted_count(D);
@@ -64,8 +68,16 @@ static void run(ProbDesc D, const Options& opt, double* U) {
   constexpr int SK = KIND == KIND_HERM ? KIND_ARROW : KIND;
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < D.n; ++k) root_body<SK, 1>(D, opt, k, 0);
+  if (g_batch_check) {
+    *repair_count(w) = 0u;
+    for (int k = 0; k < D.n; ++k) check_body<SK, 1, false, DEFER_NEAR_ZERO>(D, opt, k, 0);
+    const uint32_t c = *repair_count(w);
+    if (c > (uint32_t)D.n) abort();
+    for (uint32_t q = 0; q < c; ++q) check_body<SK, 1>(D, opt, (int)repair_list(w, D.n)[q], 0);
+  } else {
 #pragma omp parallel for schedule(dynamic, 4)
-  for (int k = 0; k < D.n; ++k) check_body<SK, 1>(D, opt, k, 0);
+    for (int k = 0; k < D.n; ++k) check_body<SK, 1>(D, opt, k, 0);
+  }
   const int nd = deflated_count(w);
   for (int s = 0; s < nd; ++s) place_deflated(D, w, s);
   if (KIND == KIND_HERM && D.V) {
@@ -91,6 +103,8 @@ static void run(ProbDesc D, const Options& opt, double* U) {
   }
 }
 
+extern "C" void emu_set_batch_check(int on) { g_batch_check = on; }
+
 extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, double scalar, double* lam,
                          double* V, double* U, double* shift, double* mu, uint32_t* info, double tau_nu,
                          double tau_zero, int fp64_b, int remedies, double* kb, int root, int32_t* cnt,
@@ -112,7 +126,7 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   D.mu = mu;
   D.info = info;
   D.ws = ws.data();
-  Options opt{tau_nu, tau_zero, fp64_b, remedies, root, tau_b};
+  Options opt{tau_nu, tau_zero, fp64_b, remedies, root, tau_b, 0};
   if (kind == KIND_ARROW) run<KIND_ARROW>(D, opt, U);
   else if (kind == KIND_DPR1) run<KIND_DPR1>(D, opt, U);
   else if (kind == KIND_HERM) run<KIND_HERM>(D, opt, U);

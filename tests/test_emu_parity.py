@@ -311,3 +311,27 @@ def test_near_zero_hermitian(case, oracle_lib):
     assert_close(r["lam"], ref.lam, "lambda")
     assert_close_c(r["V"], ref.vec, "U")
     assert r["info"][int(np.argmin(np.abs(ref.lam)))] & 8
+
+
+def test_batched_check_stage_order(oracle_lib):
+    """The batched plan's check stage (Remark 2 and the DPR1 re-measure in the check itself,
+    eigenvalues near the origin listed and repaired afterwards) against the oracle, over the
+    mixed problems of the GPU batch tests and the near-zero cases."""
+    import test_gpu_batch as TB
+    probs = TB._mixed(45, 1)
+    probs += [W.Problem(W.KIND_ARROW, d.size + 1, d, z, a) for _, d, z, a in NZ.arrow_cases()]
+    probs += [W.Problem(W.KIND_DPR1, d.size, d, u, r) for _, d, u, r in NZ.dpr1_cases()]
+    emu.set_batch_check(True)
+    try:
+        for p, pr in enumerate(probs):
+            r = emu.solve(pr.kind, pr.d, pr.z, pr.scalar)
+            rl, rV, rU = TB._oracle(pr)
+            assert_close(r["lam"], rl, f"problem {p} values")
+            if pr.kind == W.KIND_HERM:
+                assert_close_c(r["V"], rV, f"problem {p} vectors")
+            else:
+                assert_close(r["V"], rV, f"problem {p} vectors")
+            if rU is not None:
+                assert_close(r["U"], rU, f"problem {p} left vectors")
+    finally:
+        emu.set_batch_check(False)
