@@ -136,7 +136,7 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
  * forbid hipMalloc).  Same arguments, kernels and results as arrow_eig, for
  * 1 <= n <= ARROW_NOALLOC_N_MAX (above it: -2).  Instead of the handle's
  * workspace it uses a scratch array in static device memory, 16 + 25
- * ARROW_NOALLOC_N_MAX doubles (6.25 MiB), which every device the library runs
+ * ARROW_NOALLOC_N_MAX doubles (6.5 MiB), which every device the library runs
  * on holds until the process ends; its address is looked up in arrow_create
  * (ARROW_ERR_HIP if that failed).  It calls no hipMalloc, hipFree or other
  * allocating routine.  The scratch is shared by every arrow_eig_noalloc call on
@@ -354,6 +354,19 @@ int arrow_set_lanes_table(arrow_handle_t h, int scope, int32_t entries, const in
  *   matrix order n (out[6]; a pass visits the n-1 poles, n for DPR1 norms).
  *   Synchronises the stream and copies 24 n bytes to the host.
  */
+/*
+ * arrow_conditions: the condition numbers of the most recent single-problem
+ * call on this handle (arrow_eig, arrow_eig_noalloc, arrow_eig_herm, dpr1_eig,
+ * arrow_svd), per output column: kb[k] = K_b (Sec. 3, eq. (K2)) of the element
+ * b at the shift the first pass chose for the k-th eigenvalue, knu[k] = K_nu
+ * (eq. (K0)), the test that decides the Remark 2 remedies.  kb, knu: device
+ * arrays of n doubles, either may be null; NaN where a value was not
+ * evaluated (n = 1, remedies off, deflated or unsolved eigenpairs).  Copied on
+ * the handle's stream (asynchronous); call it before the handle's next solve,
+ * which reuses the workspace they are kept in.  ARROW_ERR_STATE: no call yet.
+ */
+int arrow_conditions(arrow_handle_t h, double* kb, double* knu);
+
 int arrow_last_timing(arrow_handle_t h, double* ms);
 int arrow_timing_of(arrow_handle_t h, int age, double* ms);
 int arrow_last_counters(arrow_handle_t h, int64_t* out);

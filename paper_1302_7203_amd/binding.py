@@ -82,6 +82,7 @@ def lib():
                 L.arrow_last_timing.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
                 L.arrow_timing_of.argtypes = [P, I, ctypes.POINTER(ctypes.c_double)]
                 L.arrow_last_counters.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+                L.arrow_conditions.argtypes = [P, P, P]
                 L.arrow_set_lanes_table.argtypes = [P, I, ctypes.c_int32, P, P]
                 L.arrow_probe_fma.argtypes = [P, I64, I, P]
                 L.arrow_probe_fill.argtypes = [P, I64, D, P]
@@ -90,7 +91,7 @@ def lib():
                 for f in ("arrow_probe_fma", "arrow_probe_fill", "arrow_probe_copy", "arrow_probe_rcp",
                           "arrow_create", "arrow_destroy", "arrow_set_stream", "arrow_set_option",
                           "arrow_eig", "arrow_eig_noalloc", "arrow_eig_herm", "tridiag_eig", "dpr1_eig", "arrow_svd",
-                          "arrow_last_timing", "arrow_timing_of", "arrow_last_counters",
+                          "arrow_last_timing", "arrow_timing_of", "arrow_last_counters", "arrow_conditions",
                           "arrow_set_lanes_table"):
                     getattr(L, f).restype = ctypes.c_int
                 _lib = L
@@ -179,6 +180,19 @@ def last_counters(device=None) -> dict:
 
 def _ptr(t: torch.Tensor | None):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def conditions(n: int, device=None):
+    """(K_b, K_nu) per output column of the last single-problem call on the default handle
+    of `device` (see arrow_conditions), as float64 tensors of length n on that device."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    h = handle(device)
+    with torch.cuda.device(device):
+        _bind_stream(h, device)
+        kb = torch.empty(n, dtype=torch.float64, device=device)
+        knu = torch.empty(n, dtype=torch.float64, device=device)
+        _check(lib().arrow_conditions(h, _ptr(kb), _ptr(knu)), "arrow_conditions")
+    return kb, knu
 
 
 def _dev_vec(x, n, device, name):

@@ -410,6 +410,7 @@ static int launch_problem(arrow_handle_t h, const ProbDesc& D) {
     h->timed_calls = std::min(h->timed_calls + 1, 2);
   }
   h->last_n = D.n;
+  h->last_ws = D.ws;
   return hipGetLastError() == hipSuccess ? ARROW_OK : ARROW_ERR_HIP;
 }
 
@@ -421,7 +422,7 @@ static bool finite_h(double x) { return x - x == 0.0; }
 // until the process ends).  Host code never uses the array's name as a device
 // address: arrow_create looks up each device's address once, with that device
 // current, and every later use goes through scratch_dev[].
-constexpr size_t NOALLOC_WS_DOUBLES = 16 + (size_t)ARROW_NOALLOC_N_MAX * 25;
+constexpr size_t NOALLOC_WS_DOUBLES = 16 + (size_t)ARROW_NOALLOC_N_MAX * 26;
 static __device__ __align__(256) double scratch[NOALLOC_WS_DOUBLES];
 constexpr int SCRATCH_DEVICES = 64;
 static double* scratch_dev[SCRATCH_DEVICES];
@@ -449,7 +450,7 @@ static double* scratch_of(int device) {
   return scratch_rc[device] == 1 ? scratch_dev[device] : nullptr;
 }
 
-static_assert(NOALLOC_WS_DOUBLES == 16 + (size_t)ARROW_NOALLOC_N_MAX * 25, "workspace of ws_doubles()");
+static_assert(NOALLOC_WS_DOUBLES == 16 + (size_t)ARROW_NOALLOC_N_MAX * 26, "workspace of ws_doubles()");
 
 extern "C" {
 
@@ -577,6 +578,17 @@ int arrow_timing_of(arrow_handle_t h, int age, double* ms) {
 }
 
 int arrow_last_timing(arrow_handle_t h, double* ms) { return arrow_timing_of(h, 0, ms); }
+
+int arrow_conditions(arrow_handle_t h, double* kb, double* knu) {
+  if (!valid(h)) return -1;
+  if (!h->last_ws || h->last_n < 1) return ARROW_ERR_STATE;
+  DeviceGuard g(h->device);
+  const Ws w = ws_view(h->last_ws, h->last_n);
+  const size_t bytes = (size_t)h->last_n * sizeof(double);
+  if (kb && hipMemcpyAsync(kb, w.kbc, bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return ARROW_ERR_HIP;
+  if (knu && hipMemcpyAsync(knu, w.knu, bytes, hipMemcpyDeviceToDevice, h->stream) != hipSuccess) return ARROW_ERR_HIP;
+  return ARROW_OK;
+}
 
 int arrow_last_counters(arrow_handle_t h, int64_t* out) {
   if (!valid(h)) return -1;

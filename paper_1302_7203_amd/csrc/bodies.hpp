@@ -33,7 +33,7 @@ struct ProbDesc {
   double* ws;          // workspace of ws_doubles(n) doubles
 };
 
-__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 25; }
+__host__ __device__ inline size_t ws_doubles(int64_t n) { return 16 + (size_t)n * 26; }
 
 // Workspace of one problem.
 struct Ws {
@@ -67,6 +67,8 @@ struct Ws {
   int32_t* cm;      // per output column: deflated eigenpair index, or -1
   int32_t* iperm;   // caller row -> sorted index
   double* nr1;      // first pass: 1 / ||x|| at the first-pass mu, from the root's last pass (NaN: none)
+  double* kbc;      // per output column: K_b (eq. K2) of the first pass's shift (NaN: none)
+  double* knu;      // per output column: K_nu (eq. K0) of the first pass (NaN: not evaluated)
 };
 
 __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
@@ -83,8 +85,8 @@ __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
   w.pv1 = p; p += N;
   w.mu1 = p; p += N;
   w.kb1 = p; p += N;
-  w.ip1 = (int32_t*)p; p += N;
-  w.fl1 = (uint32_t*)p; p += N;
+  w.ip1 = (int32_t*)p;
+  w.fl1 = (uint32_t*)p + N; p += N;
   w.pv = p; p += N;
   w.sf = p; p += N;
   w.mu = p; p += N;
@@ -99,6 +101,8 @@ __host__ __device__ inline Ws ws_view(double* base, int64_t n) {
   w.cm = (int32_t*)p;
   w.iperm = w.cm + N; p += N;
   w.nr1 = p; p += N;
+  w.kbc = p; p += N;
+  w.knu = p; p += N;
   return w;
 }
 
@@ -376,6 +380,7 @@ __host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, i
   if (D.mu) D.mu[col] = 0.0;
   if (D.info) D.info[col] = INFO_DEFLATED;
   w.pv[col] = v; w.sf[col] = 0.0; w.mu[col] = 0.0; w.inrm[col] = 0.0;
+  w.kbc[col] = NAN; w.knu[col] = NAN;
   w.cm[col] = s;
 }
 
@@ -556,6 +561,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
       w.pv[k] = NAN; w.sf[k] = NAN; w.mu[k] = NAN; w.inrm[k] = NAN;
+      w.kbc[k] = NAN; w.knu[k] = NAN;
       D.lam[k] = NAN;
       if (D.shift) D.shift[k] = NAN;
       if (D.mu) D.mu[k] = NAN;
@@ -569,6 +575,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
   int c_it = 0, c_dd = 0, c_plain = 1;   // the norm pass
   double rn = NAN;   // 1/||x|| from a remedy's last rational pass, when it ran one
   double off_hint = -1.0;   // the norm pass's scale, when it is not |s + mu|
+  double knu_out = NAN;     // K_nu of the first pass, for the outputs
   if (m > 0 && opt.remedies) {
     const int i = w.ip1[k];
     const int side = (k == i) ? +1 : -1;
@@ -581,6 +588,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     const int o = (side > 0) ? k + 1 : k - 1;
     const double dist_o = fabs(pdiff<KIND>(w.pv1[o], di) + w.mu1[o]);
     const double knu = fabs(mu) / fmin(fabs(mu), dist_o);
+    knu_out = knu;
     const bool zero_pole = w.hdr[2] != 0.0;
     const bool near_zero = quot > opt.tau_zero && !zero_pole;
     if constexpr (DEFER == DEFER_ALL) {
@@ -709,6 +717,8 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       }
     }
     w.pv[col] = pv;
+    w.kbc[col] = w.kb1[k];
+    w.knu[col] = knu_out;
     w.sf[col] = s;
     w.mu[col] = mu;
     // q = (D - lambda)^{-1} u for rho < 0 is minus the vector of (-D) + |rho| u u^T

@@ -25,6 +25,7 @@ struct arrow_handle_s {
   int ev_set;         // set of the most recent timed call
   int timed_calls;    // timed calls launched so far, up to 2
   int64_t last_n;
+  double* last_ws;    // workspace of the most recent single-problem call (the handle's, or the scratch)
   size_t lds_max;     // bytes of dynamic LDS one block may use
   int cus;            // compute units of the device
   // lanes per eigenvalue by order n: [ARROW_SCHEDULE_SINGLE] for single

@@ -103,7 +103,7 @@ def request_parts(pr: Problem, vectors=True):
     112-byte descriptor and six table words, with room to spare)."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 25 * pr.n)) + 160
+    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 26 * pr.n)) + 160
     return out, info, rest
 
 

@@ -33,7 +33,7 @@ def _load():
         P = ctypes.c_void_p
         L.emu_solve.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, ctypes.c_double, P, P, P, P, P, P,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
-                                ctypes.c_double]
+                                ctypes.c_double, P]
         L.emu_solve.restype = ctypes.c_int
         L.emu_set_batch_check.argtypes = [ctypes.c_int]
         L.emu_set_batch_check.restype = None
@@ -60,10 +60,10 @@ def solve(kind, d, z, scalar, vectors=True, tau_nu=30.0, tau_zero=10.0, fp64_b=0
     lam = np.empty(n)
     Vb = np.empty((n, n), dtype=np.complex128 if kind == 3 else np.float64) if vectors else None
     Ub = np.empty((n, n)) if (vectors and kind == 2) else None
-    sh, mu, kb = np.empty(n), np.empty(n), np.empty(n)
+    sh, mu, kb, knu = np.empty(n), np.empty(n), np.empty(n), np.empty(n)
     info = np.empty(n, dtype=np.uint32)
     cnt = np.empty((n, 6), dtype=np.int32)
     _load().emu_solve(kind, n, _p(d), _p(z), float(scalar), _p(lam), _p(Vb), _p(Ub), _p(sh), _p(mu), _p(info),
-                      tau_nu, tau_zero, fp64_b, remedies, _p(kb), root, _p(cnt), tau_b)
+                      tau_nu, tau_zero, fp64_b, remedies, _p(kb), root, _p(cnt), tau_b, _p(knu))
     return {"lam": lam, "V": None if Vb is None else Vb.T, "U": None if Ub is None else Ub.T,
-            "shift": sh, "mu": mu, "info": info, "kb": kb, "cnt": cnt}
+            "shift": sh, "mu": mu, "info": info, "kb": kb, "knu": knu, "cnt": cnt}

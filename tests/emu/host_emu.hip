@@ -108,7 +108,7 @@ extern "C" void emu_set_batch_check(int on) { g_batch_check = on; }
 extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, double scalar, double* lam,
                          double* V, double* U, double* shift, double* mu, uint32_t* info, double tau_nu,
                          double tau_zero, int fp64_b, int remedies, double* kb, int root, int32_t* cnt,
-                         double tau_b) {
+                         double tau_b, double* knu) {
   std::vector<double> ws(ws_doubles(n), 0.0);
   ProbDesc D{};
   D.kind = kind;
@@ -134,6 +134,10 @@ extern "C" int emu_solve(int kind, int64_t n, const double* d, const double* z, 
   if (kb) {
     const Ws w = ws_view(D.ws, D.n);
     for (int k = 0; k < D.n; ++k) kb[k] = w.kb1[k];
+  }
+  if (knu) {
+    const Ws w = ws_view(D.ws, D.n);
+    for (int k = 0; k < D.n; ++k) knu[k] = w.knu[k];
   }
   if (cnt) {
     const Ws w = ws_view(D.ws, D.n);

@@ -51,6 +51,11 @@ def test_example3_negative_control_and_kb(oracle_lib):
                   5.217390439488477e9]
     for k in range(1, 6):
         assert abs(good["kb"][k] - kb_printed[k - 1]) <= 1e-6 * kb_printed[k - 1], (k, good["kb"][k])
+    # K_nu (eq. K0) of lambda_6, printed 7.941165469988994; the K_nu ~ 1 values to 1e-6
+    knu_printed = [9.999999090793056e-1, 9.999996083428923e-1, 1.000000117045544, 9.999998561319470e-1,
+                   7.941165469988994]
+    for k in range(1, 6):
+        assert abs(good["knu"][k] - knu_printed[k - 1]) <= 1e-6 * knu_printed[k - 1], (k, good["knu"][k])
 
 
 def test_uniform_512(oracle_lib):

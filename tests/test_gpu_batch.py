@@ -167,8 +167,17 @@ def test_full_size_batch_sampled(env, oracle_lib):
     b = batch.Batch(probs, device=dev, graph=True)
     b.run()
     torch.cuda.synchronize()
+    # 320 problems stratified by kind and by order: 24 from each (kind, octave of n) class up
+    # to n = 512 and 8 from each of (512, 768] and (768, 1024] (the oracle's cost grows as n^2)
     rng = np.random.default_rng(7)
-    idx = sorted(set(int(i) for i in rng.integers(0, len(probs), 40)) | {0, 1, len(probs) - 1})
+    idx = set()
+    for kind in (W.KIND_ARROW, W.KIND_DPR1):
+        for lo, hi, take in ((8, 16, 24), (16, 32, 24), (32, 64, 24), (64, 128, 24), (128, 256, 24),
+                             (256, 512, 24), (512, 768, 8), (768, 1024, 8)):
+            pool = [p for p, pr in enumerate(probs) if pr.kind == kind and lo < pr.n <= hi]
+            idx |= set(int(i) for i in rng.choice(pool, min(take, len(pool)), replace=False))
+    idx = sorted(idx | {0, 1, len(probs) - 1})
+    print(f"10,000-problem plan: oracle for {len(idx)} problems", flush=True)
     _check(b, probs, torch, idx=idx)
     info = b.info_pool.cpu().numpy().astype(np.uint32)
     assert not np.any(info & (16 | 32 | 256))

@@ -80,18 +80,19 @@ def _sample_ks(n, info, step, extra=16):
     return np.array(sorted(ks), dtype=np.int64)
 
 
-def test_graded_4096_sampled(gpu, oracle_lib):
+def test_graded_4096_full(gpu, oracle_lib):
+    """The graded n = 4096 workload in full: every eigenvalue and every entry of V (16.8M)
+    against the oracle."""
     torch, _, _ = gpu
     pr = W.single_graded_4096()
     out = _arrow(gpu, pr.d, pr.z, pr.scalar)
     lam, info = _np(out.lam), _np(out.info).astype(np.uint32)
     assert np.all(info & 1)                       # b in double-double everywhere
     assert np.all(np.diff(lam) < 0)
-    ks = _sample_ks(pr.n, info, 8)
-    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
-    assert_close(lam[ks], ref.lam, "lambda")
-    V = out.V[:, torch.from_numpy(ks).to(out.V.device)].cpu().numpy()
-    assert_close(V, ref.vec, "V columns")
+    print("graded n=4096: oracle for all 4096 eigenpairs", flush=True)
+    ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar)
+    assert_close(lam, ref.lam, "lambda")
+    assert_close(_np(out.V), ref.vec, "V")
 
 
 def test_uniform_16384_sampled(gpu, oracle_lib):
@@ -101,7 +102,12 @@ def test_uniform_16384_sampled(gpu, oracle_lib):
     lam, info = _np(out.lam), _np(out.info).astype(np.uint32)
     # interlacing with the (sorted) poles for every eigenvalue
     assert np.all(lam[:-1] > pr.d) and np.all(pr.d > lam[1:])
-    ks = _sample_ks(pr.n, info, 512)
+    # every 16th eigenpair (1024 eigenvalues and columns, 16.8M entries), every one that
+    # took a remedy, and the ends
+    ks = _sample_ks(pr.n, info, 16)
+    flagged = np.flatnonzero(info & (2 | 4 | 8))
+    ks = np.union1d(ks, flagged).astype(np.int64)
+    print(f"uniform n=16384: oracle for {ks.size} eigenpairs", flush=True)
     ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks)
     assert_close(lam[ks], ref.lam, "lambda")
     V = out.V[:, torch.from_numpy(ks).to(out.V.device)].cpu().numpy()
@@ -481,3 +487,23 @@ def test_fp64_b_where_kb_is_small(gpu, oracle_lib):
                 binding.set_option(binding.OPT_TAU_B, bad)
     finally:
         binding.set_option(binding.OPT_TAU_B, 0.0)
+
+
+def test_example3_conditions_kb_knu(gpu):
+    """arrow_conditions after Example 3 (Sec. 5): the printed K_b (eq. K2) of
+    lambda_2..lambda_6 to 1e-6, and K_nu (eq. K0), printed 7.941165469988994 for
+    lambda_6 and about 1 for the others (their printed digits carry ~1e-7 of the
+    first pass's noise, so 1e-6)."""
+    torch, binding, dev = gpu
+    d, z, a = EXAMPLES["ex3"]
+    _arrow(gpu, d, z, a)
+    kb, knu = binding.conditions(6, dev)
+    torch.cuda.synchronize(dev)
+    kb, knu = kb.cpu().numpy(), knu.cpu().numpy()
+    kb_printed = [3.243243243540540e9, 3.636363636818182e9, 4.444444445000000e9, 5.217390439488477e9,
+                  5.217390439488477e9]
+    knu_printed = [9.999999090793056e-1, 9.999996083428923e-1, 1.000000117045544, 9.999998561319470e-1,
+                   7.941165469988994]
+    for k in range(1, 6):
+        assert abs(kb[k] - kb_printed[k - 1]) <= 1e-6 * kb_printed[k - 1], (k, kb[k])
+        assert abs(knu[k] - knu_printed[k - 1]) <= 1e-6 * knu_printed[k - 1], (k, knu[k])
