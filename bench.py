@@ -179,8 +179,8 @@ def batched_headline(args, workloads, dev, steps, cpu=True):
     torch.cuda.synchronize(dev)
     f_iter = F_RATIONAL if args.root == "rational" else F_BISECT
     root_flops = f_iter * cnt["root_iter_terms"] + F_DD * cnt["root_dd_terms"] + F_SELECT * cnt["root_plain_terms"]
-    roof = {"kernel": "k_b_stage<false> (root stage)", "bound": "alu", "achieved": root_flops / (stages[1] * 1e-3) / 1e12,
-            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": profiled_traffic("batch_mixed", "k_b_stage<false>"),
+    roof = {"kernel": "k_b_root (root stage)", "bound": "alu", "achieved": root_flops / (stages[1] * 1e-3) / 1e12,
+            "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s", "traffic": profiled_traffic("batch_mixed", "k_b_root"),
             "flops_per_launch": root_flops}
     roof["frac"] = roof["achieved"] / roof["peak"]
     vec_bytes = float(sum(8.0 * p.n * p.n + 16.0 * p.n for p in probs))

@@ -81,8 +81,9 @@ typedef struct arrow_handle_s* arrow_handle_t;
                                   bound of a few, eigenvalues carry about K_b times the FP64 sums'
                                   rounding instead of double-double's: a few ulps to ~1e-14 */
 #define ARROW_OPT_CHECK_LANES 9 /* batched plans: lanes per eigenvalue in the check stage (K_nu test,
-                                  Remark 2 remedies, norms): 4, 8, 16 (default), 32 or 64, or 0 for
-                                  those of the first pass */
+                                  norms): 4 (default), 8, 16, 32 or 64, or 0 for those of the first
+                                  pass; the Remark 2 remedies and the DPR1 re-measure that the test
+                                  calls for are re-run on whole wavefronts */
 
 /* Create a handle on HIP device `device`.  *h receives the handle. */
 int arrow_create(arrow_handle_t* h, int device);

@@ -464,7 +464,7 @@ int arrow_create(arrow_handle_t* h, int device) {
   p->device = device;
   p->stream = nullptr;
   p->opt.tau_nu = 30.0;
-  p->opt.check_lanes = 16;
+  p->opt.check_lanes = 4;
   p->opt.tau_zero = 10.0;
   p->opt.fp64_b = 0;
   p->opt.tau_b = 0.0;

@@ -2,13 +2,14 @@
 // uneven order in one plan of five launches.
 //
 //   k_b_prep    one block per problem: sort (Sec. 1 ordering) and prologue
-//   k_b_stage   persistent: every wavefront takes (problem, eigenvalue-group)
+//   k_b_root    persistent: every wavefront takes (problem, eigenvalue-group)
 //               items from an atomic queue and runs the first pass (shift,
 //               b, root of the inverse) on them; problems are queued by
 //               decreasing order n so the long items start first
-//   k_b_stage   the same queue again for the K_nu test, the remedies of Remark 2
-//               and the DPR1 re-measure, and the norms; eigenvalues near the
-//               origin (Remark 1) are listed
+//   k_b_check   a second queue of the same kind for the K_nu test and the
+//               norms; the eigenvalues that need a remedy of Remark 2 or the
+//               DPR1 re-measure are gathered per wavefront and re-solved on
+//               all its lanes; eigenvalues near the origin (Remark 1) are listed
 //   k_b_repair  the listed Remark 1 repairs, a block per eigenvalue; then the
 //               eigenpairs of a deflated arrowhead (Sec. 1) are placed
 //   k_b_vec     every problem's vector tiles (row tiles for large n, flat
@@ -81,22 +82,47 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
   }
 }
 
-template <bool CHECK, int KIND, int G>
-__device__ inline void run_item(const ProbDesc& D, const Options& opt, int k, int ln) {
-  // Remark 2 and the DPR1 re-measure on the item's G lanes; only Remark 1 is
-  // listed for k_b_repair (its exact sum of f(0) runs on a whole block)
-  if (CHECK) check_body<KIND, G, false, DEFER_NEAR_ZERO>(D, opt, k, ln);
-  else root_body<KIND, G>(D, opt, k, ln);
+// First pass of one eigenvalue of an item (G lanes each).
+template <int KIND>
+__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln) {
+  switch (G) {
+    case 4: root_body<KIND, 4>(D, opt, k, ln); break;
+    case 8: root_body<KIND, 8>(D, opt, k, ln); break;
+    case 16: root_body<KIND, 16>(D, opt, k, ln); break;
+    case 32: root_body<KIND, 32>(D, opt, k, ln); break;
+    default: root_body<KIND, 64>(D, opt, k, ln); break;
+  }
 }
 
-template <bool CHECK, int KIND>
-__device__ inline void run_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln) {
+// Check stage of one item: the 64/G eigenvalues k0, k0 + 1, ... of one
+// problem, G lanes each (every lane of the wavefront calls this; lanes past
+// the order idle).  Remark 2 and the DPR1 re-measure -- a few percent of the
+// eigenvalues, each a full re-solve -- are not run on the item's G lanes,
+// which would leave the wavefront's other groups waiting: the eigenvalues that
+// need one are gathered by a ballot and re-run one after the other on all 64
+// lanes.  Only Remark 1 is listed for k_b_repair (its exact sum of f(0) runs on
+// a whole block).
+template <int KIND, int G>
+__device__ inline void check_item(const ProbDesc& D, const Options& opt, int k0, int lane) {
+  const int k = k0 + lane / G, ln = lane & (G - 1);
+  bool need = false;
+  if (k < D.n) need = check_body<KIND, G, false, DEFER_WAVE>(D, opt, k, ln);
+  uint64_t mask = __ballot(need && ln == 0);
+  while (mask) {
+    const int g = __builtin_ctzll(mask) / G;
+    mask &= mask - 1;
+    check_body<KIND, WAVE, false, DEFER_NEAR_ZERO>(D, opt, k0 + g, lane);
+  }
+}
+
+template <int KIND>
+__device__ inline void check_kind(const ProbDesc& D, const Options& opt, int G, int k0, int lane) {
   switch (G) {
-    case 4: run_item<CHECK, KIND, 4>(D, opt, k, ln); break;
-    case 8: run_item<CHECK, KIND, 8>(D, opt, k, ln); break;
-    case 16: run_item<CHECK, KIND, 16>(D, opt, k, ln); break;
-    case 32: run_item<CHECK, KIND, 32>(D, opt, k, ln); break;
-    default: run_item<CHECK, KIND, 64>(D, opt, k, ln); break;
+    case 4: check_item<KIND, 4>(D, opt, k0, lane); break;
+    case 8: check_item<KIND, 8>(D, opt, k0, lane); break;
+    case 16: check_item<KIND, 16>(D, opt, k0, lane); break;
+    case 32: check_item<KIND, 32>(D, opt, k0, lane); break;
+    default: check_item<KIND, 64>(D, opt, k0, lane); break;
   }
 }
 
@@ -108,32 +134,60 @@ constexpr int ROOT_CHUNK = 2;
 constexpr int CHECK_CHUNK = 8;
 
 // at least four wavefronts per SIMD: the pole loads come from L2 and need company to hide
-template <bool CHECK>
-__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_stage(BatchArgs B,
-                                                                                                 Options opt) {
-  constexpr int CHUNK = CHECK ? CHECK_CHUNK : ROOT_CHUNK;
+__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_root(BatchArgs B,
+                                                                                                Options opt) {
   const int lane = threadIdx.x & (WAVE - 1);
   for (;;) {
     int first = 0;
-    if (lane == 0) first = (int)atomicAdd(&B.counters[CHECK ? 1 : 0], (unsigned)CHUNK);
+    if (lane == 0) first = (int)atomicAdd(&B.counters[0], (unsigned)ROOT_CHUNK);
     first = __shfl(first, 0);
-    const int total = CHECK ? B.total_check : B.total_items;
-    if (first >= total) break;
-    const int last = min(first + CHUNK, total);
-    const int32_t* start = CHECK ? B.check_start : B.item_start;
+    if (first >= B.total_items) break;
+    const int last = min(first + ROOT_CHUNK, B.total_items);
     for (int item = first; item < last; ++item) {
-      const int p = find_problem(start, B.count, item);
+      const int p = find_problem(B.item_start, B.count, item);
       const ProbDesc D = B.descs[p];
-      const int G = CHECK ? B.check_lanes[p] : B.lanes[p];
-      const int k = (item - start[p]) * (WAVE / G) + lane / G;
+      const int G = B.lanes[p];
+      const int k = (item - B.item_start[p]) * (WAVE / G) + lane / G;
       const int ln = lane & (G - 1);
       if (k < D.n) {
         switch (D.kind) {
           case KIND_ARROW:
-          case KIND_HERM: run_kind<CHECK, KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
-          case KIND_DPR1: run_kind<CHECK, KIND_DPR1>(D, opt, G, k, ln); break;
-          default: run_kind<CHECK, KIND_SVD>(D, opt, G, k, ln); break;
+          case KIND_HERM: root_kind<KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
+          case KIND_DPR1: root_kind<KIND_DPR1>(D, opt, G, k, ln); break;
+          default: root_kind<KIND_SVD>(D, opt, G, k, ln); break;
         }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_check(BatchArgs B,
+                                                                                                 Options opt) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  // the current problem and its items [p_lo, p_hi), kept across items: items
+  // are short, and those of a chunk are consecutive, so the search runs about
+  // once per chunk
+  int p = 0, p_lo = 0, p_hi = 0;
+  for (;;) {
+    int first = 0;
+    if (lane == 0) first = (int)atomicAdd(&B.counters[1], (unsigned)CHECK_CHUNK);
+    first = __builtin_amdgcn_readfirstlane(first);
+    if (first >= B.total_check) break;
+    const int last = min(first + CHECK_CHUNK, B.total_check);
+    for (int item = first; item < last; ++item) {
+      if (item < p_lo || item >= p_hi) {
+        p = find_problem(B.check_start, B.count, item);
+        p_lo = B.check_start[p];
+        p_hi = B.check_start[p + 1];
+      }
+      const ProbDesc D = B.descs[p];
+      const int G = B.check_lanes[p];
+      const int k0 = (item - p_lo) * (WAVE / G);
+      switch (D.kind) {
+        case KIND_ARROW:
+        case KIND_HERM: check_kind<KIND_ARROW>(D, opt, G, k0, lane); break;   // HERM: the real arrowhead on |z|
+        case KIND_DPR1: check_kind<KIND_DPR1>(D, opt, G, k0, lane); break;
+        default: check_kind<KIND_SVD>(D, opt, G, k0, lane); break;
       }
     }
   }
@@ -463,8 +517,8 @@ static int batch_launch(arrow_batch_s* b, hipStream_t st) {
   const bool tm = b->ev_made && !(b->flags & ARROW_BATCH_GRAPH);
   auto ev = [&](int e) -> hipEvent_t { return tm ? b->ev[e] : nullptr; };
   launch_ev(k_b_prep, dim3((unsigned)b->count), dim3(BLOCK), st, ev(0), ev(1), A);
-  launch_ev(k_b_stage<false>, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(2), ev(3), A, opt);
-  launch_ev(k_b_stage<true>, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(4), ev(5), A, opt);
+  launch_ev(k_b_root, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(2), ev(3), A, opt);
+  launch_ev(k_b_check, dim3((unsigned)b->persistent_blocks), dim3(STAGE_BLOCK), st, ev(4), ev(5), A, opt);
   launch_ev(k_b_repair, dim3((unsigned)(b->count * b->repair_per)), dim3(REPAIR_BLOCK), st, ev(6), ev(7), A, opt,
             b->repair_per);
   if (b->total_vec > 0) launch_ev(k_b_vec, dim3((unsigned)b->total_vec), dim3(BLOCK), st, ev(8), ev(9), A);

@@ -485,7 +485,11 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
 // the listed eigenvalues with a whole block each; everything else is finished
 // here.  DEFER = DEFER_NEAR_ZERO: only Remark 1 is listed (its exact sum of f(0)
 // runs on whole wavefronts); Remark 2 and the DPR1 re-measure run here on the
-// caller's G lanes, as the first pass does.
+// caller's G lanes, as the first pass does.  DEFER = DEFER_WAVE: Remark 1 is
+// listed as for DEFER_NEAR_ZERO; an eigenvalue that needs Remark 2 or the DPR1
+// re-measure writes nothing and makes the call return true, and the caller runs
+// check_body on it again (DEFER_NEAR_ZERO) with all lanes of its wavefront.
+// Every other call returns false.
 // The list reuses the sort's rank array, free once the poles are sorted; its
 // length sits in hdr[6] and is cleared by the prologue.
 
@@ -546,17 +550,17 @@ __host__ __device__ inline void defer_repair(const Ws& w, int64_t n, int k, int 
   repair_list(w, n)[at] = (uint32_t)k;
 }
 
-constexpr int DEFER_NONE = 0, DEFER_ALL = 1, DEFER_NEAR_ZERO = 2;
+constexpr int DEFER_NONE = 0, DEFER_ALL = 1, DEFER_NEAR_ZERO = 2, DEFER_WAVE = 3;
 
 template <int KIND, int G, bool HOT = false, int DEFER = DEFER_NONE>
-__host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt, int k, int ln,
+__host__ __device__ inline bool check_body(const ProbDesc& D, const Options& opt, int k, int ln,
                                            const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);
   const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
   const uint32_t pf = *prob_flags(w);
   if (k >= P.n) {
     if (ln == 0) { w.cnt[6 * k + 3] = 0; w.cnt[6 * k + 4] = 0; w.cnt[6 * k + 5] = 0; }
-    return;
+    return false;
   }
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
@@ -567,7 +571,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       if (D.mu) D.mu[k] = NAN;
       if (D.info) D.info[k] = pf;
     }
-    return;
+    return false;
   }
   double pv = w.pv1[k], s = 0.0, mu = w.mu1[k];
   uint32_t fl = w.fl1[k];
@@ -594,14 +598,17 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     if constexpr (DEFER == DEFER_ALL) {
       if (near_zero || knu > opt.tau_nu) {
         defer_repair(w, D.n, k, ln);
-        return;
+        return false;
       }
     }
-    if constexpr (DEFER == DEFER_NEAR_ZERO) {
+    if constexpr (DEFER == DEFER_NEAR_ZERO || DEFER == DEFER_WAVE) {
       if (near_zero) {
         defer_repair(w, D.n, k, ln);
-        return;
+        return false;
       }
+    }
+    if constexpr (DEFER == DEFER_WAVE) {
+      if (knu > opt.tau_nu) return true;
     }
     if constexpr (DEFER != DEFER_ALL) {   // the fully deferring check stage returned above
       // Remark 1 runs only where nothing was deferred: its exact sum needs whole wavefronts
@@ -679,8 +686,9 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
       if (tau < 0.5 * gap) {
         if constexpr (DEFER == DEFER_ALL) {
           defer_repair(w, D.n, k, ln);
-          return;
+          return false;
         }
+        if constexpr (DEFER == DEFER_WAVE) return true;
         int it = 0;
         const double t2 = dpr1_from_last_pole<G>(P, tau, ln, &it);
         pv = dn; s = 0.0; mu = t2;
@@ -729,6 +737,7 @@ __host__ __device__ inline void check_body(const ProbDesc& D, const Options& opt
     if (D.mu) D.mu[col] = sg * mu;
     if (D.info) D.info[col] = fl;
   }
+  return false;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,7 +1,13 @@
 // Double-double arithmetic on FP64, written from the published error-free
 // transformations: TwoSum (Knuth, TAOCP vol. 2, 4.2.2), FastTwoSum (Dekker
-// 1971), TwoProd through one fused multiply-add, and the usual double-double
-// add/mul/div built from them.  A value is the unevaluated sum hi + lo with
+// 1971), TwoProd through one fused multiply-add, and the double-double
+// add/mul/div built from them.  dd_add (two TwoSums, the low parts added and
+// renormalised twice) and dd_div (three quotient digits) follow the
+// "accurate" addition and the long division of Hida, Li and Bailey's
+// double-double/quad-double library (QD; "Algorithms for quad-double precision
+// floating point arithmetic", ARITH-15, 2001), written here from that paper's
+// description; dd_mul is Dekker's product with its cross terms gathered by
+// FMA.  A value is the unevaluated sum hi + lo with
 // |lo| <= ulp(hi)/2; the unit roundoff of the format is about 2^-104, which
 // realises the "double of the working precision" of Sec. 4 (Theorem 6).
 //

@@ -69,8 +69,13 @@ static void run(ProbDesc D, const Options& opt, double* U) {
 #pragma omp parallel for schedule(dynamic, 4)
   for (int k = 0; k < D.n; ++k) root_body<SK, 1>(D, opt, k, 0);
   if (g_batch_check) {
+    // as the batched check stage: Remark 2 and the DPR1 re-measure gathered and
+    // re-run (DEFER_WAVE, then DEFER_NEAR_ZERO), Remark 1 listed for the repairs
     *repair_count(w) = 0u;
-    for (int k = 0; k < D.n; ++k) check_body<SK, 1, false, DEFER_NEAR_ZERO>(D, opt, k, 0);
+    std::vector<int> again;
+    for (int k = 0; k < D.n; ++k)
+      if (check_body<SK, 1, false, DEFER_WAVE>(D, opt, k, 0)) again.push_back(k);
+    for (int k : again) check_body<SK, 1, false, DEFER_NEAR_ZERO>(D, opt, k, 0);
     const uint32_t c = *repair_count(w);
     if (c > (uint32_t)D.n) abort();
     for (uint32_t q = 0; q < c; ++q) check_body<SK, 1>(D, opt, (int)repair_list(w, D.n)[q], 0);
