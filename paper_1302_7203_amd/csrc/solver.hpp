@@ -258,6 +258,35 @@ __host__ __device__ inline void for_terms(int ln, int m, int excl, F&& f) {
   for (; j < m; j += G) f(j, true);
 }
 
+// As for_terms, in the same order, with the loads of TERM_UNROLL terms issued
+// together ahead of their arithmetic: load(j) returns term j's data and
+// f(j, above, data) uses it.  Where a term's arithmetic is long (the
+// double-double b pass) the compiler otherwise issues each term's loads just
+// before its arithmetic and waits on them one term at a time.
+struct v2 {   // two doubles of one term
+  double a, b;
+};
+
+template <int G, class L, class F>
+__host__ __device__ inline void for_terms_ld(int ln, int m, int excl, L&& load, F&& f) {
+  using T = decltype(load(0));
+  const int cut = (excl >= 0 && excl < m) ? excl : m;
+  int j = ln;
+  auto run = [&](int end, bool above) {
+    for (; j + (TERM_UNROLL - 1) * G < end; j += TERM_UNROLL * G) {
+      T t[TERM_UNROLL];
+#pragma unroll
+      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * G);
+#pragma unroll
+      for (int u = 0; u < TERM_UNROLL; ++u) f(j + u * G, above, t[u]);
+    }
+    for (; j < end; j += G) f(j, above, load(j));
+  };
+  run(cut, false);
+  if (j == excl) j += G;
+  run(m, true);
+}
+
 // The positive zero of t^2 - beta t - s^2 (s >= 0), in the form that avoids
 // cancellation.  beta and s are first brought below 2 by a power of two, so
 // neither square leaves the exponent range: x-space quantities are of the
@@ -291,8 +320,8 @@ __host__ __device__ inline void select_shift(const Prob& P, int k, int ln, int& 
   // 2^-24 errors could flip it the eigenvalue is that near the midpoint, so
   // either end-pole is a valid shift: the bare reciprocal estimate suffices
   double s = 0.0;
-#pragma unroll 4
-  for (int j = ln; j < m; j += G) s = fma(P.ch[j], recip_est(pdiff<KIND>(P.ds[j], dk) - mid), s);
+  for_terms_ld<G>(ln, m, -1, [&](int j) { return v2{P.ds[j], P.ch[j]}; },
+                  [&](int, bool, const v2& t) { s = fma(t.b, recip_est(pdiff<KIND>(t.a, dk) - mid), s); });
   s = gsum<G>(s);
   const double a = dd_to_d(dd_sub(P.corner, pval_dd<KIND>(dk)));
   const double fmid = (a - mid) - s;
@@ -324,21 +353,25 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   if (i > 0) dn = fabs(pdiff<KIND>(P.ds[i - 1], di));
   if (i + 1 < m) dn = fmin(dn, fabs(pdiff<KIND>(P.ds[i + 1], di)));
   const double gs = (dn > 0.0 && dn < INFINITY) ? ldexp(1.0, ilogb(dn)) : 1.0;
-  for_terms<G>(ln, m, i, [&](int j, bool above) {
-    const double ej = pdiff<KIND>(P.ds[j], di);
+  struct Term {
+    double d, ch, cl;
+  };
+  for_terms_ld<G>(ln, m, i, [&](int j) { return Term{P.ds[j], P.ch[j], FP64_B ? 0.0 : P.cl[j]}; },
+                  [&](int, bool above, const Term& t) {
+    const double ej = pdiff<KIND>(t.d, di);
     // delta_j, the diagonal of A_i^{-1}, within 11 ulps: the two-digit
     // quotient's remainder corrects its first digit, so c/e stays good to
     // about 2^-98, and the upper end below is widened for it
     const double rj = recip1(ej);
     if constexpr (FP64_B) {
-      const double t = P.ch[j] * rj;
-      if (above) f2 += t; else f1 += t;
+      const double q = t.ch * rj;
+      if (above) f2 += q; else f1 += q;
     } else {
-      const dd q = dd_div2_raw(dd{P.ch[j], P.cl[j]}, pdiff_dd<KIND>(P.ds[j], di), rj);
+      const dd q = dd_div2_raw(dd{t.ch, t.cl}, pdiff_dd<KIND>(t.d, di), rj);
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
     const double rs = rj * gs;
-    r2 = fma(P.ch[j], rs * rs, r2);
+    r2 = fma(t.ch, rs * rs, r2);
   });
   r2 = gsum<G>(r2);
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
@@ -450,12 +483,12 @@ template <int KIND, int G, bool OFF>
 __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
                                          double& sum, double& dsum, double& d2sum) {
   double a = 0.0, b = 0.0, c = 0.0;
-  for_terms<G>(ln, P.m, excl, [&](int j, bool) {
-    const double e = OFF ? pdiff<KIND>(P.ds[j], pv) - s : pdiff<KIND>(P.ds[j], pv);
+  for_terms_ld<G>(ln, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
+    const double e = OFF ? pdiff<KIND>(t.a, pv) - s : pdiff<KIND>(t.a, pv);
     const double q = recip(e * fma(nu, e, -1.0));
     const double v = e * q;                // 1 / (nu e - 1)
-    a = fma(P.ch[j], q, a);
-    const double d1 = (P.ch[j] * v) * v;
+    a = fma(t.b, q, a);
+    const double d1 = (t.b * v) * v;
     b += d1;
     c = fma(d1, e * v, c);
   });
@@ -958,18 +991,16 @@ __host__ __device__ inline double inv_norm(const Prob& P, double pv, double s, d
   const double g = (off > 0.0) ? ldexp(1.0, ilogb(fmin(fmax(off, 0x1p-1000), 0x1p500))) : 1.0;
   double acc = 0.0;
   if constexpr (KIND == KIND_DPR1) {
-#pragma unroll 4
-    for (int j = ln; j < P.nsorted; j += G) {
-      const double x = P.zs[j] * (recip(((P.ds[j] - pv) - s) - mu) * g);
+    for_terms_ld<G>(ln, P.nsorted, -1, [&](int j) { return v2{P.ds[j], P.zs[j]}; }, [&](int, bool, const v2& t) {
+      const double x = t.b * (recip(((t.a - pv) - s) - mu) * g);
       acc = fma(x, x, acc);
-    }
+    });
     acc = gsum<G>(acc);
   } else {
-#pragma unroll 4
-    for (int j = ln; j < P.m; j += G) {
-      const double r = recip((pdiff<KIND>(P.ds[j], pv) - s) - mu) * g;
-      acc = fma(P.ch[j] * r, r, acc);
-    }
+    for_terms_ld<G>(ln, P.m, -1, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
+      const double r = recip((pdiff<KIND>(t.a, pv) - s) - mu) * g;
+      acc = fma(t.b * r, r, acc);
+    });
     acc = gsum<G>(acc) + g * g;
   }
   return g / sqrt(acc);
