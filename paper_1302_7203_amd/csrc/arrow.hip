@@ -251,16 +251,19 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt
   }
 }
 
+// cols <= VEC_COLS_MAX (vec_shape)
 template <int KIND, int W, int RPT>
 __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles, int cols) {
+  __shared__ VecTileStage L;
   const int ct = blockIdx.x / row_tiles;
-  vec_tile<KIND, W, RPT>(D, blockIdx.x - ct * row_tiles, ct, cols);
+  vec_tile<KIND, W, RPT>(D, blockIdx.x - ct * row_tiles, ct, cols, L);
 }
 
 template <int RPT>
 __global__ __launch_bounds__(BLOCK) void k_vec_c(ProbDesc D, int row_tiles, int cols) {
+  __shared__ VecTileStage L;
   const int ct = blockIdx.x / row_tiles;
-  vec_tile_c<RPT>(D, blockIdx.x - ct * row_tiles, ct, cols);
+  vec_tile_c<RPT>(D, blockIdx.x - ct * row_tiles, ct, cols, L);
 }
 
 // ---------------------------------------------------------------------------

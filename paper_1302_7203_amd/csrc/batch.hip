@@ -39,6 +39,7 @@ namespace {
 constexpr int WAVE = 64;
 constexpr int STAGE_BLOCK = 256;
 constexpr int VEC_TALL_MIN = 512; // n from which vectors are written in row tiles
+static_assert(VEC_TALL_MIN <= VEC_FLAT_ROWS, "flat tiles stage every row of their problem in LDS");
 
 struct BatchArgs {
   const ProbDesc* descs;     // problems in queue order
@@ -48,6 +49,7 @@ struct BatchArgs {
   const int32_t* vec_mode;   // per problem: 0 flat tiles, 1 row tiles, 2 row tiles with 16-byte stores
   const int32_t* check_start;// count + 1 prefix sums of check-stage items
   const int32_t* check_lanes;// lanes per eigenvalue in the check stage, per problem
+  const int32_t* vec_prob;   // per vector tile: its problem
   uint32_t* counters;        // [0] first-pass queue, [1] check queue
   int32_t count;
   int32_t total_items;
@@ -221,33 +223,34 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_b_repair(BatchArgs B, Options 
 }
 
 template <int KIND>
-__device__ inline void vec_one(const ProbDesc& D, int t, int mode) {
+__device__ inline void vec_one(const ProbDesc& D, int t, int mode, VecFlatStage& L) {
   if (mode == 0) {
-    vec_flat<KIND>(D, t);
+    vec_flat<KIND>(D, t, L);
   } else {
     const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
     const int ct = t / row_tiles;
-    if (mode == 2) vec_tile<KIND, 2>(D, t - ct * row_tiles, ct);
-    else vec_tile<KIND, 1>(D, t - ct * row_tiles, ct);
+    if (mode == 2) vec_tile<KIND, 2, VEC_RPT>(D, t - ct * row_tiles, ct, VEC_COLS, L);
+    else vec_tile<KIND, 1, VEC_RPT>(D, t - ct * row_tiles, ct, VEC_COLS, L);
   }
 }
 
 // every problem's vectors: its tiles are a contiguous range of blocks
 __global__ __launch_bounds__(BLOCK) void k_b_vec(BatchArgs B) {
-  const int p = find_problem(B.vec_start, B.count, (int)blockIdx.x);
+  __shared__ VecFlatStage L;
+  const int p = B.vec_prob[blockIdx.x];
   const ProbDesc D = B.descs[p];
   const int t = (int)blockIdx.x - B.vec_start[p];
   const int mode = B.vec_mode[p];
   switch (D.kind) {
-    case KIND_ARROW: vec_one<KIND_ARROW>(D, t, mode); break;
-    case KIND_DPR1: vec_one<KIND_DPR1>(D, t, mode); break;
+    case KIND_ARROW: vec_one<KIND_ARROW>(D, t, mode, L); break;
+    case KIND_DPR1: vec_one<KIND_DPR1>(D, t, mode, L); break;
     case KIND_HERM: {   // complex row tiles at every n
       const int row_tiles = (D.n + VEC_TILE - 1) / VEC_TILE;
       const int ct = t / row_tiles;
-      vec_tile_c<VEC_RPT>(D, t - ct * row_tiles, ct, VEC_COLS);
+      vec_tile_c<VEC_RPT>(D, t - ct * row_tiles, ct, VEC_COLS, L);
       break;
     }
-    default: vec_one<KIND_SVD>(D, t, mode); break;
+    default: vec_one<KIND_SVD>(D, t, mode, L); break;
   }
 }
 
@@ -293,7 +296,7 @@ struct arrow_batch_s {
   size_t dev_bytes;
   std::vector<ProbDesc> descs;
   std::vector<int32_t> tabs;   // item_start (count+1), lanes (count), vec_start (count+1), vec_mode (count),
-                               // check_start (count+1), check_lanes (count)
+                               // check_start (count+1), check_lanes (count), vec_prob (one per vector tile)
   BatchArgs args;
   int persistent_blocks;
   hipGraph_t graph;
@@ -309,17 +312,32 @@ static constexpr uint32_t BATCH_MAGIC = 0xBA7C4EDu;
 
 static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// vector tiles of one problem: complex row tiles (Hermitian), flat tiles of
+// whole columns (n < VEC_TALL_MIN), or row tiles
+static int64_t vec_tiles(const arrow_desc_t& a) {
+  if (a.vec_off < 0) return 0;
+  const int64_t n = a.n;
+  if (a.kind != ARROW_KIND_HERM && n < VEC_TALL_MIN) {
+    const int64_t c = vec_flat_cols(n);
+    return (n + c - 1) / c;
+  }
+  return ((n + VEC_TILE - 1) / VEC_TILE) * ((n + VEC_COLS - 1) / VEC_COLS);
+}
+
 struct Layout {
   size_t off_desc, off_tab, off_ws, total;
+  int64_t vec_total;
 };
 
 static Layout plan_layout(int64_t count, const arrow_desc_t* descs) {
   Layout L;
+  L.vec_total = 0;
+  for (int64_t p = 0; p < count; ++p) L.vec_total += vec_tiles(descs[p]);
   size_t off = 256;                                   // counters
   L.off_desc = off;
   off = align_up(off + (size_t)count * sizeof(ProbDesc), 256);
   L.off_tab = off;
-  off = align_up(off + (size_t)(6 * count + 3) * sizeof(int32_t), 256);
+  off = align_up(off + (size_t)(6 * count + 3 + L.vec_total) * sizeof(int32_t), 256);
   L.off_ws = off;
   for (int64_t p = 0; p < count; ++p) off += align_up(ws_doubles(descs[p].n) * sizeof(double), 256);
   L.total = off;
@@ -388,6 +406,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   }
   DeviceGuard g(h->device);
   const Layout L = plan_layout(count, descs);
+  if (L.vec_total > INT32_MAX / 2) return -2;
   if (workspace && workspace_bytes < L.total) return -8;
   arrow_batch_s* b = new (std::nothrow) arrow_batch_s();
   if (!b) return ARROW_ERR_NOMEM;
@@ -412,13 +431,14 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t c) { return descs[a].n > descs[c].n; });
   b->descs.resize((size_t)count);
-  b->tabs.assign((size_t)(6 * count + 3), 0);
+  b->tabs.assign((size_t)(6 * count + 3 + L.vec_total), 0);
   int32_t* item_start = b->tabs.data();
   int32_t* lanes = item_start + count + 1;
   int32_t* vec_start = lanes + count;
   int32_t* vec_mode = vec_start + count + 1;
   int32_t* check_start = vec_mode + count;
   int32_t* check_lanes = check_start + count + 1;
+  int32_t* vec_prob = check_lanes + count;
   char* base = (char*)b->dev;
   size_t wsoff = L.off_ws;
   int64_t items = 0, vchunks = 0, citems = 0;
@@ -450,20 +470,17 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
     citems += (a.n + (WAVE / Gc) - 1) / (WAVE / Gc);
     vec_start[q] = (int32_t)vchunks;
     if (D.V && a.kind == ARROW_KIND_HERM) {
-      const int64_t n = a.n;
       vec_mode[q] = 1;
-      vchunks += ((n + VEC_TILE - 1) / VEC_TILE) * ((n + VEC_COLS - 1) / VEC_COLS);
     } else if (D.V) {
       const int64_t n = a.n;
       if (n < VEC_TALL_MIN) {
         vec_mode[q] = 0;
-        vchunks += (n * n + VEC_FLAT - 1) / VEC_FLAT;
       } else {
         const bool pair = (n % 2 == 0) && (((uintptr_t)D.V & 15) == 0) && (!D.U || (((uintptr_t)D.U & 15) == 0));
         vec_mode[q] = pair ? 2 : 1;
-        vchunks += ((n + VEC_TILE - 1) / VEC_TILE) * ((n + VEC_COLS - 1) / VEC_COLS);
       }
     }
+    for (int64_t t = vec_tiles(a); t > 0; --t) vec_prob[vchunks++] = (int32_t)q;
   }
   item_start[count] = (int32_t)items;
   vec_start[count] = (int32_t)vchunks;
@@ -493,6 +510,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   A.vec_mode = A.vec_start + count + 1;
   A.check_start = A.vec_mode + count;
   A.check_lanes = A.check_start + count + 1;
+  A.vec_prob = A.check_lanes + count;
   A.total_check = (int32_t)citems;
   A.counters = (uint32_t*)base;
   A.count = (int32_t)count;

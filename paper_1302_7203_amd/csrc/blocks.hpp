@@ -189,10 +189,34 @@ __device__ inline void sort_block(const ProbDesc& D) {
 // consecutive rows with one 16-byte non-temporal store (n and the leading
 // dimensions even, V and U 16-byte aligned); W = 1 writes one row per store.
 // The measured best tile shape depends on n (vec_shape).
-constexpr int VEC_RPT = 4;                     // rows per thread (batched path, and n <= 4096)
+//
+// The block's column data (shift pole, offset, mu, 1/||x||, ...) is staged in
+// LDS before the column loop: read from the workspace inside the loop, each
+// column's loads would wait behind the previous column's stores, which the
+// compiler cannot tell apart from them.
+#ifndef AHD_VEC_RPT
+#define AHD_VEC_RPT 2
+#endif
+constexpr int VEC_RPT = AHD_VEC_RPT;           // rows per thread (batched path)
 constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
-constexpr int VEC_COLS = 16;                   // columns per block (batched path)
+#ifndef AHD_VEC_COLS
+#define AHD_VEC_COLS 8
+#endif
+constexpr int VEC_COLS = AHD_VEC_COLS;         // columns per block (batched path)
+constexpr int VEC_COLS_MAX = 32;               // most columns a row-tile block takes (vec_shape)
+constexpr int VEC_FLAT_COLS = 256;             // most columns a flat tile takes
+constexpr int VEC_FLAT_ROWS = 512;             // flat tiles serve orders below this
 typedef double v2d __attribute__((ext_vector_type(2)));
+
+// LDS of a vector block: C columns' data and, for flat tiles, R rows' data
+template <int C, int R>
+struct VecStage {
+  double pv[C], sf[C], mu[C], inrm[C], sig[C];
+  int cm[C];
+  double dr[R], num[R];
+};
+using VecTileStage = VecStage<VEC_COLS_MAX, 1>;
+using VecFlatStage = VecStage<VEC_FLAT_COLS, VEC_FLAT_ROWS>;
 
 struct VecShape {
   int rpt, cols;
@@ -209,8 +233,24 @@ __host__ __device__ inline VecShape vec_shape(int64_t n) {
   return VecShape{2, n >= 512 ? 2 : 1};
 }
 
-template <int KIND, int W, int RPT = VEC_RPT>
-__device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VEC_COLS) {
+// columns [c0, c0 + nc) of the workspace's final shift pairs into L (every
+// thread of the block calls this; it ends with a barrier)
+template <int KIND, class S>
+__device__ inline void stage_cols(const ProbDesc& D, const Ws& w, int c0, int nc, int nd, S& L) {
+  for (int c = threadIdx.x; c < nc; c += BLOCK) {
+    const int col = c0 + c;
+    L.pv[c] = w.pv[col];
+    L.sf[c] = w.sf[col];
+    L.mu[c] = w.mu[col];
+    L.inrm[c] = w.inrm[col];
+    if constexpr (KIND == KIND_SVD) L.sig[c] = D.lam[col];
+    if constexpr (KIND == KIND_ARROW) L.cm[c] = nd > 0 ? w.cm[col] : -1;
+  }
+  __syncthreads();
+}
+
+template <int KIND, int W, int RPT, class S>
+__device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols, S& L) {
   static_assert(W == 1 || W == 2, "one or two rows per store");
   static_assert(RPT % W == 0, "rows per thread");
   constexpr int PER = RPT / W;                 // stores per column per thread
@@ -229,12 +269,14 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
     }
   }
   const int c0 = ct * cols;
-  const int c1 = min(n, c0 + cols);
+  const int nc = min(n - c0, cols);
   const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
-  for (int col = c0; col < c1; ++col) {
+  stage_cols<KIND>(D, w, c0, nc, nd, L);
+  for (int c = 0; c < nc; ++c) {
+    const int col = c0 + c;
     double* vc = D.V + (size_t)col * (size_t)D.ldv;
     if (KIND == KIND_ARROW && nd > 0) {
-      const int it = w.cm[col];
+      const int it = L.cm[c];
       if (it >= 0 && it < nd) {   // a deflated eigenvector (the whole block takes this branch)
         auto entry = [&](int r, double zr) { return r < n - 1 ? deflated_entry(w, it, w.iperm[r], zr) : 0.0; };
 #pragma unroll
@@ -252,9 +294,9 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
         continue;
       }
     }
-    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
+    const double pv = L.pv[c], s = L.sf[c], mu = L.mu[c], inrm = L.inrm[c];
     double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
-    const double sigma = (KIND == KIND_SVD) ? D.lam[col] : 0.0;
+    const double sigma = (KIND == KIND_SVD) ? L.sig[c] : 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W;
@@ -280,8 +322,8 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols = VE
 
 // Complex eigenvector entries of a Hermitian arrowhead (vec_entry_c), one
 // 16-byte (re, im) store each; rows and columns are tiled as in vec_tile.
-template <int RPT>
-__device__ inline void vec_tile_c(const ProbDesc& D, int rt, int ct, int cols) {
+template <int RPT, class S>
+__device__ inline void vec_tile_c(const ProbDesc& D, int rt, int ct, int cols, S& L) {
   constexpr int TILE = BLOCK * RPT;
   const int n = D.n;
   const Ws w = ws_view(D.ws, n);
@@ -295,10 +337,11 @@ __device__ inline void vec_tile_c(const ProbDesc& D, int rt, int ct, int cols) {
     zi[q] = body ? D.z[2 * r + 1] : 0.0;
   }
   const int c0 = ct * cols;
-  const int c1 = min(n, c0 + cols);
-  for (int col = c0; col < c1; ++col) {
-    const double pv = w.pv[col], s = w.sf[col], mu = w.mu[col], inrm = w.inrm[col];
-    v2d* uc = (v2d*)D.V + (size_t)col * (size_t)D.ldv;
+  const int nc = min(n - c0, cols);
+  stage_cols<KIND_HERM>(D, w, c0, nc, 0, L);
+  for (int c = 0; c < nc; ++c) {
+    const double pv = L.pv[c], s = L.sf[c], mu = L.mu[c], inrm = L.inrm[c];
+    v2d* uc = (v2d*)D.V + (size_t)(c0 + c) * (size_t)D.ldv;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int r = rt * TILE + q * BLOCK + threadIdx.x;
@@ -313,36 +356,54 @@ __device__ inline void vec_tile_c(const ProbDesc& D, int rt, int ct, int cols) {
 }
 
 // vec_flat, for small n (a row tile would leave most threads idle): tile t is
-// the column-major entries [t*VEC_FLAT, (t+1)*VEC_FLAT) of the n x n block
-// (ld = n), BLOCK consecutive entries per step; a thread finds its (row,
-// column) once and then steps it without dividing.
-constexpr int VEC_FLAT = 4096;
+// the columns [t*C, (t+1)*C) of the n x n block (ld = n), C = vec_flat_cols(n),
+// whose entries are contiguous.  The problem's rows and the tile's columns are
+// staged in LDS; BLOCK consecutive entries are written per step, and a thread
+// finds its (row, column) once and then steps it without dividing.
+#ifndef AHD_VEC_FLAT_ENTRIES
+#define AHD_VEC_FLAT_ENTRIES 4096
+#endif
+constexpr int VEC_FLAT_ENTRIES = AHD_VEC_FLAT_ENTRIES;   // entries a flat tile aims at
 
-template <int KIND>
-__device__ inline void vec_flat(const ProbDesc& D, int t) {
-  const int n = D.n;
+__host__ __device__ inline int vec_flat_cols(int64_t n) {
+  const int64_t c = VEC_FLAT_ENTRIES / n;
+  return (int)(c < 1 ? 1 : (c > VEC_FLAT_COLS ? VEC_FLAT_COLS : c));
+}
+
+template <int KIND, class S>
+__device__ inline void vec_flat(const ProbDesc& D, int t, S& L) {
+  const int n = D.n;   // below VEC_FLAT_ROWS
   const Ws w = ws_view(D.ws, n);
-  const int64_t nn = (int64_t)n * n;
-  int64_t e = (int64_t)t * VEC_FLAT + threadIdx.x;
-  if (e >= nn) return;
-  int col = (int)(e / n);
-  int row = (int)(e - (int64_t)col * n);
-  const int q = BLOCK / n, rem = BLOCK - q * n;
+  const int C = vec_flat_cols(n);
+  const int c0 = t * C;
+  const int nc = min(C, n - c0);
   const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
-  for (int step = 0; step < VEC_FLAT / BLOCK && e < nn; ++step, e += BLOCK) {
-    const bool body = (KIND == KIND_DPR1) ? true : (row < n - 1);
-    const double dr = body ? in_pole<KIND>(D, row) : 0.0;
-    const double num = body ? ((KIND == KIND_SVD) ? dr * D.z[row] : D.z[row]) : 0.0;
-    const int it = (KIND == KIND_ARROW && nd > 0) ? w.cm[col] : -1;
-    const double v = (it >= 0 && it < nd) ? (body ? deflated_entry(w, it, w.iperm[row], num) : 0.0)
-                               : vec_entry<KIND>(dr, num, row == n - 1, w.pv[col], w.sf[col], w.mu[col], w.inrm[col]);
-    __builtin_nontemporal_store(v, D.V + e);
-    if (KIND == KIND_SVD && D.U) __builtin_nontemporal_store(svd_left(D, D.lam[col], v, row), D.U + e);
+  for (int r = threadIdx.x; r < n; r += BLOCK) {
+    const bool body = (KIND == KIND_DPR1) ? true : (r < n - 1);
+    const double d = body ? in_pole<KIND>(D, r) : 0.0;
+    L.dr[r] = d;
+    L.num[r] = body ? ((KIND == KIND_SVD) ? d * D.z[r] : D.z[r]) : 0.0;
+  }
+  stage_cols<KIND>(D, w, c0, nc, nd, L);
+  const int ne = nc * n;
+  double* out = D.V + (size_t)c0 * (size_t)n;
+  double* uout = (KIND == KIND_SVD && D.U) ? D.U + (size_t)c0 * (size_t)n : nullptr;
+  int e = threadIdx.x;
+  int c = e / n;
+  int row = e - c * n;
+  const int q = BLOCK / n, rem = BLOCK - q * n;
+  for (; e < ne; e += BLOCK) {
+    const int it = (KIND == KIND_ARROW && nd > 0) ? L.cm[c] : -1;
+    const double v = (it >= 0 && it < nd)
+        ? (row < n - 1 ? deflated_entry(w, it, w.iperm[row], L.num[row]) : 0.0)
+        : vec_entry<KIND>(L.dr[row], L.num[row], row == n - 1, L.pv[c], L.sf[c], L.mu[c], L.inrm[c]);
+    __builtin_nontemporal_store(v, out + e);
+    if (KIND == KIND_SVD && uout) __builtin_nontemporal_store(svd_left(D, L.sig[c], v, row), uout + e);
     row += rem;
-    col += q;
+    c += q;
     if (row >= n) {
       row -= n;
-      ++col;
+      ++c;
     }
   }
 }

@@ -390,18 +390,24 @@ __host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, i
 
 // 1/||x|| of eq. (eigenvecAi) at the root nu of a rational pass over the poles
 // shifted by (pv, s), from that pass's last point last[0] and its sums
-// last[1] = S2 = sum zeta_j^2 v_j^2 and last[2] = S3 = sum zeta_j^2 e_j v_j^3,
+// last[1] = S2 = sum zeta_j^2 v_j^2 and last[2] = l S3, S3 = sum zeta_j^2 e_j v_j^3,
 // v_j = 1/(nu e_j - 1): the entries are nu zeta_j v_j, the excluded pole's (weight
 // cx; 0 when none is excluded) -nu zeta_x, and -1, so ||x||^2 = nu^2 (S2 + cx) + 1,
-// carried from last[0] to nu to first order (d(nu^2 S2)/dnu = 2 nu S2 - 2 nu^2 S3).
+// carried from l = last[0] to nu to first order (d(nu^2 S2)/dnu = 2 nu S2 - 2 nu^2 S3).
+// The rational iteration may stop on a candidate it has not evaluated, once
+// its step is below 2^-24 of the distance to the nearest pole: each v_j then
+// moves by less than 2^-24 relative, and the neglected second-order term is
+// below 2^-46 of ||x||^2.
 __host__ __device__ inline double norm_from_pass(const double* last, double nu, double cx) {
   const double l = last[0], a0 = last[1] + cx;
-  const double acc = l * l * a0 + 1.0 + (2.0 * l * a0 - 2.0 * l * l * last[2]) * (nu - l);
+  // the step enters as (nu - l) / l: the product of the sums with 1/l alone
+  // underflows when the sums are near 1e-225 and l near 1e225
+  const double rl = 1.0 / l;
+  const double dl = 2.0 * (a0 - last[2]) * ((nu - l) * rl);
+  const double acc = l * l * (a0 + dl) + 1.0;
   if (acc < INFINITY) return 1.0 / sqrt(acc);
   // l^2 overflowed (lambda within about 2^-512 of its pole): in units of l^2
-  const double rl = 1.0 / l;
-  const double acc2 = a0 + rl * rl + (2.0 * a0 * rl - 2.0 * last[2]) * (nu - l);
-  return fabs(rl) / sqrt(acc2);
+  return fabs(rl) / sqrt(a0 + dl + rl * rl);
 }
 
 template <int KIND, int G, bool HOT = false>

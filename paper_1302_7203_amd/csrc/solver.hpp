@@ -48,6 +48,10 @@ constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 
 constexpr int MAX_BISECT = 4000;
 constexpr int MAX_RATIONAL = 60;     // rational steps before falling back to bisection steps
 constexpr int RATIONAL_TO_BISECT = 14;
+#ifndef AHD_EARLY2
+#define AHD_EARLY2 24
+#define AHD_EARLY1 36
+#endif
 
 enum RootMethod { ROOT_BISECT = 0, ROOT_RATIONAL = 1 };
 
@@ -476,9 +480,11 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
 // midpoints are taken.  One O(n) pass per step gives psi and psi'.
 
 // sums over j != excl of  c_j / (e_j (nu e_j - 1)),  c_j / (nu e_j - 1)^2  and
-// c_j e_j / (nu e_j - 1)^3, with e_j = pdiff(d_j, pv) - s (the pole terms of
+// nu c_j e_j / (nu e_j - 1)^3, with e_j = pdiff(d_j, pv) - s (the pole terms of
 // psi and of its first two derivatives, up to constant factors); OFF = false
-// when the offset s is known to be zero.
+// when the offset s is known to be zero.  The third sum is taken times nu: it
+// is then of the size of the second, whereas the plain sum of c_j e_j v_j^3
+// underflows when the poles are as small as 1e-220 and nu as large as 1e220.
 template <int KIND, int G, bool OFF>
 __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
                                          double& sum, double& dsum, double& d2sum) {
@@ -490,7 +496,7 @@ __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int
     a = fma(t.b, q, a);
     const double d1 = (t.b * v) * v;
     b += d1;
-    c = fma(d1, e * v, c);
+    c = fma(d1, (e * nu) * v, c);
   });
   sum = gsum<G>(a);
   dsum = gsum<G>(b);
@@ -632,6 +638,13 @@ __host__ __device__ inline double bounded_next(double x, double h, double hnoise
       *done = 1;
       return (cand > lo && cand < hi) ? cand : x;
     }
+#if AHD_EARLY2 > 0
+    if (cand > lo && cand < hi &&
+        fabs(cand - x) <= (second ? ldexp(1.0, -AHD_EARLY2) : ldexp(1.0, -AHD_EARLY1)) * (x - fmax(y, 0.0))) {
+      *done = 1;
+      return cand;
+    }
+#endif
     if (hi_open && cand >= hi) return hi;
     slo = fmax(slo, lo);
     shi = fmin(shi, hi);
@@ -705,7 +718,7 @@ __host__ __device__ inline double rational_inverse(const Prob& P, int i, int sid
     const double rnu = 1.0 / nu;
     const double psi = (s1 + rnu) * rci;                       // psi(nu)
     const double dpsi = -(s2 + rnu * rnu) * rci;               // psi'(nu)
-    const double d2psi = 2.0 * (s3 + rnu * rnu * rnu) * rci;   // psi''(nu)
+    const double d2psi = 2.0 * (s3 * rnu + rnu * rnu * rnu) * rci;   // psi''(nu)
     const double psi_x = sg * psi, dpsi_x = dpsi, d2psi_x = sg * d2psi;
     const double h = c0 - x + psi_x;
     if (h > 0) xlo = x; else xhi = x;
@@ -779,7 +792,7 @@ __host__ __device__ inline double dpr1_inverse(const Prob& P, double pv, double 
       const double rnu = 1.0 / nu;
       const double psi_x = sg * (s1 + rnu);
       const double dpsi_x = -(s2 + rnu * rnu);
-      const double d2psi_x = sg * 2.0 * (s3 + rnu * rnu * rnu);
+      const double d2psi_x = sg * 2.0 * (s3 * rnu + rnu * rnu * rnu);
       const double h = c0 + psi_x;
       if (h > 0) xlo = x; else xhi = x;
       if (h == 0) break;
