@@ -136,7 +136,7 @@ int arrow_eig(arrow_handle_t h, int64_t n, const double* d, const double* z, dou
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels and results as arrow_eig, for
  * 1 <= n <= ARROW_NOALLOC_N_MAX (above it: -2).  Instead of the handle's
- * workspace it uses a scratch array in static device memory, 16 + 25
+ * workspace it uses a scratch array in static device memory, 16 + 26
  * ARROW_NOALLOC_N_MAX doubles (6.5 MiB), which every device the library runs
  * on holds until the process ends; its address is looked up in arrow_create
  * (ARROW_ERR_HIP if that failed).  It calls no hipMalloc, hipFree or other
