@@ -302,6 +302,9 @@ def serving_leg(args, dev):
            "offered_load": args.serve_load, "offered_solves_per_s": rate,
            "achieved_solves_per_s": st["solves_per_s"], "achieved_eigenpairs_per_s": st["eigenpairs_per_s"],
            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+           "latency_parts_ms": {k: round(v, 4) for k, v in st.items()
+                                if k.startswith(("admit_wait", "launch_wait", "device"))},
+           "slowest_1pct_mean_n": st["n_mean_slowest_1pct"], "streams": 3, "aging_ms": 20.0,
            "launches": launches, "mean_batch": len(probs) / max(1, launches), "peak_arena_gib": peak / (1 << 30)}
     if got:
         import oracle

@@ -3,15 +3,19 @@
 Requests (arrowhead eigen, DPR1 eigen, triangular-arrowhead SVD) arrive over
 time.  The loop
 
-* admits them first-come first-served whenever their device bytes (inputs,
-  outputs, info words and solver workspace) fit in a fixed HBM budget -- one
-  arena allocated once, so the loop itself never allocates device memory;
+* admits them in arrival order whenever their device bytes (inputs, outputs,
+  info words and solver workspace) fit in a fixed HBM budget -- one arena
+  allocated once, so the loop itself never allocates device memory.  A request
+  that does not fit is passed over by later, smaller ones until it has waited
+  `aging_s`; from then on nothing is admitted past it, so the space it needs
+  frees up as batches finish and it cannot starve;
 * packs everything admitted since the last launch into one batch plan
   (arrow_batch_create with workspace carved from the arena) and launches it
   on one of a few streams, so batches that arrive while others run overlap
   with them on the device;
-* polls completion events, records each request's latency (arrival to results
-  resident on the device) and returns the arena space of finished requests.
+* polls completion events, records each request's arrival, admission, launch
+  and completion times (latency: arrival to results resident on the device)
+  and returns the arena space of finished requests.
 
 Each request's results are the same as if it were solved alone: a problem's
 kernels depend only on its own data and its order n (which fixes its lanes).
@@ -20,6 +24,7 @@ from __future__ import annotations
 
 import bisect
 import ctypes
+import functools
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -97,13 +102,29 @@ def _up(nbytes: int) -> int:
 BATCH_OVERHEAD = 8 * ALIGN
 
 
+@functools.lru_cache(maxsize=None)
+def _plan_bytes(kind: int, n: int, vectors: bool) -> int:
+    """Device bytes of a batch plan holding this one problem (the library's own layout:
+    counters, descriptor, tables -- one word per vector tile among them -- and solver
+    workspace); a plan of many problems needs at most the sum of these."""
+    d = (batch.ArrowDesc * 1)()
+    d[0].kind, d[0].n, d[0].scalar = kind, n, 1.0
+    d[0].d_off, d[0].z_off, d[0].lam_off = 0, 0, 0
+    d[0].vec_off = 0 if vectors else -1
+    d[0].left_off = -1
+    d[0].info_off = 0
+    got = int(batch.lib().arrow_batch_workspace_size(1, ctypes.cast(d, ctypes.c_void_p)))
+    if got <= 0:
+        raise ValueError(f"no batch plan for kind {kind}, n = {n}")
+    return got
+
+
 def request_parts(pr: Problem, vectors=True):
     """(outputs, info, rest): arena bytes of a request's results, of its info words, and of
-    its share of the batch's input chunk and plan workspace (inputs, solver workspace,
-    112-byte descriptor and six table words, with room to spare)."""
+    its share of the batch's input chunk and plan workspace."""
     out = _up(8 * out_doubles(pr, vectors))
     info = _up(4 * pr.n)
-    rest = 8 * _in_doubles(pr) + _up(8 * (16 + 26 * pr.n)) + 160
+    rest = _up(8 * _in_doubles(pr)) + _plan_bytes(pr.kind, pr.n, vectors)
     return out, info, rest
 
 
@@ -117,8 +138,9 @@ class Request:
     rid: int
     problem: Problem
     arrival: float                 # seconds on the loop's clock
-    admitted: float = -1.0
-    done: float = -1.0
+    admitted: float = -1.0         # its results' arena space granted
+    launched: float = -1.0         # its batch's kernels queued on a stream
+    done: float = -1.0             # results complete on the device (seen by the poll)
     out: tuple | None = None       # (offset, size) in the arena: values, vectors, left vectors
     info: tuple | None = None
     desc_fields: dict = field(default_factory=dict)
@@ -129,12 +151,17 @@ class Request:
 
 
 class Scheduler:
-    """Admission policy (no device work): FIFO admission by byte budget, batches capped in size."""
+    """Admission policy (no device work): requests in arrival order by byte budget, batches
+    capped in size; later requests may pass one that does not fit, until it has waited
+    aging_s (at most `lookahead` pending requests are looked at per admission)."""
 
-    def __init__(self, arena: Arena, max_batch=4096, vectors=True):
+    def __init__(self, arena: Arena, max_batch=4096, vectors=True, aging_s=0.02, lookahead=256, max_work=None):
         self.arena = arena
         self.max_batch = max_batch
+        self.max_work = max_work      # cap on the sum of n^2 over a batch (None: none)
         self.vectors = vectors
+        self.aging_s = aging_s
+        self.lookahead = lookahead
         self.pending: deque[Request] = deque()
 
     def submit(self, req: Request):
@@ -142,27 +169,51 @@ class Scheduler:
             raise ValueError(f"request {req.rid} needs more than the whole HBM budget")
         self.pending.append(req)
 
+    def _take(self, req: Request, reserve: int, now: float) -> int:
+        """Grant req its results' and info words' space if it fits next to `reserve` bytes
+        kept for the batch; returns its share of the batch's input chunk and workspace,
+        or -1 when it does not fit."""
+        out_b, info_b, rest = request_parts(req.problem, self.vectors)
+        if self.arena.capacity - self.arena.used - reserve < out_b + info_b + rest:
+            return -1
+        got = self.arena.alloc(out_b)
+        if got is None:
+            return -1
+        inf = self.arena.alloc(info_b)
+        if inf is None:
+            self.arena.free(*got)
+            return -1
+        req.out, req.info, req.admitted = got, inf, now
+        return rest
+
     def admit(self, now: float) -> list[Request]:
-        """Requests admitted now, in arrival order, as one batch: stops at the first one
-        that does not fit.  Their results and info words are allocated here; room for the
-        batch's inputs and plan workspace is kept free for the launch that follows at once."""
+        """Requests admitted now, in arrival order, as one batch.  Their results and info
+        words are allocated here; room for the batch's inputs and plan workspace is kept
+        free for the launch that follows at once.  A request that does not fit is passed
+        over while it is younger than aging_s; an older one stops the scan, so that no
+        later request takes the space it waits for."""
         out = []
         reserve = BATCH_OVERHEAD
-        while self.pending and len(out) < self.max_batch:
-            req = self.pending[0]
-            out_b, info_b, rest = request_parts(req.problem, self.vectors)
-            if self.arena.capacity - self.arena.used - reserve < out_b + info_b + rest:
+        skipped = []
+        looked = 0
+        work = 0
+        while self.pending and len(out) < self.max_batch and looked < self.lookahead:
+            req = self.pending.popleft()
+            looked += 1
+            if out and self.max_work is not None and work + req.problem.n ** 2 > self.max_work:
+                self.pending.appendleft(req)   # the batch is full; the next one starts here
                 break
-            got = self.arena.alloc(out_b)
-            if got is None:
+            rest = self._take(req, reserve, now)
+            work += req.problem.n ** 2 if rest >= 0 else 0
+            if rest >= 0:
+                reserve += rest
+                out.append(req)
+                continue
+            skipped.append(req)
+            if now - req.arrival >= self.aging_s:
                 break
-            inf = self.arena.alloc(info_b)
-            if inf is None:
-                self.arena.free(*got)
-                break
-            req.out, req.info, req.admitted = got, inf, now
-            reserve += rest
-            out.append(self.pending.popleft())
+        for req in reversed(skipped):   # passed-over requests keep their place in line
+            self.pending.appendleft(req)
         return out
 
     def release(self, req: Request):
@@ -184,10 +235,10 @@ class Server:
     """Continuous batching of requests on one device within an HBM budget."""
 
     def __init__(self, hbm_budget: int, device=None, streams=3, max_batch=4096, vectors=True,
-                 staging_bytes=64 << 20, on_done=None):
+                 staging_bytes=64 << 20, on_done=None, aging_s=0.02, max_work=None, trace=False):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = Arena(hbm_budget)
-        self.sched = Scheduler(self.arena, max_batch=max_batch, vectors=vectors)
+        self.sched = Scheduler(self.arena, max_batch=max_batch, vectors=vectors, aging_s=aging_s, max_work=max_work)
         self.vectors = vectors
         self.buf = torch.empty(hbm_budget // 8, dtype=torch.float64, device=self.device)   # the arena
         self.base = self.buf.data_ptr()
@@ -211,6 +262,9 @@ class Server:
         # on_done(server, req) runs when req's results are complete on the device and
         # before its arena space is returned; it may read server.result(req) synchronously.
         self.on_done = on_done
+        # trace: timing events around every batch's kernels, for device_intervals()
+        self.trace = trace
+        self.traced: list[tuple] = []
 
     # -- device bookkeeping -------------------------------------------------
     def _free_stream(self):
@@ -272,6 +326,9 @@ class Server:
             copied = torch.cuda.Event()
             copied.record(stream)
             self.slot_busy[s] = copied
+            if self.trace:
+                t_start = torch.cuda.Event(enable_timing=True)
+                t_start.record(stream)
             plan = ctypes.c_void_p()
             rc = L.arrow_batch_create(self.handles[s], len(reqs), ctypes.cast(descs, ctypes.c_void_p),
                                       ctypes.c_void_p(self.base), ctypes.c_void_p(self.base),
@@ -279,8 +336,14 @@ class Server:
                                       ctypes.byref(plan))
             binding._check(rc, "arrow_batch_create")
             binding._check(L.arrow_batch_run(plan), "arrow_batch_run")
+            if self.trace:
+                t_end = torch.cuda.Event(enable_timing=True)
+                t_end.record(stream)
+                self.traced.append((t_start, t_end, s))
             ev = torch.cuda.Event()
             ev.record(stream)
+        for r in reqs:
+            r.launched = now
         self.inflight.append(InFlight(reqs, plan, (in_chunk, ws), ev, stream, s))
         self.launches += 1
         return True
@@ -303,6 +366,14 @@ class Server:
             else:
                 still.append(f)
         self.inflight = still
+
+    def device_intervals(self):
+        """(start ms, end ms, stream) of every traced batch on the device, relative to the
+        first batch's start (call once they are complete)."""
+        if not self.traced:
+            return []
+        t0 = self.traced[0][0]
+        return [(t0.elapsed_time(a), t0.elapsed_time(b), s) for a, b, s in self.traced]
 
     def release(self, req: Request):
         """The client is done with req's results: return its arena space."""
@@ -354,7 +425,7 @@ class Server:
                 adm = self.sched.admit(t)
                 if adm:
                     back = self._try_launch(adm, t)
-                    for r in reversed(back):
+                    for r in sorted(back, key=lambda q: q.rid, reverse=True):
                         self.sched.release(r)
                         r.admitted = -1.0
                         self.sched.pending.appendleft(r)
@@ -384,10 +455,23 @@ class Server:
 
 
 def latency_stats(reqs: list[Request]):
+    """Throughput and latency percentiles, with the latency split into its parts: waiting
+    for admission (arrival to admitted), admitted but not launched (a free stream, the
+    batch's inputs and plan), and on the device (launch to completion seen)."""
     lat = np.array([r.latency for r in reqs])
     t_end = max(r.done for r in reqs)
     t_start = min(r.arrival for r in reqs)
     pairs = sum(r.problem.n for r in reqs)
-    return {"requests": len(reqs), "wall_s": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
-            "eigenpairs_per_s": pairs / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
+    parts = {"admit_wait": np.array([r.admitted - r.arrival for r in reqs]),
+             "launch_wait": np.array([r.launched - r.admitted for r in reqs]),
+             "device": np.array([r.done - r.launched for r in reqs])}
+    slow = lat >= np.percentile(lat, 99)
+    out = {"requests": len(reqs), "wall_s": t_end - t_start, "solves_per_s": len(reqs) / (t_end - t_start),
+           "eigenpairs_per_s": pairs / (t_end - t_start), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3)}
+    for k, v in parts.items():
+        out[f"{k}_p50_ms"] = float(np.percentile(v, 50) * 1e3)
+        out[f"{k}_p99_ms"] = float(np.percentile(v, 99) * 1e3)
+        out[f"{k}_mean_ms_slowest_1pct"] = float(v[slow].mean() * 1e3)
+    out["n_mean_slowest_1pct"] = float(np.mean([r.problem.n for r, s_ in zip(reqs, slow) if s_]))
+    return out

@@ -71,3 +71,23 @@ def test_tight_budget_forces_waiting_but_finishes():
     assert waited > 0
     assert srv.arena.used == 0
     srv.close()
+
+
+def test_batches_overlap_on_the_device():
+    """With several streams, batches run at the same time: the batches' device intervals
+    (timing events around each batch's kernels) add up to more than the span they cover,
+    which a one-at-a-time execution could not do."""
+    import torch
+    from paper_1302_7203_amd import serve
+    dev = torch.device("cuda", 0)
+    arr = [(0.0, p) for _, p in _stream(200, 14, nmax=2000)]
+    srv = serve.Server(hbm_budget=8 << 30, device=dev, streams=3, max_batch=16, trace=True)
+    reqs = srv.run(arr)
+    torch.cuda.synchronize(dev)
+    assert all(r.done > 0 for r in reqs)
+    iv = srv.device_intervals()
+    assert len(iv) >= 10 and len({s for _, _, s in iv}) == 3
+    busy = sum(b - a for a, b, _ in iv)
+    span = max(b for _, b, _ in iv) - min(a for a, _, _ in iv)
+    assert busy > 1.2 * span, (busy, span)
+    srv.close()

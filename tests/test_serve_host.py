@@ -77,6 +77,38 @@ def test_fifo_admission_by_budget():
     assert s.arena.used == 0
 
 
+def test_admission_passes_a_blocked_request_until_it_ages():
+    """A request that does not fit is passed over by later ones that do, while it is
+    younger than aging_s; once older, nothing is admitted past it, and it goes first
+    when the space frees up."""
+    rng = np.random.default_rng(4)
+    big = [W.uniform_arrow(300, rng) for _ in range(2)]
+    small = [W.uniform_arrow(40, rng) for _ in range(4)]
+    cap = request_bytes(big[0]) + 2 * request_bytes(small[0]) + BATCH_OVERHEAD
+    assert cap < 2 * request_bytes(big[0])
+    s = Scheduler(Arena(cap), aging_s=0.05)
+    for i, p in enumerate([big[0], big[1], small[0], small[1]]):
+        s.submit(Request(i, p, 0.0))
+    first = s.admit(0.01)                       # request 1 (young, no room) is passed over
+    assert [r.rid for r in first] == [0, 2, 3]
+    assert [r.rid for r in s.pending] == [1]
+    launch1 = s.arena.alloc(sum(_side(r) for r in first))
+    assert launch1 is not None
+    s.arena.free(*launch1)                      # the batch finished ...
+    s.release(first[1])                         # ... and two small results were taken
+    s.release(first[2])
+    s.submit(Request(4, small[2], 0.06))
+    # request 1 is now older than aging_s and still does not fit: request 4 would, but may
+    # not pass it
+    assert s.admit(0.07) == [] and [r.rid for r in s.pending] == [1, 4]
+    s.release(first[0])
+    second = s.admit(0.08)
+    assert [r.rid for r in second][0] == 1
+    for r in second:
+        s.release(r)
+    assert s.arena.used == 0
+
+
 def test_request_bytes_cover_the_plan_workspace():
     """A batch's input chunk and plan workspace fit in its requests' reserved share plus
     the per-batch overhead, for batches of one and of many."""
@@ -88,7 +120,8 @@ def test_request_bytes_cover_the_plan_workspace():
     for trial in range(6):
         k = 1 if trial < 2 else 20
         gen = (W.uniform_arrow, W.dpr1, W.svd_arrow, W.herm_arrow)
-        probs = [gen[c](int(n), rng) for n, c in zip(rng.integers(1, 300, k), rng.integers(0, 4, k))]
+        hi = 300 if trial % 2 == 0 else 3000     # small problems, and row-tiled ones with long tile tables
+        probs = [gen[c](int(n), rng) for n, c in zip(rng.integers(1, hi, k), rng.integers(0, 4, k))]
         pk = batch.pack(probs)
         ws = int(L.arrow_batch_workspace_size(len(probs), ctypes.cast(pk.descs, ctypes.c_void_p)))
         up = lambda x: (x + ALIGN - 1) // ALIGN * ALIGN   # noqa: E731
