@@ -135,9 +135,13 @@ __device__ inline void check_kind(const ProbDesc& D, const Options& opt, int G, 
 constexpr int ROOT_CHUNK = 2;
 constexpr int CHECK_CHUNK = 8;
 
-// at least four wavefronts per SIMD: the pole loads come from L2 and need company to hide
-__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_b_root(BatchArgs B,
-                                                                                                Options opt) {
+// at least ROOT_WAVES wavefronts per SIMD: the pole loads come from L2 and need company to hide
+#ifndef AHD_ROOT_WAVES
+#define AHD_ROOT_WAVES 4
+#endif
+constexpr int ROOT_WAVES = AHD_ROOT_WAVES;
+__global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(ROOT_WAVES))) void k_b_root(
+    BatchArgs B, Options opt) {
   const int lane = threadIdx.x & (WAVE - 1);
   for (;;) {
     int first = 0;
@@ -516,7 +520,7 @@ int arrow_batch_create(arrow_handle_t h, int64_t count, const arrow_desc_t* desc
   A.count = (int32_t)count;
   A.total_items = b->total_items;
   // persistent grid: enough resident wavefronts to fill every SIMD several times
-  const int64_t want = (int64_t)h->cus * 16 * WAVE / STAGE_BLOCK;
+  const int64_t want = (int64_t)h->cus * 4 * ROOT_WAVES * WAVE / STAGE_BLOCK;
   const int64_t need = ((int64_t)items * WAVE + STAGE_BLOCK - 1) / STAGE_BLOCK;
   b->persistent_blocks = (int)std::max<int64_t>(1, std::min(want, need));
   if ((flags & ARROW_BATCH_TIMING) && !(flags & ARROW_BATCH_GRAPH)) {

@@ -116,6 +116,23 @@ def test_uniform_16384_sampled(gpu, oracle_lib):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.timeout(900)
+def test_uniform_16384_every_eigenvalue(gpu, oracle_lib, capsys):
+    """Every one of the 16384 eigenvalues of the uniform n = 16384 workload against the
+    oracle (about four minutes of the oracle on 16 host threads; progress is printed per
+    chunk of 2048)."""
+    torch, _, _ = gpu
+    pr = W.single_uniform_16384()
+    out = _arrow(gpu, pr.d, pr.z, pr.scalar, vectors=False)
+    lam = _np(out.lam)
+    for c0 in range(0, pr.n, 2048):
+        ks = np.arange(c0, min(pr.n, c0 + 2048), dtype=np.int64)
+        ref = oracle.arrow_eig(pr.d, pr.z, pr.scalar, ks=ks, vectors=False)
+        assert_close(lam[ks], ref.lam, f"lambda {c0}..{ks[-1]}")
+        with capsys.disabled():
+            print(f"uniform n=16384: eigenvalues {c0}..{ks[-1]} match the oracle", flush=True)
+
+
 @pytest.mark.parametrize("kind", [W.KIND_ARROW, W.KIND_DPR1, W.KIND_SVD])
 def test_odd_order_above_4096_sampled(gpu, kind, oracle_lib):
     """n = 5001: the tall vector tiles with one row per store (odd n), for every kind."""
