@@ -38,8 +38,11 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int STAGE_BLOCK = 256;
-constexpr int VEC_TALL_MIN = 512; // n from which vectors are written in row tiles
-static_assert(VEC_TALL_MIN <= VEC_FLAT_ROWS, "flat tiles stage every row of their problem in LDS");
+#ifndef AHD_VEC_TALL_MIN
+#define AHD_VEC_TALL_MIN 512
+#endif
+constexpr int VEC_TALL_MIN = AHD_VEC_TALL_MIN; // n from which vectors are written in row tiles
+static_assert(VEC_TALL_MIN - 1 <= VEC_FLAT_ROWS, "flat tiles stage every row of their problem in LDS");
 
 struct BatchArgs {
   const ProbDesc* descs;     // problems in queue order

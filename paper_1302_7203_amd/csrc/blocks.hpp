@@ -205,7 +205,10 @@ constexpr int VEC_TILE = BLOCK * VEC_RPT;      // rows per block
 constexpr int VEC_COLS = AHD_VEC_COLS;         // columns per block (batched path)
 constexpr int VEC_COLS_MAX = 32;               // most columns a row-tile block takes (vec_shape)
 constexpr int VEC_FLAT_COLS = 256;             // most columns a flat tile takes
-constexpr int VEC_FLAT_ROWS = 512;             // flat tiles serve orders below this
+#ifndef AHD_VEC_FLAT_ROWS
+#define AHD_VEC_FLAT_ROWS 512
+#endif
+constexpr int VEC_FLAT_ROWS = AHD_VEC_FLAT_ROWS; // flat tiles serve orders below this
 typedef double v2d __attribute__((ext_vector_type(2)));
 
 // LDS of a vector block: C columns' data and, for flat tiles, R rows' data
