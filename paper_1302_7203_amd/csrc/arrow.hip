@@ -251,12 +251,17 @@ __global__ __launch_bounds__(REPAIR_BLOCK) void k_repair(ProbDesc D, Options opt
   }
 }
 
-// cols <= VEC_COLS_MAX (vec_shape)
+// cols <= VEC_COLS_MAX (vec_shape).  A single problem's tiles read their
+// columns' shift data straight from the workspace: staged in LDS first they
+// were slower at n = 4096 (27.8 against 25.7 us) and equal at n = 16384.
+#ifndef AHD_SINGLE_VEC_STAGE
+#define AHD_SINGLE_VEC_STAGE 0
+#endif
 template <int KIND, int W, int RPT>
 __global__ __launch_bounds__(BLOCK) void k_vec(ProbDesc D, int row_tiles, int cols) {
   __shared__ VecTileStage L;
   const int ct = blockIdx.x / row_tiles;
-  vec_tile<KIND, W, RPT>(D, blockIdx.x - ct * row_tiles, ct, cols, L);
+  vec_tile<KIND, W, RPT, VecTileStage, AHD_SINGLE_VEC_STAGE != 0>(D, blockIdx.x - ct * row_tiles, ct, cols, L);
 }
 
 template <int RPT>

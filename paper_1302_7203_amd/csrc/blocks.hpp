@@ -252,7 +252,7 @@ __device__ inline void stage_cols(const ProbDesc& D, const Ws& w, int c0, int nc
   __syncthreads();
 }
 
-template <int KIND, int W, int RPT, class S>
+template <int KIND, int W, int RPT, class S, bool STAGE = true>
 __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols, S& L) {
   static_assert(W == 1 || W == 2, "one or two rows per store");
   static_assert(RPT % W == 0, "rows per thread");
@@ -274,12 +274,12 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols, S& 
   const int c0 = ct * cols;
   const int nc = min(n - c0, cols);
   const int nd = (KIND == KIND_ARROW) ? deflated_count(w) : 0;
-  stage_cols<KIND>(D, w, c0, nc, nd, L);
+  if constexpr (STAGE) stage_cols<KIND>(D, w, c0, nc, nd, L);
   for (int c = 0; c < nc; ++c) {
     const int col = c0 + c;
     double* vc = D.V + (size_t)col * (size_t)D.ldv;
     if (KIND == KIND_ARROW && nd > 0) {
-      const int it = L.cm[c];
+      const int it = STAGE ? L.cm[c] : w.cm[col];
       if (it >= 0 && it < nd) {   // a deflated eigenvector (the whole block takes this branch)
         auto entry = [&](int r, double zr) { return r < n - 1 ? deflated_entry(w, it, w.iperm[r], zr) : 0.0; };
 #pragma unroll
@@ -297,9 +297,10 @@ __device__ inline void vec_tile(const ProbDesc& D, int rt, int ct, int cols, S& 
         continue;
       }
     }
-    const double pv = L.pv[c], s = L.sf[c], mu = L.mu[c], inrm = L.inrm[c];
+    const double pv = STAGE ? L.pv[c] : w.pv[col], s = STAGE ? L.sf[c] : w.sf[col];
+    const double mu = STAGE ? L.mu[c] : w.mu[col], inrm = STAGE ? L.inrm[c] : w.inrm[col];
     double* uc = (KIND == KIND_SVD && D.U) ? D.U + (size_t)col * (size_t)D.ldu : nullptr;
-    const double sigma = (KIND == KIND_SVD) ? L.sig[c] : 0.0;
+    const double sigma = (KIND == KIND_SVD) ? (STAGE ? L.sig[c] : D.lam[col]) : 0.0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int r = rt * TILE + q * BLOCK * W + threadIdx.x * W;
