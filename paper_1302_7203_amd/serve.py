@@ -8,7 +8,9 @@ time.  The loop
   allocated once, so the loop itself never allocates device memory.  A request
   that does not fit is passed over by later, smaller ones until it has waited
   `aging_s`; from then on nothing is admitted past it, so the space it needs
-  frees up as batches finish and it cannot starve;
+  frees up as batches finish and it cannot starve.  Requests of order below
+  `split_n` and the larger ones go to separate batches, so that a small
+  request is not held until a large one in its batch is done;
 * packs everything admitted since the last launch into one batch plan
   (arrow_batch_create with workspace carved from the arena) and launches it
   on one of a few streams, so batches that arrive while others run overlap
@@ -155,10 +157,14 @@ class Scheduler:
     capped in size; later requests may pass one that does not fit, until it has waited
     aging_s (at most `lookahead` pending requests are looked at per admission)."""
 
-    def __init__(self, arena: Arena, max_batch=4096, vectors=True, aging_s=0.02, lookahead=256, max_work=None):
+    def __init__(self, arena: Arena, max_batch=4096, vectors=True, aging_s=0.02, lookahead=256, max_work=None,
+                 split_n=None):
         self.arena = arena
         self.max_batch = max_batch
         self.max_work = max_work      # cap on the sum of n^2 over a batch (None: none)
+        # requests of order below split_n and the others go to separate batches (None: mixed):
+        # a small request is complete only when its whole batch is
+        self.split_n = split_n
         self.vectors = vectors
         self.aging_s = aging_s
         self.lookahead = lookahead
@@ -186,20 +192,27 @@ class Scheduler:
         req.out, req.info, req.admitted = got, inf, now
         return rest
 
-    def admit(self, now: float) -> list[Request]:
+    def admit(self, now: float, allow_big: bool = True) -> list[Request]:
         """Requests admitted now, in arrival order, as one batch.  Their results and info
         words are allocated here; room for the batch's inputs and plan workspace is kept
         free for the launch that follows at once.  A request that does not fit is passed
         over while it is younger than aging_s; an older one stops the scan, so that no
-        later request takes the space it waits for."""
+        later request takes the space it waits for.  With split_n, the batch takes the size
+        class of the oldest pending request, or only small ones when allow_big is false."""
         out = []
         reserve = BATCH_OVERHEAD
         skipped = []
         looked = 0
         work = 0
+        big = None
+        if self.split_n is not None and self.pending:
+            big = allow_big and self.pending[0].problem.n >= self.split_n
         while self.pending and len(out) < self.max_batch and looked < self.lookahead:
             req = self.pending.popleft()
             looked += 1
+            if big is not None and (req.problem.n >= self.split_n) != big:
+                skipped.append(req)            # the other size class: a batch of its own
+                continue
             if out and self.max_work is not None and work + req.problem.n ** 2 > self.max_work:
                 self.pending.appendleft(req)   # the batch is full; the next one starts here
                 break
@@ -229,16 +242,18 @@ class InFlight:
     event: object
     stream: object
     staging_slot: int
+    big: bool = False
 
 
 class Server:
     """Continuous batching of requests on one device within an HBM budget."""
 
-    def __init__(self, hbm_budget: int, device=None, streams=3, max_batch=4096, vectors=True,
-                 staging_bytes=64 << 20, on_done=None, aging_s=0.02, max_work=None, trace=False):
+    def __init__(self, hbm_budget: int, device=None, streams=4, max_batch=4096, vectors=True,
+                 staging_bytes=64 << 20, on_done=None, aging_s=0.02, max_work=None, trace=False, split_n=2048):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.arena = Arena(hbm_budget)
-        self.sched = Scheduler(self.arena, max_batch=max_batch, vectors=vectors, aging_s=aging_s, max_work=max_work)
+        self.sched = Scheduler(self.arena, max_batch=max_batch, vectors=vectors, aging_s=aging_s, max_work=max_work,
+                               split_n=split_n)
         self.vectors = vectors
         self.buf = torch.empty(hbm_budget // 8, dtype=torch.float64, device=self.device)   # the arena
         self.base = self.buf.data_ptr()
@@ -344,7 +359,9 @@ class Server:
             ev.record(stream)
         for r in reqs:
             r.launched = now
-        self.inflight.append(InFlight(reqs, plan, (in_chunk, ws), ev, stream, s))
+        split = self.sched.split_n
+        big = split is not None and any(r.problem.n >= split for r in reqs)
+        self.inflight.append(InFlight(reqs, plan, (in_chunk, ws), ev, stream, s, big))
         self.launches += 1
         return True
 
@@ -422,7 +439,9 @@ class Server:
                 self.sched.submit(reqs[nxt])
                 nxt += 1
             if self.sched.pending and self._free_stream() is not None:
-                adm = self.sched.admit(t)
+                # batches of large requests never take the last stream: small ones always have one
+                busy_big = sum(1 for f in self.inflight if f.big)
+                adm = self.sched.admit(t, allow_big=len(self.streams) < 2 or busy_big < len(self.streams) - 1)
                 if adm:
                     back = self._try_launch(adm, t)
                     for r in sorted(back, key=lambda q: q.rid, reverse=True):

@@ -109,6 +109,25 @@ def test_admission_passes_a_blocked_request_until_it_ages():
     assert s.arena.used == 0
 
 
+def test_size_classes_form_separate_batches():
+    """With split_n, a batch holds only requests below it or only the others: the class of
+    the oldest pending request; the rest wait for the next admission, in order."""
+    rng = np.random.default_rng(6)
+    ns = (50, 900, 60, 1200, 70)
+    probs = [W.uniform_arrow(n, rng) for n in ns]
+    s = Scheduler(Arena(1 << 30), split_n=512)
+    for i, p in enumerate(probs):
+        s.submit(Request(i, p, 0.0))
+    first = s.admit(0.0)
+    assert [r.rid for r in first] == [0, 2, 4]
+    assert [r.rid for r in s.pending] == [1, 3]
+    second = s.admit(0.0)
+    assert [r.rid for r in second] == [1, 3] and not s.pending
+    for r in first + second:
+        s.release(r)
+    assert s.arena.used == 0
+
+
 def test_request_bytes_cover_the_plan_workspace():
     """A batch's input chunk and plan workspace fit in its requests' reserved share plus
     the per-batch overhead, for batches of one and of many."""
