@@ -48,9 +48,6 @@ constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 
 constexpr int MAX_BISECT = 4000;
 constexpr int MAX_RATIONAL = 60;     // rational steps before falling back to bisection steps
 constexpr int RATIONAL_TO_BISECT = 14;
-#ifndef AHD_PSI_RCP1
-#define AHD_PSI_RCP1 0
-#endif
 #ifndef AHD_EARLY2
 #define AHD_EARLY2 24
 #define AHD_EARLY1 36
@@ -494,11 +491,7 @@ __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int
   double a = 0.0, b = 0.0, c = 0.0;
   for_terms_ld<G>(ln, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
     const double e = OFF ? pdiff<KIND>(t.a, pv) - s : pdiff<KIND>(t.a, pv);
-#if AHD_PSI_RCP1
-    const double q = recip1(e * fma(nu, e, -1.0));
-#else
     const double q = recip(e * fma(nu, e, -1.0));
-#endif
     const double v = e * q;                // 1 / (nu e - 1)
     a = fma(t.b, q, a);
     const double d1 = (t.b * v) * v;
