@@ -398,6 +398,20 @@ __host__ __device__ inline void place_deflated(const ProbDesc& D, const Ws& w, i
 // its step is below 2^-24 of the distance to the nearest pole: each v_j then
 // moves by less than 2^-24 relative, and the neglected second-order term is
 // below 2^-46 of ||x||^2.
+// The DPR1 eigenvector q = (D - lambda I)^{-1} u of D + rho u u^T (Sec. 6.3) from
+// the norm of the reduced arrowhead's x: its Pick function is
+// f(lambda) = (d_n - lambda) phi(lambda), phi the DPR1 secular function
+// 1 + rho sum_j u_j^2 / (d_j - lambda), so at an eigenvalue (phi = 0)
+// f'(lambda) = (d_n - lambda) phi'(lambda) = (d_n - lambda) rho ||q||^2, while
+// f'(lambda) = -||x||^2.  Hence 1/||q|| = sqrt(rho (lambda - d_n)) / ||x||, with
+// lambda - d_n = (pole - d_n) + offset, no cancellation while lambda is not the
+// eigenvalue next to d_n that the check stage re-measures.  NaN (a norm pass
+// then runs) when lambda - d_n is not positive.
+__host__ __device__ inline double dpr1_inorm(const Prob& P, double inrm_x, double lam_minus_pole, double pole) {
+  const double ldn = (pole - P.ds[P.nsorted - 1]) + lam_minus_pole;
+  return (ldn > 0.0 && inrm_x == inrm_x) ? inrm_x * sqrt(P.rho * ldn) : NAN;
+}
+
 __host__ __device__ inline double norm_from_pass(const double* last, double nu, double cx) {
   const double l = last[0], a0 = last[1] + cx;
   // the step enters as (nu - l) / l: the product of the sums with 1/l alone
@@ -460,10 +474,11 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   // the rational pass forms for psi'.  It was formed at that pass's point;
   // the step to the final nu is taken to first order, d/dnu (nu^2 S2(nu)) =
   // 2 nu S2 - 2 nu^2 S3 with S3 = sum zeta_j^2 e_j v_j^3, also formed there.
-  // (DPR1's vector is not the arrowhead's: its norm takes a pass of its own.)
+  // DPR1's vector is not the arrowhead's; its norm follows from the arrowhead's (dpr1_inorm).
   double nr1 = NAN;
-  if constexpr (KIND != KIND_DPR1) {
-    if (last[0] == last[0]) nr1 = norm_from_pass(last, nu, P.ch[i]);
+  if (last[0] == last[0]) {
+    nr1 = norm_from_pass(last, nu, P.ch[i]);
+    if constexpr (KIND == KIND_DPR1) nr1 = dpr1_inorm(P, nr1, 1.0 / nu, P.ds[i]);
   }
   if (ln == 0) {
     w.cnt[6 * k + 0] = iters;
@@ -661,7 +676,10 @@ __host__ __device__ inline bool check_body(const ProbDesc& D, const Options& opt
                                             nu_est, last)
                 : bisect_inverse<KIND, G>(P, i2, bp.b, bp.lo, bp.hi, ln, &it);
             pv = d2; s = 0.0; mu = 1.0 / nu;
-            if (KIND != KIND_DPR1 && last[0] == last[0]) rn = norm_from_pass(last, nu, P.ch[i2]);
+            if (last[0] == last[0]) {
+              rn = norm_from_pass(last, nu, P.ch[i2]);
+              if constexpr (KIND == KIND_DPR1) rn = dpr1_inorm(P, rn, mu, d2);
+            }
             fl |= INFO_REMEDY_A;
             done = true;
             c_it += it; c_dd += opt.fp64_b ? 0 : 1; c_plain += opt.fp64_b ? 1 : 0;
@@ -675,7 +693,10 @@ __host__ __device__ inline bool check_body(const ProbDesc& D, const Options& opt
           double last[3] = {NAN, NAN, NAN};
           const double m2 = dpr1_inverse<KIND, G>(P, di, s, ln, &z0, &it, opt.root, 1.0 / (mu - s), last);
           pv = di; mu = z0 ? 0.0 : m2;
-          if (KIND != KIND_DPR1 && !z0 && last[0] == last[0]) rn = norm_from_pass(last, 1.0 / m2, 0.0);
+          if (!z0 && last[0] == last[0]) {
+            rn = norm_from_pass(last, 1.0 / m2, 0.0);
+            if constexpr (KIND == KIND_DPR1) rn = dpr1_inorm(P, rn, s + m2, di);
+          }
           fl |= INFO_REMEDY_B;
           c_it += it; c_dd += 1;
         }
@@ -698,6 +719,7 @@ __host__ __device__ inline bool check_body(const ProbDesc& D, const Options& opt
         int it = 0;
         const double t2 = dpr1_from_last_pole<G>(P, tau, ln, &it);
         pv = dn; s = 0.0; mu = t2;
+        rn = NAN;   // a remedy's norm above was for the eigenvalue before this re-measure
         fl |= INFO_POLE_SHIFT;
         c_it += it;
       }
