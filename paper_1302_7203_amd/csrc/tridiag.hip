@@ -325,9 +325,10 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
       int2* dsp = (int2*)recs.p;
       if (hipMemcpyAsync(dsp, copies.data(), copies.size() * sizeof(int2), hipMemcpyHostToDevice, st) != hipSuccess)
         return ARROW_ERR_HIP;
+      // recs is written again below, after this kernel in stream order; the host's copy
+      // list is refilled only after the next synchronisation
       hipLaunchKernelGGL(k_td_copy, dim3(64, (unsigned)copies.size()), dim3(TD_BLOCK), 0, st, dsp, (int)n,
                          qb[in ^ 1], qb[in]);
-      if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // recs is reused below
     }
     // the merges of this level; u of every one, then eigenvalues and u to the host
     all.clear();
@@ -449,7 +450,9 @@ int tridiag_eig(arrow_handle_t h, int64_t n, const double* a, const double* b, d
                        qb[outb]);
     hipLaunchKernelGGL(k_td_scatter, dim3(grid_x(widest * widest), (unsigned)all.size()), dim3(TD_BLOCK), 0, st, drec,
                        (const int*)posb.p, (const double*)scratch, (int)n, qb[outb]);
-    if (hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;   // host arrays are refilled next level
+    // the host arrays copied to the device above are refilled next level: the plan's
+    // destruction synchronised the stream after those copies; without a plan, wait here
+    if (descs.empty() && hipStreamSynchronize(st) != hipSuccess) return ARROW_ERR_HIP;
   }
   // results: eigenvalues (descending) and the root's block
   const int fin = H & 1;
