@@ -66,7 +66,7 @@ typedef struct arrow_handle_s* arrow_handle_t;
 #define ARROW_N_MAX 33554432
 
 /* options for arrow_set_option */
-#define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 30) */
+#define ARROW_OPT_TAU_NU 1     /* K_nu above which a Remark 2 remedy is applied (default 100) */
 #define ARROW_OPT_TAU_ZERO 2   /* (|d_i|+|mu|)/|lambda| above which Remark 1 applies (default 10) */
 #define ARROW_OPT_FP64_B 3     /* 1: b in FP64 only (Algorithm 2), a negative control (default 0) */
 #define ARROW_OPT_REMEDIES 4   /* 0: no K_nu / near-zero remedies (default 1) */

@@ -471,7 +471,7 @@ int arrow_create(arrow_handle_t* h, int device) {
   if (!p) return ARROW_ERR_NOMEM;
   p->device = device;
   p->stream = nullptr;
-  p->opt.tau_nu = 30.0;
+  p->opt.tau_nu = 100.0;
   p->opt.check_lanes = 4;
   p->opt.tau_zero = 10.0;
   p->opt.fp64_b = 0;

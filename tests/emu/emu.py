@@ -51,7 +51,7 @@ def set_batch_check(on: bool):
     _load().emu_set_batch_check(1 if on else 0)
 
 
-def solve(kind, d, z, scalar, vectors=True, tau_nu=30.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1, tau_b=0.0):
+def solve(kind, d, z, scalar, vectors=True, tau_nu=100.0, tau_zero=10.0, fp64_b=0, remedies=1, root=1, tau_b=0.0):
     """kind 0 arrowhead, 1 DPR1, 2 SVD, 3 Hermitian arrowhead (complex z; complex V).
     Returns dict of numpy arrays (V[:, k] = k-th vector)."""
     d = np.ascontiguousarray(d, dtype=np.float64)
