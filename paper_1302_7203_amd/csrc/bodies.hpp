@@ -466,7 +466,7 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   int iters = 0;
   double last[3] = {NAN, NAN, NAN};   // the rational pass's last point nu and its sums S2, S3
   const double nu = (opt.root == ROOT_RATIONAL)
-      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters, NAN, last)
+      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters, bp.x0, last)
       : bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
   // ||x||^2 of eq. (eigenvecAi) at mu = 1/nu: with v_j = 1/(nu e_j - 1) the
   // entry x_j = zeta_j/(e_j - mu) is nu zeta_j v_j (j != i) and x_i = -nu zeta_i, so

@@ -48,6 +48,9 @@ constexpr double EPS = 2.220446049250313080847e-16;  // 2^-52, eps of Algorithm 
 constexpr int MAX_BISECT = 4000;
 constexpr int MAX_RATIONAL = 60;     // rational steps before falling back to bisection steps
 constexpr int RATIONAL_TO_BISECT = 14;
+#ifndef AHD_START_MODEL
+#define AHD_START_MODEL 1
+#endif
 #ifndef AHD_EARLY2
 #define AHD_EARLY2 24
 #define AHD_EARLY1 36
@@ -341,6 +344,7 @@ __host__ __device__ inline void select_shift(const Prob& P, int k, int ln, int& 
 
 struct BPass {
   double b, Kb, lo, hi;
+  double x0;   // a start for the root in x = side*nu from a two-pole model (NaN: none)
 };
 
 template <int KIND, int G, bool FP64_B>
@@ -352,7 +356,7 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   double f1 = 0.0, f2 = 0.0;            // the same sums in FP64 (Algorithm 2 only)
   // sum_{j != i} zeta_j^2 (gs / e_j)^2 with gs the power of two at or below
   // the distance to the nearest pole, so that every gs / e_j is at most 1
-  double r2 = 0.0;
+  double r2 = 0.0, r3 = 0.0;   // and sum zeta_j^2 (gs / e_j)^3, for the start model
   double dn = INFINITY;
   if (i > 0) dn = fabs(pdiff<KIND>(P.ds[i - 1], di));
   if (i + 1 < m) dn = fmin(dn, fabs(pdiff<KIND>(P.ds[i + 1], di)));
@@ -375,9 +379,16 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
     const double rs = rj * gs;
-    r2 = fma(t.ch, rs * rs, r2);
+    const double rs2 = rs * rs;
+    r2 = fma(t.ch, rs2, r2);
+#if AHD_START_MODEL
+    r3 = fma(t.ch, rs2 * rs, r3);
+#endif
   });
   r2 = gsum<G>(r2);
+#if AHD_START_MODEL
+  r3 = gsum<G>(r3);
+#endif
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
   const double ci = P.ch[i];
   BPass r;
@@ -420,6 +431,42 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   const double xh = (xl + u) * (1.0 + 64.0 * EPS);
   if (side > 0) { r.lo = xl; r.hi = xh; }
   else { r.lo = -xh; r.hi = -xl; }
+  r.x0 = NAN;
+#if AHD_START_MODEL
+  // A start nearer the zero than xh: keep the nearest pole y = xl exact with its
+  // residue ry and put the rest of the residue mass, R - ry, at its mean
+  // position p (first moment over mass), so h(x) ~ c0 - x + ry/(x - y) + Rr/(x - p).
+  // In units of 1/gs (x' = gs x) every quantity is of moderate size.  The model
+  // lies below the bound whose zero is xh (p <= y), so it is negative there;
+  // it is decreasing and convex right of y, and Newton's steps from a point left
+  // of its zero approach the zero from the left: a first step from xh, then steps
+  // from wherever it lands, kept inside (y, xh).
+  if (jn >= 0 && jn < m && xl > 0.0) {
+    const double rci = 1.0 / ci;
+    const double rg = gs * recip(pdiff<KIND>(P.ds[jn], di));
+    const double ry = P.ch[jn] * rci * (rg * rg);
+    const double rt = (r2 + gs * gs) * rci;
+    const double rr = rt - ry;
+    const double yy = xl * gs, c0 = sg * r.b * gs, xhh = xh * gs;
+    const double m1 = sg * r3 * rci - ry * yy;   // first moment of the rest (the pole at 0 adds none)
+    if (rr > 0.0 && yy < xhh) {
+      const double pp = fmin(m1 / rr, yy);
+      // the model is only a start, good to about 1e-3 of the zero: four steps
+      // with the fast reciprocal solve it well past that
+      double x = xhh;
+      for (int k = 0; k < 4; ++k) {
+        const double a1 = recip(x - yy), a2 = recip(x - pp);
+        const double h = c0 - x + ry * a1 + rr * a2;
+        const double dh = -1.0 - ry * a1 * a1 - rr * a2 * a2;
+        double xn = x - h * recip(dh);
+        if (!(xn > yy)) xn = 0.5 * (x + yy);
+        if (!(xn < xhh)) xn = xhh;
+        x = xn;
+      }
+      r.x0 = sg * (x / gs);   // back to nu
+    }
+  }
+#endif
   return r;
 }
 
