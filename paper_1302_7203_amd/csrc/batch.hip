@@ -87,9 +87,27 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
   }
 }
 
-// First pass of one eigenvalue of an item (G lanes each).
+// First pass of one eigenvalue of an item (G lanes each).  hot: what the
+// wavefront's LDS slice holds -- 1 the sorted poles and then the shaft
+// weights, 2 the poles alone, 0 nothing.
 template <int KIND>
-__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln) {
+__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln, int hot,
+                                 const double* lds) {
+  const double* hc = lds + sorted_count(D);
+  if (hot == 1) {
+    switch (G) {
+      case 4: root_body<KIND, 4, 1>(D, opt, k, ln, lds, hc); return;
+      case 8: root_body<KIND, 8, 1>(D, opt, k, ln, lds, hc); return;
+      default: root_body<KIND, 16, 1>(D, opt, k, ln, lds, hc); return;
+    }
+  }
+  if (hot == 2) {
+    switch (G) {
+      case 4: root_body<KIND, 4, 2>(D, opt, k, ln, lds); return;
+      case 8: root_body<KIND, 8, 2>(D, opt, k, ln, lds); return;
+      default: root_body<KIND, 16, 2>(D, opt, k, ln, lds); return;
+    }
+  }
   switch (G) {
     case 4: root_body<KIND, 4>(D, opt, k, ln); break;
     case 8: root_body<KIND, 8>(D, opt, k, ln); break;
@@ -98,6 +116,15 @@ __device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, i
     default: root_body<KIND, 64>(D, opt, k, ln); break;
   }
 }
+
+// Doubles of LDS per wavefront for a problem's sorted poles and shaft weights
+// (2 (n - 1), DPR1 2n), or for the poles alone when both do not fit: every
+// pass of the root stage reads them, each lane a term at a time, and from LDS
+// they come without the vector memory path.
+#ifndef AHD_ROOT_STAGE
+#define AHD_ROOT_STAGE 1280
+#endif
+constexpr int ROOT_STAGE = AHD_ROOT_STAGE;
 
 // Check stage of one item: the 64/G eigenvalues k0, k0 + 1, ... of one
 // problem, G lanes each (every lane of the wavefront calls this; lanes past
@@ -146,6 +173,9 @@ constexpr int ROOT_WAVES = AHD_ROOT_WAVES;
 __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(ROOT_WAVES))) void k_b_root(
     BatchArgs B, Options opt) {
   const int lane = threadIdx.x & (WAVE - 1);
+  __shared__ double lds_all[STAGE_BLOCK / WAVE][ROOT_STAGE > 0 ? ROOT_STAGE : 1];
+  double* lds = lds_all[threadIdx.x / WAVE];
+  int staged = -1;   // the problem whose arrays the slice holds
   for (;;) {
     int first = 0;
     if (lane == 0) first = (int)atomicAdd(&B.counters[0], (unsigned)ROOT_CHUNK);
@@ -158,12 +188,29 @@ __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(ROO
       const int G = B.lanes[p];
       const int k = (item - B.item_start[p]) * (WAVE / G) + lane / G;
       const int ln = lane & (G - 1);
+      const int ns = sorted_count(D);
+      const int hot = G > 16 ? 0 : (2 * ns <= ROOT_STAGE ? 1 : (ns <= ROOT_STAGE ? 2 : 0));
+      if (hot && staged != p) {
+        // the slice is the wavefront's own: its LDS reads and writes run in
+        // order, so only the compiler must not move them across the copy
+        const Ws w = ws_view(D.ws, D.n);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int j = lane; j < ns; j += WAVE) {
+          lds[j] = w.ds[j];
+          if (hot == 1) lds[ns + j] = w.ch[j];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        staged = p;
+      }
       if (k < D.n) {
         switch (D.kind) {
           case KIND_ARROW:
-          case KIND_HERM: root_kind<KIND_ARROW>(D, opt, G, k, ln); break;   // HERM: the real arrowhead on |z|
-          case KIND_DPR1: root_kind<KIND_DPR1>(D, opt, G, k, ln); break;
-          default: root_kind<KIND_SVD>(D, opt, G, k, ln); break;
+          case KIND_HERM: root_kind<KIND_ARROW>(D, opt, G, k, ln, hot, lds); break;   // HERM: the real arrowhead on |z|
+          case KIND_DPR1: root_kind<KIND_DPR1>(D, opt, G, k, ln, hot, lds); break;
+          default: root_kind<KIND_SVD>(D, opt, G, k, ln, hot, lds); break;
         }
       }
     }

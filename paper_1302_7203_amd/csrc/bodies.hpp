@@ -128,10 +128,11 @@ __host__ __device__ inline int count_above(const double* a, int len, double x, b
   return lo;
 }
 
-// HOT: hot_d / hot_c are copies of the sorted poles and shaft weights (in LDS)
-// used by the O(n) passes in place of the workspace arrays.  A compile-time
-// choice, so that the compiler knows which memory the passes read.
-template <bool HOT = false>
+// HOT = 1: hot_d / hot_c are copies of the sorted poles and shaft weights (in
+// LDS) used by the O(n) passes in place of the workspace arrays; HOT = 2: the
+// poles alone (hot_c unused).  A compile-time choice, so that the compiler
+// knows which memory the passes read.
+template <int HOT = 0>
 __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const double* hot_d = nullptr,
                                           const double* hot_c = nullptr) {
   Prob P;
@@ -145,10 +146,8 @@ __host__ __device__ inline Prob make_prob(const ProbDesc& D, const Ws& w, const 
   P.dz = w.dz;
   P.corner = {w.hdr[0], w.hdr[1]};
   P.rho = D.scalar;
-  if constexpr (HOT) {
-    P.ds = hot_d;
-    P.ch = hot_c;
-  }
+  if constexpr (HOT >= 1) P.ds = hot_d;
+  if constexpr (HOT == 1) P.ch = hot_c;
   return P;
 }
 
@@ -424,7 +423,7 @@ __host__ __device__ inline double norm_from_pass(const double* last, double nu, 
   return fabs(rl) / sqrt(a0 + dl + rl * rl);
 }
 
-template <int KIND, int G, bool HOT = false>
+template <int KIND, int G, int HOT = 0>
 __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln,
                                           const double* hot_d = nullptr, const double* hot_c = nullptr) {
   const Ws w = ws_view(D.ws, D.n);

@@ -433,9 +433,10 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   else { r.lo = -xh; r.hi = -xl; }
   r.x0 = NAN;
 #if AHD_START_MODEL
-  // A start nearer the zero than xh: keep the nearest pole y = xl exact with its
-  // residue ry and put the rest of the residue mass, R - ry, at its mean
-  // position p (first moment over mass), so h(x) ~ c0 - x + ry/(x - y) + Rr/(x - p).
+  // A start nearer the zero than xh: keep the nearest pole y = xl and the next
+  // one on the same side exact with their residues and put the rest of the
+  // residue mass at its mean position p (first moment over mass), so
+  // h(x) ~ c0 - x + ry/(x - y) + r2/(x - y2) + Rr/(x - p).
   // In units of 1/gs (x' = gs x) every quantity is of moderate size.  The model
   // lies below the bound whose zero is xh (p <= y), so it is negative there;
   // it is decreasing and convex right of y, and Newton's steps from a point left
@@ -448,16 +449,27 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
     const double rt = (r2 + gs * gs) * rci;
     const double rr = rt - ry;
     const double yy = xl * gs, c0 = sg * r.b * gs, xhh = xh * gs;
-    const double m1 = sg * r3 * rci - ry * yy;   // first moment of the rest (the pole at 0 adds none)
+    double m1 = sg * r3 * rci - ry * yy;   // first moment of the rest (the pole at 0 adds none)
+    // the next pole on the same side is kept exact too
+    const int j2 = jn - side;
+    double y2 = 0.0, rx2 = 0.0;
+    if (j2 >= 0 && j2 < m) {
+      const double g2 = gs * recip(pdiff<KIND>(P.ds[j2], di));
+      y2 = sg * g2;
+      rx2 = P.ch[j2] * rci * (g2 * g2);
+    }
+    const double rrest = rr - rx2;
+    m1 -= rx2 * y2;
     if (rr > 0.0 && yy < xhh) {
-      const double pp = fmin(m1 / rr, yy);
+      const double pp = rrest > 0.0 ? fmin(m1 / rrest, yy) : 0.0;
+      const double rq = fmax(rrest, 0.0);
       // the model is only a start, good to about 1e-3 of the zero: four steps
       // with the fast reciprocal solve it well past that
       double x = xhh;
       for (int k = 0; k < 4; ++k) {
-        const double a1 = recip(x - yy), a2 = recip(x - pp);
-        const double h = c0 - x + ry * a1 + rr * a2;
-        const double dh = -1.0 - ry * a1 * a1 - rr * a2 * a2;
+        const double a1 = recip(x - yy), a2 = recip(x - pp), a3 = recip(x - y2);
+        const double h = c0 - x + ry * a1 + rq * a2 + rx2 * a3;
+        const double dh = -1.0 - ry * a1 * a1 - rq * a2 * a2 - rx2 * a3 * a3;
         double xn = x - h * recip(dh);
         if (!(xn > yy)) xn = 0.5 * (x + yy);
         if (!(xn < xhh)) xn = xhh;
@@ -713,70 +725,108 @@ __host__ __device__ inline double bounded_next(double x, double h, double hnoise
   return (lo > 0.0 && hi > 16.0 * lo) ? bits_mid(lo, hi) : 0.5 * (lo + hi);
 }
 
-// extreme eigenvalue of A_i^{-1} on the given side, by the rational iteration
-template <int KIND, int G>
-__host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
-                                                   double hi, double ymax_nu, int ln, int* iters,
-                                                   double nu_est = NAN, double* last = nullptr) {
-  const double sg = (double)side;
-  const double di = P.ds[i];
-  const double rci = 1.0 / P.ch[i];
-  const double src = 1.0 / sqrt(P.ch[i]);   // sqrt(rci)
+// Extreme eigenvalue of A_i^{-1} on the given side, by the rational iteration.
+// The iteration is split into its set-up and its steps so that a caller can
+// stop after a few passes and resume later, possibly on other lanes: RatState
+// is everything a step reads and updates, RatConsts what follows from (i, side)
+// and the lower end y alone.
+struct RatState {
+  double x, xlo, xhi;   // next point and the bracket kept from the signs of h, in x = side*nu
+  double slo, shi;      // the tightest model bounds met so far (bounded_next)
+  double c0, y;         // side*b and the nearest pole of psi_x (x-space)
+  int it, hi_open;      // steps taken; xhi is a bound that has not been evaluated
+};
+
+struct RatConsts {
+  double sg, rci, src, sry;
+};
+
+// rci = 1/zeta_i^2, src = its square root and sry the square root of the
+// residue of psi_x at y: c_jn / (zeta_i^2 e_jn^2) for the neighbouring pole jn,
+// or 1/zeta_i^2 for the pole at 0 when no pole lies right of it
+template <int KIND>
+__host__ __device__ inline RatConsts rat_consts(const Prob& P, int i, int side, double y) {
+  RatConsts c;
+  c.sg = (double)side;
+  c.rci = 1.0 / P.ch[i];
+  c.src = 1.0 / sqrt(P.ch[i]);
+  c.sry = c.src;
+  if (y > 0.0) {
+    const double e = pdiff<KIND>(P.ds[i - side], P.ds[i]);
+    c.sry = sqrt(P.ch[i - side]) * c.src / fabs(e);
+  }
+  return c;
+}
+
+__host__ __device__ inline RatState rat_init(const RatConsts& c, double b, double lo, double hi, double ymax_nu,
+                                             double nu_est) {
+  RatState s;
   // x-space bracket
-  double xlo = (side > 0) ? lo : -hi;
-  double xhi = (side > 0) ? hi : -lo;
-  const double y = sg * ymax_nu;
-  const double c0 = sg * b;
-  double x = xhi;
-  int hi_open = 0;   // xhi is a bound that has not been evaluated
-  if (y <= 0.0) {
+  s.xlo = (c.sg > 0) ? lo : -hi;
+  s.xhi = (c.sg > 0) ? hi : -lo;
+  s.y = c.sg * ymax_nu;
+  s.c0 = c.sg * b;
+  s.x = s.xhi;
+  s.hi_open = 0;
+  if (s.y <= 0.0) {
     // exterior eigenvalue: every other pole of psi_x lies left of 0 and its
     // term is positive for x > 0, so h(x) >= c0 - x + rci / x and the zero of
     // that two-by-two model (the corner block of A_i^{-1}) bounds the wanted
     // zero from below.  Across the decades between it and the Gershgorin bound
     // the iteration starts from the bit-pattern midpoint.
-    const double x2 = pos_root(c0, src);
-    xlo = fmax(xlo, x2 * (1.0 - 4.0 * EPS));
-    if (xlo > 0.0 && xhi > 16.0 * xlo) {
-      x = bits_mid(xlo, xhi);
-      hi_open = 1;
+    const double x2 = pos_root(s.c0, c.src);
+    s.xlo = fmax(s.xlo, x2 * (1.0 - 4.0 * EPS));
+    if (s.xlo > 0.0 && s.xhi > 16.0 * s.xlo) {
+      s.x = bits_mid(s.xlo, s.xhi);
+      s.hi_open = 1;
     }
   }
   // an estimate (a repair re-solving a known eigenvalue from another shift)
   // inside the bracket is the better start
-  const double x_est = sg * nu_est;
-  if (x_est > xlo && x_est < xhi) x = x_est;
-  // square root of the residue of psi_x at y: c_jn / (zeta_i^2 e_jn^2) for the
-  // neighbouring pole jn, or 1/zeta_i^2 for the pole at 0 when no pole lies
-  // right of it
-  double sry = src;
-  if (y > 0.0) {
-    const double e = pdiff<KIND>(P.ds[i - side], di);
-    sry = sqrt(P.ch[i - side]) * src / fabs(e);
+  const double x_est = c.sg * nu_est;
+  if (x_est > s.xlo && x_est < s.xhi) s.x = x_est;
+  s.slo = s.xlo;
+  s.shi = s.xhi;
+  s.it = 0;
+  return s;
+}
+
+// One pass at s.x and the next point; true when the iteration has finished
+// (s.x is then the root).  last[] receives the pass's point and sums.
+template <int KIND, int G>
+__host__ __device__ inline bool rat_step(const Prob& P, int i, const RatConsts& c, RatState& s, int ln,
+                                         double* last) {
+  if (s.x >= s.xhi) s.hi_open = 0;
+  const double nu = c.sg * s.x;
+  double s1, s2, s3;
+  psi_pass<KIND, G, false>(P, P.ds[i], 0.0, i, nu, ln, s1, s2, s3);
+  if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
+  const double rnu = 1.0 / nu;
+  const double psi = (s1 + rnu) * c.rci;                       // psi(nu)
+  const double dpsi = -(s2 + rnu * rnu) * c.rci;               // psi'(nu)
+  const double d2psi = 2.0 * (s3 * rnu + rnu * rnu * rnu) * c.rci;   // psi''(nu)
+  const double psi_x = c.sg * psi, dpsi_x = dpsi, d2psi_x = c.sg * d2psi;
+  const double h = s.c0 - s.x + psi_x;
+  if (h > 0) s.xlo = s.x; else s.xhi = s.x;
+  if (h == 0) return true;
+  const double hnoise = 8.0 * EPS * (fabs(s.c0) + fabs(s.x) + fabs(psi_x));
+  int done = 0;
+  s.x = bounded_next(s.x, h, hnoise, psi_x, dpsi_x, d2psi_x, s.y, c.sry, s.c0, s.xlo, s.xhi, s.it, s.hi_open, s.slo,
+                     s.shi, &done);
+  ++s.it;
+  return done || s.it >= MAX_RATIONAL + MAX_BISECT;
+}
+
+template <int KIND, int G>
+__host__ __device__ inline double rational_inverse(const Prob& P, int i, int side, double b, double lo,
+                                                   double hi, double ymax_nu, int ln, int* iters,
+                                                   double nu_est = NAN, double* last = nullptr) {
+  const RatConsts c = rat_consts<KIND>(P, i, side, (double)side * ymax_nu);
+  RatState s = rat_init(c, b, lo, hi, ymax_nu, nu_est);
+  while (!rat_step<KIND, G>(P, i, c, s, ln, last)) {
   }
-  double slo = xlo, shi = xhi;
-  int it = 0;
-  for (; it < MAX_RATIONAL + MAX_BISECT; ++it) {
-    if (x >= xhi) hi_open = 0;
-    const double nu = sg * x;
-    double s1, s2, s3;
-    psi_pass<KIND, G, false>(P, di, 0.0, i, nu, ln, s1, s2, s3);
-    if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
-    const double rnu = 1.0 / nu;
-    const double psi = (s1 + rnu) * rci;                       // psi(nu)
-    const double dpsi = -(s2 + rnu * rnu) * rci;               // psi'(nu)
-    const double d2psi = 2.0 * (s3 * rnu + rnu * rnu * rnu) * rci;   // psi''(nu)
-    const double psi_x = sg * psi, dpsi_x = dpsi, d2psi_x = sg * d2psi;
-    const double h = c0 - x + psi_x;
-    if (h > 0) xlo = x; else xhi = x;
-    if (h == 0) break;
-    const double hnoise = 8.0 * EPS * (fabs(c0) + fabs(x) + fabs(psi_x));
-    int done = 0;
-    x = bounded_next(x, h, hnoise, psi_x, dpsi_x, d2psi_x, y, sry, c0, xlo, xhi, it, hi_open, slo, shi, &done);
-    if (done) { ++it; break; }
-  }
-  if (iters) *iters = it;
-  return sg * x;
+  if (iters) *iters = s.it;
+  return c.sg * s.x;
 }
 
 // ---------------------------------------------------------------------------
