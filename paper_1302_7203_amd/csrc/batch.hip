@@ -87,33 +87,99 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
   }
 }
 
-// First pass of one eigenvalue of an item (G lanes each).  hot: what the
-// wavefront's LDS slice holds -- 1 the sorted poles and then the shaft
-// weights, 2 the poles alone, 0 nothing.
-template <int KIND>
-__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int ln, int hot,
+// First pass of the 64/G eigenvalues of an item, G lanes each (every lane of
+// the wavefront calls this; `valid`: the lane's eigenvalue k exists).  The
+// rational iteration takes from one to several passes, and on fixed groups
+// every group would wait for the slowest of its wavefront.  Instead, after
+// each step, once the unfinished eigenvalues fit in groups twice as wide,
+// they are regrouped: the g-th unfinished one moves (its state copied lane to
+// lane) to lanes [g gc, (g + 1) gc) with gc the widest power of two that fits,
+// so its further passes run on more lanes.  All groups solve the item's
+// problem, so they keep reading the same poles.  The regrouping depends only
+// on the item's own eigenvalues: a problem gives the same bits alone or in any
+// batch.  HOT: what the wavefront's LDS slice holds (make_prob).
+template <int KIND, int G, int HOT>
+__device__ inline void root_item(const ProbDesc& D, const Options& opt, int k, int lane, bool valid,
                                  const double* lds) {
-  const double* hc = lds + sorted_count(D);
+  const int ln = lane & (G - 1);
+  const Ws w = ws_view(D.ws, D.n);
+  const Prob P = make_prob<HOT>(D, w, lds, lds + sorted_count(D));
+  int i = 0;
+  RatConsts c{};
+  RatState s{};
+  bool mine = false;   // the lane's group holds an unfinished eigenvalue
+  if (valid) mine = root_begin<KIND, G, HOT>(D, opt, w, P, k, ln, i, c, s);
+  double last[3] = {NAN, NAN, NAN};
+  if constexpr (G == WAVE) {
+    if (mine) {
+      while (!rat_step<KIND, G>(P, i, c, s, ln, last)) {
+      }
+      root_finish<KIND>(P, w, k, i, ln, c.sg * s.x, s.it, last);
+    }
+  } else {
+    int gc = G, lc = ln;
+    for (;;) {
+      if (mine && rat_step<KIND, 0>(P, i, c, s, lc, last, gc)) {
+        root_finish<KIND>(P, w, k, i, lc, c.sg * s.x, s.it, last);
+        mine = false;
+      }
+      const uint64_t live = __ballot(mine && lc == 0);   // first lanes of the unfinished groups
+      if (live == 0) break;
+      const int a = __popcll(live);
+      int gn = gc;
+      while (gn < WAVE && 2 * gn * a <= WAVE) gn *= 2;
+      if (gn != gc) {
+        const int g = lane / gn;
+        uint64_t rest = live;
+        for (int t = 0; t < g && rest; ++t) rest &= rest - 1;
+        const int src = rest ? __builtin_ctzll(rest) : lane;
+        k = __shfl(k, src);
+        i = __shfl(i, src);
+        c.sg = __shfl(c.sg, src);
+        c.rci = __shfl(c.rci, src);
+        c.sry = __shfl(c.sry, src);
+        s.x = __shfl(s.x, src);
+        s.xlo = __shfl(s.xlo, src);
+        s.xhi = __shfl(s.xhi, src);
+        s.slo = __shfl(s.slo, src);
+        s.shi = __shfl(s.shi, src);
+        s.c0 = __shfl(s.c0, src);
+        s.y = __shfl(s.y, src);
+        s.it = __shfl(s.it, src);
+        s.hi_open = __shfl(s.hi_open, src);
+        mine = g < a;
+        gc = gn;
+        lc = lane & (gn - 1);
+      }
+    }
+  }
+}
+
+// hot: what the wavefront's LDS slice holds -- 1 the sorted poles and then
+// the shaft weights, 2 the poles alone, 0 nothing (G <= 16 only).
+template <int KIND>
+__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int lane, bool valid, int hot,
+                                 const double* lds) {
   if (hot == 1) {
     switch (G) {
-      case 4: root_body<KIND, 4, 1>(D, opt, k, ln, lds, hc); return;
-      case 8: root_body<KIND, 8, 1>(D, opt, k, ln, lds, hc); return;
-      default: root_body<KIND, 16, 1>(D, opt, k, ln, lds, hc); return;
+      case 4: root_item<KIND, 4, 1>(D, opt, k, lane, valid, lds); return;
+      case 8: root_item<KIND, 8, 1>(D, opt, k, lane, valid, lds); return;
+      default: root_item<KIND, 16, 1>(D, opt, k, lane, valid, lds); return;
     }
   }
   if (hot == 2) {
     switch (G) {
-      case 4: root_body<KIND, 4, 2>(D, opt, k, ln, lds); return;
-      case 8: root_body<KIND, 8, 2>(D, opt, k, ln, lds); return;
-      default: root_body<KIND, 16, 2>(D, opt, k, ln, lds); return;
+      case 4: root_item<KIND, 4, 2>(D, opt, k, lane, valid, lds); return;
+      case 8: root_item<KIND, 8, 2>(D, opt, k, lane, valid, lds); return;
+      default: root_item<KIND, 16, 2>(D, opt, k, lane, valid, lds); return;
     }
   }
   switch (G) {
-    case 4: root_body<KIND, 4>(D, opt, k, ln); break;
-    case 8: root_body<KIND, 8>(D, opt, k, ln); break;
-    case 16: root_body<KIND, 16>(D, opt, k, ln); break;
-    case 32: root_body<KIND, 32>(D, opt, k, ln); break;
-    default: root_body<KIND, 64>(D, opt, k, ln); break;
+    case 4: root_item<KIND, 4, 0>(D, opt, k, lane, valid, lds); break;
+    case 8: root_item<KIND, 8, 0>(D, opt, k, lane, valid, lds); break;
+    case 16: root_item<KIND, 16, 0>(D, opt, k, lane, valid, lds); break;
+    case 32: root_item<KIND, 32, 0>(D, opt, k, lane, valid, lds); break;
+    default: root_item<KIND, 64, 0>(D, opt, k, lane, valid, lds); break;
   }
 }
 
@@ -187,7 +253,6 @@ __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(ROO
       const ProbDesc D = B.descs[p];
       const int G = B.lanes[p];
       const int k = (item - B.item_start[p]) * (WAVE / G) + lane / G;
-      const int ln = lane & (G - 1);
       const int ns = sorted_count(D);
       const int hot = G > 16 ? 0 : (2 * ns <= ROOT_STAGE ? 1 : (ns <= ROOT_STAGE ? 2 : 0));
       if (hot && staged != p) {
@@ -205,13 +270,12 @@ __global__ __launch_bounds__(STAGE_BLOCK) __attribute__((amdgpu_waves_per_eu(ROO
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         staged = p;
       }
-      if (k < D.n) {
-        switch (D.kind) {
-          case KIND_ARROW:
-          case KIND_HERM: root_kind<KIND_ARROW>(D, opt, G, k, ln, hot, lds); break;   // HERM: the real arrowhead on |z|
-          case KIND_DPR1: root_kind<KIND_DPR1>(D, opt, G, k, ln, hot, lds); break;
-          default: root_kind<KIND_SVD>(D, opt, G, k, ln, hot, lds); break;
-        }
+      const bool valid = k < D.n;
+      switch (D.kind) {
+        case KIND_ARROW:
+        case KIND_HERM: root_kind<KIND_ARROW>(D, opt, G, k, lane, valid, hot, lds); break;   // HERM: the real arrowhead on |z|
+        case KIND_DPR1: root_kind<KIND_DPR1>(D, opt, G, k, lane, valid, hot, lds); break;
+        default: root_kind<KIND_SVD>(D, opt, G, k, lane, valid, hot, lds); break;
       }
     }
   }

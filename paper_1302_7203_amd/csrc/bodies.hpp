@@ -423,32 +423,58 @@ __host__ __device__ inline double norm_from_pass(const double* last, double nu, 
   return fabs(rl) / sqrt(a0 + dl + rl * rl);
 }
 
+// The results of a first pass that depend on its root: mu, the step count and
+// the norm.  ||x||^2 of eq. (eigenvecAi) at mu = 1/nu: with v_j = 1/(nu e_j - 1)
+// the entry x_j = zeta_j/(e_j - mu) is nu zeta_j v_j (j != i) and x_i = -nu zeta_i,
+// so ||x||^2 = nu^2 (S2 + zeta_i^2) + 1, S2 = sum_{j != i} zeta_j^2 v_j^2 -- the sum
+// the rational pass forms for psi'.  It was formed at that pass's point; the
+// step to the final nu is taken to first order, d/dnu (nu^2 S2(nu)) =
+// 2 nu S2 - 2 nu^2 S3 with S3 = sum zeta_j^2 e_j v_j^3, also formed there.
+// DPR1's vector is not the arrowhead's; its norm follows from the arrowhead's
+// (dpr1_inorm).
+template <int KIND>
+__host__ __device__ inline void root_finish(const Prob& P, const Ws& w, int k, int i, int ln, double nu, int iters,
+                                            const double* last) {
+  double nr1 = NAN;
+  if (last[0] == last[0]) {
+    nr1 = norm_from_pass(last, nu, P.ch[i]);
+    if constexpr (KIND == KIND_DPR1) nr1 = dpr1_inorm(P, nr1, 1.0 / nu, P.ds[i]);
+  }
+  if (ln == 0) {
+    w.cnt[6 * k + 0] = iters;
+    w.mu1[k] = 1.0 / nu;
+    w.nr1[k] = nr1;
+  }
+}
+
+// The first pass up to its root: the cases with nothing to solve, the shift,
+// b and the outputs that follow from them.  Returns true when the rational
+// iteration is left to run from (i, c, s); otherwise the pass is complete
+// (the bisection of Algorithm 3 runs here).
 template <int KIND, int G, int HOT = 0>
-__host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln,
-                                          const double* hot_d = nullptr, const double* hot_c = nullptr) {
-  const Ws w = ws_view(D.ws, D.n);
-  const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
+__host__ __device__ inline bool root_begin(const ProbDesc& D, const Options& opt, const Ws& w, const Prob& P, int k,
+                                           int ln, int& i, RatConsts& c, RatState& s) {
   const uint32_t pf = *prob_flags(w);
   if (ln == 0) w.nr1[k] = NAN;   // the norm from the root pass, set below when there is one
   if (k >= P.n) {   // past the order of a deflated problem
     if (ln == 0) { w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0; }
-    return;
+    return false;
   }
   if (pf & INFO_NOT_SOLVED) {
     if (ln == 0) {
       w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0;
       w.pv1[k] = NAN; w.mu1[k] = NAN; w.kb1[k] = NAN; w.ip1[k] = -1; w.fl1[k] = pf;
     }
-    return;
+    return false;
   }
   if (P.m == 0) {  // n == 1: lambda = corner, x = [-1]
     if (ln == 0) {
       w.cnt[6 * k + 0] = 0; w.cnt[6 * k + 1] = 0; w.cnt[6 * k + 2] = 0;
       w.pv1[k] = 0.0; w.mu1[k] = dd_to_d(P.corner); w.kb1[k] = 0.0; w.ip1[k] = -1; w.fl1[k] = 0;
     }
-    return;
+    return false;
   }
-  int i, side;
+  int side;
   select_shift<KIND, G>(P, k, ln, i, side);
   // b in double-double (Theorem 6) unless FP64 is asked for, or unless the
   // FP64 pass's K_b (eq. K2) is at most tau_b: Algorithm 5 keeps b from
@@ -462,37 +488,45 @@ __host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt,
   }
   if (dd_b) bp = b_pass_t<KIND, G, false>(P, i, side, ln);
   const int plain_b = (opt.fp64_b || opt.tau_b > 0.0) ? 1 : 0;
-  int iters = 0;
-  double last[3] = {NAN, NAN, NAN};   // the rational pass's last point nu and its sums S2, S3
-  const double nu = (opt.root == ROOT_RATIONAL)
-      ? rational_inverse<KIND, G>(P, i, side, bp.b, bp.lo, bp.hi, side > 0 ? bp.lo : bp.hi, ln, &iters, bp.x0, last)
-      : bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
-  // ||x||^2 of eq. (eigenvecAi) at mu = 1/nu: with v_j = 1/(nu e_j - 1) the
-  // entry x_j = zeta_j/(e_j - mu) is nu zeta_j v_j (j != i) and x_i = -nu zeta_i, so
-  // ||x||^2 = nu^2 (S2 + zeta_i^2) + 1, S2 = sum_{j != i} zeta_j^2 v_j^2 -- the sum
-  // the rational pass forms for psi'.  It was formed at that pass's point;
-  // the step to the final nu is taken to first order, d/dnu (nu^2 S2(nu)) =
-  // 2 nu S2 - 2 nu^2 S3 with S3 = sum zeta_j^2 e_j v_j^3, also formed there.
-  // DPR1's vector is not the arrowhead's; its norm follows from the arrowhead's (dpr1_inorm).
-  double nr1 = NAN;
-  if (last[0] == last[0]) {
-    nr1 = norm_from_pass(last, nu, P.ch[i]);
-    if constexpr (KIND == KIND_DPR1) nr1 = dpr1_inorm(P, nr1, 1.0 / nu, P.ds[i]);
-  }
   if (ln == 0) {
-    w.cnt[6 * k + 0] = iters;
     w.cnt[6 * k + 1] = dd_b ? 1 : 0;
     w.cnt[6 * k + 2] = ((k > 0 && k < P.m) ? 1 : 0) + plain_b;
     w.pv1[k] = P.ds[i];
-    w.mu1[k] = 1.0 / nu;
     w.kb1[k] = bp.Kb;
-    w.nr1[k] = nr1;
     w.ip1[k] = i;
     uint32_t fl = dd_b ? INFO_DD_B : 0u;
     // Theorem 6 needs K_b <= O(1/eps); flag when the double-double b cannot hold it
     if (bp.Kb * (double)(D.n + 4) * 4.930380657631324e-32 > 1e-3) fl |= INFO_KB_LARGE;
     w.fl1[k] = fl;
   }
+  if (opt.root == ROOT_RATIONAL) {
+    const double ymax = side > 0 ? bp.lo : bp.hi;
+    c = rat_consts<KIND>(P, i, side, (double)side * ymax);
+    s = rat_init(c, bp.b, bp.lo, bp.hi, ymax, bp.x0);
+    return true;
+  }
+  int iters = 0;
+  const double last[3] = {NAN, NAN, NAN};
+  const double nu = bisect_inverse<KIND, G>(P, i, bp.b, bp.lo, bp.hi, ln, &iters);
+  root_finish<KIND>(P, w, k, i, ln, nu, iters, last);
+  return false;
+}
+
+// First pass for eigenvalue k (Algorithm 5 without the final K_nu test): shift,
+// b, root of the inverse and the norm of the eigenvector from the root's passes.
+template <int KIND, int G, int HOT = 0>
+__host__ __device__ inline void root_body(const ProbDesc& D, const Options& opt, int k, int ln,
+                                          const double* hot_d = nullptr, const double* hot_c = nullptr) {
+  const Ws w = ws_view(D.ws, D.n);
+  const Prob P = make_prob<HOT>(D, w, hot_d, hot_c);
+  int i = 0;
+  RatConsts c;
+  RatState s;
+  if (!root_begin<KIND, G, HOT>(D, opt, w, P, k, ln, i, c, s)) return;
+  double last[3] = {NAN, NAN, NAN};   // the rational pass's last point nu and its sums S2, S3
+  while (!rat_step<KIND, G>(P, i, c, s, ln, last)) {
+  }
+  root_finish<KIND>(P, w, k, i, ln, c.sg * s.x, s.it, last);
 }
 
 // ---------------------------------------------------------------------------

@@ -197,6 +197,22 @@ __host__ __device__ inline double greduce(double v, Op op) {
   return v;
 }
 
+// The same butterfly for a group size gc known only at run time (a power of
+// two up to 64, the same in every lane of the wavefront): for gc == G it gives
+// the bits of greduce<G>.
+template <class Op>
+__host__ __device__ inline double greduce_rt(double v, int gc, Op op) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  if (gc >= 2) v = op(v, dpp<DPP_QUAD_XOR1>(v));
+  if (gc >= 4) v = op(v, dpp<DPP_QUAD_XOR2>(v));
+  if (gc >= 8) v = op(v, dpp<DPP_HALF_MIRROR>(v));
+  if (gc >= 16) v = op(v, dpp<DPP_MIRROR>(v));
+  if (gc >= 32) v = op(v, __shfl_xor(v, 16, 64));
+  if (gc >= 64) v = op(v, __shfl_xor(v, 32, 64));
+#endif
+  return v;
+}
+
 struct OpAdd {
   __host__ __device__ double operator()(double a, double b) const { return a + b; }
 };
@@ -274,24 +290,30 @@ struct v2 {   // two doubles of one term
   double a, b;
 };
 
-template <int G, class L, class F>
-__host__ __device__ inline void for_terms_ld(int ln, int m, int excl, L&& load, F&& f) {
+// The stride g is G, or a group size chosen at run time (for_terms_ld_rt).
+template <class L, class F>
+__host__ __device__ inline void for_terms_ld_rt(int ln, int g, int m, int excl, L&& load, F&& f) {
   using T = decltype(load(0));
   const int cut = (excl >= 0 && excl < m) ? excl : m;
   int j = ln;
   auto run = [&](int end, bool above) {
-    for (; j + (TERM_UNROLL - 1) * G < end; j += TERM_UNROLL * G) {
+    for (; j + (TERM_UNROLL - 1) * g < end; j += TERM_UNROLL * g) {
       T t[TERM_UNROLL];
 #pragma unroll
-      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * G);
+      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * g);
 #pragma unroll
-      for (int u = 0; u < TERM_UNROLL; ++u) f(j + u * G, above, t[u]);
+      for (int u = 0; u < TERM_UNROLL; ++u) f(j + u * g, above, t[u]);
     }
-    for (; j < end; j += G) f(j, above, load(j));
+    for (; j < end; j += g) f(j, above, load(j));
   };
   run(cut, false);
-  if (j == excl) j += G;
+  if (j == excl) j += g;
   run(m, true);
+}
+
+template <int G, class L, class F>
+__host__ __device__ inline void for_terms_ld(int ln, int m, int excl, L&& load, F&& f) {
+  for_terms_ld_rt(ln, G, m, excl, load, f);
 }
 
 // The positive zero of t^2 - beta t - s^2 (s >= 0), in the form that avoids
@@ -544,11 +566,14 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
 // when the offset s is known to be zero.  The third sum is taken times nu: it
 // is then of the size of the second, whereas the plain sum of c_j e_j v_j^3
 // underflows when the poles are as small as 1e-220 and nu as large as 1e220.
-template <int KIND, int G, bool OFF>
-__host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
-                                         double& sum, double& dsum, double& d2sum) {
-  double a = 0.0, b = 0.0, c = 0.0;
-  for_terms_ld<G>(ln, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
+// lane ln's share of the three sums over its group's terms (stride g)
+template <int KIND, bool OFF>
+__host__ __device__ inline void psi_terms(const Prob& P, double pv, double s, int excl, double nu, int ln, int g,
+                                          double& a, double& b, double& c) {
+  a = 0.0;
+  b = 0.0;
+  c = 0.0;
+  for_terms_ld_rt(ln, g, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
     const double e = OFF ? pdiff<KIND>(t.a, pv) - s : pdiff<KIND>(t.a, pv);
     const double q = recip(e * fma(nu, e, -1.0));
     const double v = e * q;                // 1 / (nu e - 1)
@@ -557,9 +582,27 @@ __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int
     b += d1;
     c = fma(d1, (e * nu) * v, c);
   });
+}
+
+template <int KIND, int G, bool OFF>
+__host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
+                                         double& sum, double& dsum, double& d2sum) {
+  double a, b, c;
+  psi_terms<KIND, OFF>(P, pv, s, excl, nu, ln, G, a, b, c);
   sum = gsum<G>(a);
   dsum = gsum<G>(b);
   d2sum = gsum<G>(c);
+}
+
+// the same pass on groups of gc lanes, gc chosen at run time (at most 64)
+template <int KIND, bool OFF>
+__host__ __device__ inline void psi_pass_rt(const Prob& P, double pv, double s, int excl, double nu, int ln, int gc,
+                                            double& sum, double& dsum, double& d2sum) {
+  double a, b, c;
+  psi_terms<KIND, OFF>(P, pv, s, excl, nu, ln, gc, a, b, c);
+  sum = greduce_rt(a, gc, OpAdd());
+  dsum = greduce_rt(b, gc, OpAdd());
+  d2sum = greduce_rt(c, gc, OpAdd());
 }
 
 // The rational step in x-space: the zero of c0 - kappa x + A/(x - p) + B with
@@ -792,14 +835,16 @@ __host__ __device__ inline RatState rat_init(const RatConsts& c, double b, doubl
 }
 
 // One pass at s.x and the next point; true when the iteration has finished
-// (s.x is then the root).  last[] receives the pass's point and sums.
+// (s.x is then the root).  last[] receives the pass's point and sums.  gc:
+// the group's lanes when they are chosen at run time (G == 0).
 template <int KIND, int G>
 __host__ __device__ inline bool rat_step(const Prob& P, int i, const RatConsts& c, RatState& s, int ln,
-                                         double* last) {
+                                         double* last, int gc = G) {
   if (s.x >= s.xhi) s.hi_open = 0;
   const double nu = c.sg * s.x;
   double s1, s2, s3;
-  psi_pass<KIND, G, false>(P, P.ds[i], 0.0, i, nu, ln, s1, s2, s3);
+  if constexpr (G == 0) psi_pass_rt<KIND, false>(P, P.ds[i], 0.0, i, nu, ln, gc, s1, s2, s3);
+  else psi_pass<KIND, G, false>(P, P.ds[i], 0.0, i, nu, ln, s1, s2, s3);
   if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
   const double rnu = 1.0 / nu;
   const double psi = (s1 + rnu) * c.rci;                       // psi(nu)
