@@ -94,12 +94,13 @@ __global__ __launch_bounds__(BLOCK) void k_b_prep(BatchArgs B) {
 // each step, once the unfinished eigenvalues fit in groups twice as wide,
 // they are regrouped: the g-th unfinished one moves (its state copied lane to
 // lane) to lanes [g gc, (g + 1) gc) with gc the widest power of two that fits,
-// so its further passes run on more lanes.  All groups solve the item's
-// problem, so they keep reading the same poles.  The regrouping depends only
+// so its further passes run on more lanes (each width a compiled loop of its
+// own).  All groups solve the item's problem, so they keep reading the same
+// poles.  The regrouping depends only
 // on the item's own eigenvalues: a problem gives the same bits alone or in any
 // batch.  HOT: what the wavefront's LDS slice holds (make_prob).
 template <int KIND, int G, int HOT>
-__device__ inline void root_item(const ProbDesc& D, const Options& opt, int k, int lane, bool valid,
+__device__ __forceinline__ void root_item(const ProbDesc& D, const Options& opt, int k, int lane, bool valid,
                                  const double* lds) {
   const int ln = lane & (G - 1);
   const Ws w = ws_view(D.ws, D.n);
@@ -119,7 +120,7 @@ __device__ inline void root_item(const ProbDesc& D, const Options& opt, int k, i
   } else {
     int gc = G, lc = ln;
     for (;;) {
-      if (mine && rat_step<KIND, 0>(P, i, c, s, lc, last, gc)) {
+      if (mine && rat_step<KIND, G, true>(P, i, c, s, lc, last, gc)) {
         root_finish<KIND>(P, w, k, i, lc, c.sg * s.x, s.it, last);
         mine = false;
       }
@@ -158,7 +159,7 @@ __device__ inline void root_item(const ProbDesc& D, const Options& opt, int k, i
 // hot: what the wavefront's LDS slice holds -- 1 the sorted poles and then
 // the shaft weights, 2 the poles alone, 0 nothing (G <= 16 only).
 template <int KIND>
-__device__ inline void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int lane, bool valid, int hot,
+__device__ __forceinline__ void root_kind(const ProbDesc& D, const Options& opt, int G, int k, int lane, bool valid, int hot,
                                  const double* lds) {
   if (hot == 1) {
     switch (G) {

@@ -18,6 +18,8 @@
 // an offset s; the shifted pole differences are e_j = pdiff(d_j, pv) - s.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -197,22 +199,6 @@ __host__ __device__ inline double greduce(double v, Op op) {
   return v;
 }
 
-// The same butterfly for a group size gc known only at run time (a power of
-// two up to 64, the same in every lane of the wavefront): for gc == G it gives
-// the bits of greduce<G>.
-template <class Op>
-__host__ __device__ inline double greduce_rt(double v, int gc, Op op) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  if (gc >= 2) v = op(v, dpp<DPP_QUAD_XOR1>(v));
-  if (gc >= 4) v = op(v, dpp<DPP_QUAD_XOR2>(v));
-  if (gc >= 8) v = op(v, dpp<DPP_HALF_MIRROR>(v));
-  if (gc >= 16) v = op(v, dpp<DPP_MIRROR>(v));
-  if (gc >= 32) v = op(v, __shfl_xor(v, 16, 64));
-  if (gc >= 64) v = op(v, __shfl_xor(v, 32, 64));
-#endif
-  return v;
-}
-
 struct OpAdd {
   __host__ __device__ double operator()(double a, double b) const { return a + b; }
 };
@@ -290,30 +276,24 @@ struct v2 {   // two doubles of one term
   double a, b;
 };
 
-// The stride g is G, or a group size chosen at run time (for_terms_ld_rt).
-template <class L, class F>
-__host__ __device__ inline void for_terms_ld_rt(int ln, int g, int m, int excl, L&& load, F&& f) {
+template <int G, class L, class F>
+__host__ __device__ inline void for_terms_ld(int ln, int m, int excl, L&& load, F&& f) {
   using T = decltype(load(0));
   const int cut = (excl >= 0 && excl < m) ? excl : m;
   int j = ln;
   auto run = [&](int end, bool above) {
-    for (; j + (TERM_UNROLL - 1) * g < end; j += TERM_UNROLL * g) {
+    for (; j + (TERM_UNROLL - 1) * G < end; j += TERM_UNROLL * G) {
       T t[TERM_UNROLL];
 #pragma unroll
-      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * g);
+      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * G);
 #pragma unroll
-      for (int u = 0; u < TERM_UNROLL; ++u) f(j + u * g, above, t[u]);
+      for (int u = 0; u < TERM_UNROLL; ++u) f(j + u * G, above, t[u]);
     }
-    for (; j < end; j += g) f(j, above, load(j));
+    for (; j < end; j += G) f(j, above, load(j));
   };
   run(cut, false);
-  if (j == excl) j += g;
+  if (j == excl) j += G;
   run(m, true);
-}
-
-template <int G, class L, class F>
-__host__ __device__ inline void for_terms_ld(int ln, int m, int excl, L&& load, F&& f) {
-  for_terms_ld_rt(ln, G, m, excl, load, f);
 }
 
 // The positive zero of t^2 - beta t - s^2 (s >= 0), in the form that avoids
@@ -369,7 +349,9 @@ struct BPass {
   double x0;   // a start for the root in x = side*nu from a two-pole model (NaN: none)
 };
 
-template <int KIND, int G, bool FP64_B>
+// RUNS: split the term loop where FastTwoSum applies (a shorter loop body, a
+// larger kernel); the results are the same bits either way.
+template <int KIND, int G, bool FP64_B, bool RUNS = true>
 __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln) {
   const int m = P.m;
   const double di = P.ds[i];
@@ -386,8 +368,14 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
   struct Term {
     double d, ch, cl;
   };
-  for_terms_ld<G>(ln, m, i, [&](int j) { return Term{P.ds[j], P.ch[j], FP64_B ? 0.0 : P.cl[j]}; },
-                  [&](int, bool above, const Term& t) {
+  auto load = [&](int j) { return Term{P.ds[j], P.ch[j], FP64_B ? 0.0 : P.cl[j]}; };
+  // ORD: how the exact difference d_j - d_i = e.hi + e.lo is formed -- 0 by
+  // TwoSum (and, for SVD, the product of two), 1 by FastTwoSum(d_j, -d_i), valid
+  // where |d_j| >= |d_i|, 2 by FastTwoSum(-d_i, d_j), valid where |d_j| <= |d_i|:
+  // the same exact pair in 3 operations instead of 6
+  auto term = [&](auto above_c, auto ord_c, const Term& t) {
+    constexpr bool above = decltype(above_c)::value;
+    constexpr int ord = decltype(ord_c)::value;
     const double ej = pdiff<KIND>(t.d, di);
     // delta_j, the diagonal of A_i^{-1}, within 11 ulps: the two-digit
     // quotient's remainder corrects its first digit, so c/e stays good to
@@ -397,7 +385,11 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
       const double q = t.ch * rj;
       if (above) f2 += q; else f1 += q;
     } else {
-      const dd q = dd_div2_raw(dd{t.ch, t.cl}, pdiff_dd<KIND>(t.d, di), rj);
+      dd e;
+      if constexpr (ord == 1) e = dd{ej, (-di) - (ej - t.d)};
+      else if constexpr (ord == 2) e = dd{ej, t.d - (ej + di)};
+      else e = pdiff_dd<KIND>(t.d, di);
+      const dd q = dd_div2_raw(dd{t.ch, t.cl}, e, rj);
       if (above) dd_acc(p2, q); else dd_acc(p1, q);
     }
     const double rs = rj * gs;
@@ -406,7 +398,51 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
 #if AHD_START_MODEL
     r3 = fma(t.ch, rs2 * rs, r3);
 #endif
-  });
+  };
+  // lane ln's poles j = ln, ln + G, ... of [j, end), loads of TERM_UNROLL terms ahead
+  int j = ln;
+  auto run = [&](int end, auto above_c, auto ord_c) {
+    for (; j + (TERM_UNROLL - 1) * G < end; j += TERM_UNROLL * G) {
+      Term t[TERM_UNROLL];
+#pragma unroll
+      for (int u = 0; u < TERM_UNROLL; ++u) t[u] = load(j + u * G);
+#pragma unroll
+      for (int u = 0; u < TERM_UNROLL; ++u) term(above_c, ord_c, t[u]);
+    }
+    for (; j < end; j += G) term(above_c, ord_c, load(j));
+  };
+  using below_t = std::integral_constant<bool, false>;
+  using above_t = std::integral_constant<bool, true>;
+  using two_sum_t = std::integral_constant<int, 0>;
+  using fast_t = std::integral_constant<int, 1>;
+  using fast_swap_t = std::integral_constant<int, 2>;
+  if constexpr (FP64_B || KIND == KIND_SVD || !RUNS) {
+    run(i, below_t(), two_sum_t());
+    if (j == i) j += G;
+    run(m, above_t(), two_sum_t());
+  } else if (di >= 0.0) {
+    // j < i: d_j > d_i >= 0; j > i: |d_j| < d_i until d_j <= -d_i (from j2 on)
+    int lo = i + 1, hi = m;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.ds[mid] <= -di) hi = mid; else lo = mid + 1;
+    }
+    run(i, below_t(), fast_t());
+    if (j == i) j += G;
+    run(lo, above_t(), fast_swap_t());
+    run(m, above_t(), fast_t());
+  } else {
+    // j > i: d_j < d_i < 0; j < i: d_j >= -d_i up to j1, then |d_j| < -d_i
+    int lo = 0, hi = i;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (P.ds[mid] < -di) hi = mid; else lo = mid + 1;
+    }
+    run(lo, below_t(), fast_t());
+    run(i, below_t(), fast_swap_t());
+    if (j == i) j += G;
+    run(m, above_t(), fast_t());
+  }
   r2 = gsum<G>(r2);
 #if AHD_START_MODEL
   r3 = gsum<G>(r3);
@@ -505,10 +541,11 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
 }
 
 // the FP64-only variant is the negative control of Algorithm 2; the choice is
-// made once per call so that the term loop carries no branch
+// made once per call so that the term loop carries no branch.  For the
+// remedies, rare enough that code size matters more than the loop body.
 template <int KIND, int G>
 __host__ __device__ inline BPass b_pass(const Prob& P, int i, int side, int ln, int fp64_b) {
-  return fp64_b ? b_pass_t<KIND, G, true>(P, i, side, ln) : b_pass_t<KIND, G, false>(P, i, side, ln);
+  return fp64_b ? b_pass_t<KIND, G, true>(P, i, side, ln) : b_pass_t<KIND, G, false, false>(P, i, side, ln);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,14 +603,11 @@ __host__ __device__ inline double bisect_inverse(const Prob& P, int i, double b,
 // when the offset s is known to be zero.  The third sum is taken times nu: it
 // is then of the size of the second, whereas the plain sum of c_j e_j v_j^3
 // underflows when the poles are as small as 1e-220 and nu as large as 1e220.
-// lane ln's share of the three sums over its group's terms (stride g)
-template <int KIND, bool OFF>
-__host__ __device__ inline void psi_terms(const Prob& P, double pv, double s, int excl, double nu, int ln, int g,
-                                          double& a, double& b, double& c) {
-  a = 0.0;
-  b = 0.0;
-  c = 0.0;
-  for_terms_ld_rt(ln, g, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
+template <int KIND, int G, bool OFF>
+__host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
+                                         double& sum, double& dsum, double& d2sum) {
+  double a = 0.0, b = 0.0, c = 0.0;
+  for_terms_ld<G>(ln, P.m, excl, [&](int j) { return v2{P.ds[j], P.ch[j]}; }, [&](int, bool, const v2& t) {
     const double e = OFF ? pdiff<KIND>(t.a, pv) - s : pdiff<KIND>(t.a, pv);
     const double q = recip(e * fma(nu, e, -1.0));
     const double v = e * q;                // 1 / (nu e - 1)
@@ -582,27 +616,24 @@ __host__ __device__ inline void psi_terms(const Prob& P, double pv, double s, in
     b += d1;
     c = fma(d1, (e * nu) * v, c);
   });
-}
-
-template <int KIND, int G, bool OFF>
-__host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int excl, double nu, int ln,
-                                         double& sum, double& dsum, double& d2sum) {
-  double a, b, c;
-  psi_terms<KIND, OFF>(P, pv, s, excl, nu, ln, G, a, b, c);
   sum = gsum<G>(a);
   dsum = gsum<G>(b);
   d2sum = gsum<G>(c);
 }
 
-// the same pass on groups of gc lanes, gc chosen at run time (at most 64)
-template <int KIND, bool OFF>
-__host__ __device__ inline void psi_pass_rt(const Prob& P, double pv, double s, int excl, double nu, int ln, int gc,
-                                            double& sum, double& dsum, double& d2sum) {
-  double a, b, c;
-  psi_terms<KIND, OFF>(P, pv, s, excl, nu, ln, gc, a, b, c);
-  sum = greduce_rt(a, gc, OpAdd());
-  dsum = greduce_rt(b, gc, OpAdd());
-  d2sum = greduce_rt(c, gc, OpAdd());
+// The same pass on groups of gc lanes, gc one of G, 2G, ..., 64 chosen at run
+// time (the same in every lane of the wavefront): each width is its own
+// compiled loop, so the stride and the butterfly stay compile-time.
+template <int KIND, bool OFF, int G>
+__host__ __device__ inline void psi_pass_wide(const Prob& P, double pv, double s, int excl, double nu, int ln, int gc,
+                                              double& sum, double& dsum, double& d2sum) {
+  if constexpr (G < 64) {
+    if (gc > G) {
+      psi_pass_wide<KIND, OFF, 2 * G>(P, pv, s, excl, nu, ln, gc, sum, dsum, d2sum);
+      return;
+    }
+  }
+  psi_pass<KIND, G, OFF>(P, pv, s, excl, nu, ln, sum, dsum, d2sum);
 }
 
 // The rational step in x-space: the zero of c0 - kappa x + A/(x - p) + B with
@@ -835,15 +866,15 @@ __host__ __device__ inline RatState rat_init(const RatConsts& c, double b, doubl
 }
 
 // One pass at s.x and the next point; true when the iteration has finished
-// (s.x is then the root).  last[] receives the pass's point and sums.  gc:
-// the group's lanes when they are chosen at run time (G == 0).
-template <int KIND, int G>
+// (s.x is then the root).  last[] receives the pass's point and sums.  WIDE:
+// the group has gc lanes, gc one of G, 2G, ..., 64 (psi_pass_wide).
+template <int KIND, int G, bool WIDE = false>
 __host__ __device__ inline bool rat_step(const Prob& P, int i, const RatConsts& c, RatState& s, int ln,
                                          double* last, int gc = G) {
   if (s.x >= s.xhi) s.hi_open = 0;
   const double nu = c.sg * s.x;
   double s1, s2, s3;
-  if constexpr (G == 0) psi_pass_rt<KIND, false>(P, P.ds[i], 0.0, i, nu, ln, gc, s1, s2, s3);
+  if constexpr (WIDE) psi_pass_wide<KIND, false, G>(P, P.ds[i], 0.0, i, nu, ln, gc, s1, s2, s3);
   else psi_pass<KIND, G, false>(P, P.ds[i], 0.0, i, nu, ln, s1, s2, s3);
   if (last) { last[0] = nu; last[1] = s2; last[2] = s3; }   // the sums at the latest point
   const double rnu = 1.0 / nu;
