@@ -95,7 +95,7 @@ __host__ __device__ inline double dd_to_d(dd a) { return a.hi + a.lo; }
 // quotient: the remainder carries its error exactly, so the pair is good to a
 // few units of 2^-104 -- enough where quotients of one sign are summed, which
 // is the only use.  dd_div2_raw leaves the pair unnormalised (|q.lo| is a few
-// ulps of q.hi), which is all dd_acc needs; dd_div2 renormalises it.
+// ulps of q.hi); dd_div2 renormalises it.
 __host__ __device__ inline dd dd_div2_raw(dd c, dd e, double r) {
   const double q1 = c.hi * r;
   const dd p = two_prod(q1, e.hi);
@@ -108,12 +108,19 @@ __host__ __device__ inline dd dd_div2(dd c, dd e, double r) {
   return fast_two_sum(q.hi, q.lo);
 }
 
-// s += q for a running sum of terms of one sign: the error of every leading
-// addition is kept exactly (TwoSum) and gathered in s.lo.
-__host__ __device__ inline void dd_acc(dd& s, dd q) {
-  const dd t = two_sum(s.hi, q.hi);
+// s += c / e for a running sum of quotients of one sign, given r ~ 1/e.hi (as
+// for dd_div2_raw): the first digit q1 = c.hi r enters s.hi through TwoSum, and
+// the second digit, the remainder c - q1 e times r, is folded by one FMA into
+// the addition error that s.lo gathers.  The remainder's last term q1 e.lo is
+// an FMA too: two operations fewer than forming the pair (dd_div2_raw) and
+// adding it, for the same two digits.
+__host__ __device__ inline void dd_acc_div2(dd& s, dd c, dd e, double r) {
+  const double q1 = c.hi * r;
+  const dd p = two_prod(q1, e.hi);
+  const double rem = fma(-q1, e.lo, ((c.hi - p.hi) - p.lo) + c.lo);
+  const dd t = two_sum(s.hi, q1);
   s.hi = t.hi;
-  s.lo += t.lo + q.lo;
+  s.lo += fma(rem, r, t.lo);
 }
 
 __host__ __device__ inline dd dd_norm(dd s) { return fast_two_sum(s.hi, s.lo); }

@@ -389,14 +389,16 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
       if constexpr (ord == 1) e = dd{ej, (-di) - (ej - t.d)};
       else if constexpr (ord == 2) e = dd{ej, t.d - (ej + di)};
       else e = pdiff_dd<KIND>(t.d, di);
-      const dd q = dd_div2_raw(dd{t.ch, t.cl}, e, rj);
-      if (above) dd_acc(p2, q); else dd_acc(p1, q);
+      if (above) dd_acc_div2(p2, dd{t.ch, t.cl}, e, rj); else dd_acc_div2(p1, dd{t.ch, t.cl}, e, rj);
     }
+    // zeta_j^2 (gs / e_j)^2 = w gs and zeta_j^2 (gs / e_j)^3 = w (gs / e_j) gs with
+    // w = (zeta_j^2 / e_j)(gs / e_j) <= |zeta_j^2 / e_j|: the factor gs is applied
+    // after the sums
     const double rs = rj * gs;
-    const double rs2 = rs * rs;
-    r2 = fma(t.ch, rs2, r2);
+    const double w = (t.ch * rj) * rs;
+    r2 += w;
 #if AHD_START_MODEL
-    r3 = fma(t.ch, rs2 * rs, r3);
+    r3 = fma(w, rs, r3);
 #endif
   };
   // lane ln's poles j = ln, ln + G, ... of [j, end), loads of TERM_UNROLL terms ahead
@@ -443,9 +445,9 @@ __host__ __device__ inline BPass b_pass_t(const Prob& P, int i, int side, int ln
     if (j == i) j += G;
     run(m, above_t(), fast_t());
   }
-  r2 = gsum<G>(r2);
+  r2 = gsum<G>(r2) * gs;
 #if AHD_START_MODEL
-  r3 = gsum<G>(r3);
+  r3 = gsum<G>(r3) * gs;
 #endif
   const dd a = dd_sub(P.corner, pval_dd<KIND>(di));  // a = alpha - d_i
   const double ci = P.ch[i];
