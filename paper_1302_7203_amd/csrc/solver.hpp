@@ -616,11 +616,14 @@ __host__ __device__ inline void psi_pass(const Prob& P, double pv, double s, int
     a = fma(t.b, q, a);
     const double d1 = (t.b * v) * v;
     b += d1;
-    c = fma(d1, (e * nu) * v, c);
+    c = fma(d1, v, c);
   });
   sum = gsum<G>(a);
   dsum = gsum<G>(b);
-  d2sum = gsum<G>(c);
+  // the third sum's terms d1 (nu e) v are d1 (1 + v), since nu e v = 1 + v: it is
+  // the second sum plus sum d1 v.  Where the shift is the nearest pole, |nu e| >= 2
+  // near the root for every pole, so 1 + v lies in [2/3, 2] and nothing cancels
+  d2sum = dsum + gsum<G>(c);
 }
 
 // The same pass on groups of gc lanes, gc one of G, 2G, ..., 64 chosen at run
