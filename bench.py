@@ -293,9 +293,12 @@ def serving_leg(args, dev):
     sat = serve.latency_stats(srv.run([(0.0, p) for p in probs]))
     l0 = srv.launches
     rate = args.serve_load * sat["solves_per_s"]
-    offered = srv.run([(t / rate, p) for t, p in arr])
-    st = serve.latency_stats(offered)
-    launches = srv.launches - l0
+    # the stream lasts about 0.1 s, so its p99 (its 20 slowest requests) turns on a burst or
+    # two: it is offered several times and the run with the median p99 is reported, every
+    # run's p50 and p99 beside it
+    runs = [serve.latency_stats(srv.run([(t / rate, p) for t, p in arr])) for _ in range(max(1, args.serve_repeats))]
+    st = sorted(runs, key=lambda r: r["p99_ms"])[len(runs) // 2]
+    launches = (srv.launches - l0) / len(runs)
     peak = srv.peak_used
     if check_rids:
         srv.on_done = grab
@@ -319,6 +322,8 @@ def serving_leg(args, dev):
            "offered_load": args.serve_load, "offered_solves_per_s": rate,
            "achieved_solves_per_s": st["solves_per_s"], "achieved_eigenpairs_per_s": st["eigenpairs_per_s"],
            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+           "repeats": len(runs), "p50_ms_runs": [round(r["p50_ms"], 3) for r in runs],
+           "p99_ms_runs": [round(r["p99_ms"], 3) for r in runs],
            "latency_parts_ms": {k: round(v, 4) for k, v in st.items()
                                 if k.startswith(("admit_wait", "launch_wait", "device"))},
            "slowest_1pct_mean_n": st["n_mean_slowest_1pct"], "streams": 4, "aging_ms": 20.0, "split_n": 2048,
@@ -546,6 +551,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7, help="offered load as a fraction of saturated capacity")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-max-batch", type=int, default=4096, help="most requests one launch may take")
+    ap.add_argument("--serve-repeats", type=int, default=3,
+                    help="offered-load runs of the same stream; the one with the median p99 is reported")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the Hermitian / reducible / rho < 0 legs")
     ap.add_argument("--no-peaks", action="store_true", help="skip the calibration kernels")
