@@ -186,6 +186,33 @@ def test_full_size_batch_sampled(env, oracle_lib):
     torch.cuda.empty_cache()
 
 
+def test_root_staging_boundaries_sampled(env, oracle_lib):
+    """Orders at the edges of the root stage's LDS staging (poles and weights while 2 ns <= 1280,
+    the poles alone while ns <= 1280, nothing above; ns = n - 1, DPR1 n) and the regrouped
+    root stage at 8 and 16 lanes per eigenvalue, against the oracle on 24 eigenpairs each."""
+    torch, batch, dev = env
+    rng = np.random.default_rng(63)
+    probs = ([W.uniform_arrow(n, rng) for n in (641, 642, 1281, 1282, 3100)]
+             + [W.dpr1(n, rng) for n in (640, 641, 1280, 1281)] + [W.svd_arrow(1281, rng)])
+    b = batch.Batch(probs, device=dev)
+    b.run()
+    torch.cuda.synchronize()
+    for p, pr in enumerate(probs):
+        lam, V, U, info = b.result(p)
+        ks = np.unique(np.linspace(0, pr.n - 1, 24).astype(np.int64))
+        kt = torch.from_numpy(ks).to(dev)
+        if pr.kind == W.KIND_SVD:
+            r = oracle.arrow_svd(pr.d, pr.z, pr.scalar, ks=ks)
+            rl, rV = r.sigma, r.V
+            assert_close(U[:, kt].cpu().numpy(), r.U, f"n={pr.n} kind {pr.kind} left vectors")
+        else:
+            r = (oracle.arrow_eig if pr.kind == W.KIND_ARROW else oracle.dpr1_eig)(pr.d, pr.z, pr.scalar, ks=ks)
+            rl, rV = r.lam, r.vec
+        assert_close(lam[kt].cpu().numpy(), rl, f"n={pr.n} kind {pr.kind} values")
+        assert_close(V[:, kt].cpu().numpy(), rV, f"n={pr.n} kind {pr.kind} vectors")
+    b.close()
+
+
 def test_options_fixed_at_creation(env):
     """A plan keeps the handle's options from its creation: changing the root
     finder (ARROW_OPT_ROOT) or the FP64-b bound (ARROW_OPT_TAU_B) afterwards
