@@ -4,8 +4,10 @@
 //   k_b_prep    one block per problem: sort (Sec. 1 ordering) and prologue
 //   k_b_root    persistent: every wavefront takes (problem, eigenvalue-group)
 //               items from an atomic queue and runs the first pass (shift,
-//               b, root of the inverse) on them; problems are queued by
-//               decreasing order n so the long items start first
+//               b, root of the inverse) on them, reading the problem's poles
+//               (and weights) from its own LDS slice where they fit, and
+//               regrouping unfinished roots onto wider lane groups; problems
+//               are queued by decreasing order n so the long items start first
 //   k_b_check   a second queue of the same kind for the K_nu test and the
 //               norms; the eigenvalues that need a remedy of Remark 2 or the
 //               DPR1 re-measure are gathered per wavefront and re-solved on
